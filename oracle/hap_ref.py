@@ -1,0 +1,186 @@
+"""Plain FP64 HAP (test infrastructure; see the package header).
+
+Follows Algorithm 1 of the paper (Section 2): for every iteration, for every
+level l = 1..L in order, update the responsibilities (Eq. 2.1) and damp them,
+update the availabilities (Eq. 2.2, 2.3) and damp them, then update the
+inter-level messages tau, phi and the cluster preference c (Eq. 2.4-2.6).
+After the last iteration the exemplar of every point at every level is the
+argmax of alpha + rho (Eq. 2.8).
+
+Readings of points the paper leaves open (each is listed in the design notes):
+  * Levels run one after another inside an iteration (Algorithm 1), not all at
+    once from the previous state.
+  * Level l emits tau^{l+1} (up) and phi^{l-1} (down) after its own rho and
+    alpha updates, and updates c^l last; tau^{l+1} therefore uses c^l from the
+    previous iteration.  At iteration 1 that c is 0 (the initial value).
+  * Eq. 2.1 carries the tau clip only for l > 1 (tau^1 is +inf from the
+    initialisation); Eq. 2.2-2.3 carry c and phi only for l < L, so the top level
+    uses the plain AP availability and L = 1 is exactly plain AP.
+  * Damping: new = lambda*old + (1-lambda)*computed, for rho and alpha only;
+    alpha is computed from the already damped rho.
+  * max_{k != j} runs over every column k != j including k = i (whose
+    similarity is the preference); a maximum attained twice gives M2 = M1.
+  * argmax ties go to the lowest index.
+  * The similarity is the same at every level (the optional Eq. 2.7 update is
+    off); the diagonal s^l_jj holds the level-l preference p^l_j.
+  * Stopping with K > 0: after each iteration t the labels of every level are
+    compared with those of iteration t-1; the stable count goes up by one when
+    none changed (t >= 2) and resets to 0 otherwise; the run stops at the end of
+    the iteration where the count reaches K.
+
+The column sum over k not in {i, j} of Eq. 2.2 is evaluated as the full column
+sum minus the (i, j) term; the pure-Python evaluator in ``literal`` sums the
+defining terms directly and pins this identity.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class HapState:
+    """Everything that determines the continuation of a run (Algorithm 1 state)."""
+    rho: np.ndarray      # (L, N, N) responsibilities
+    alpha: np.ndarray    # (L, N, N) availabilities
+    c: np.ndarray        # (L, N) cluster preference, Eq. 2.6
+    phi: np.ndarray      # (L, N) downward message, Eq. 2.5 (phi^l is sent by level l+1)
+    tau: np.ndarray      # (L, N) upward message, Eq. 2.4 (tau^1 = +inf)
+    t: int = 0           # completed iterations
+    stable: int = 0      # consecutive iterations with unchanged labels
+    labels: np.ndarray | None = None   # (L, N) labels of iteration t
+
+    def copy(self) -> "HapState":
+        return HapState(self.rho.copy(), self.alpha.copy(), self.c.copy(), self.phi.copy(),
+                        self.tau.copy(), self.t, self.stable,
+                        None if self.labels is None else self.labels.copy())
+
+
+@dataclass
+class HapResult:
+    labels: np.ndarray           # (L, N) int64 exemplar index of every point at every level
+    iters: int                   # iterations performed (the stop iteration when converged)
+    converged: bool              # stable count reached K
+    state: HapState
+    Q: np.ndarray                # (L, N) last column sums rho_jj + sum_{k!=j} max(0, rho_kj)
+    history: list = field(default_factory=list)
+
+
+def level_similarity(S: np.ndarray, pref_l: np.ndarray) -> np.ndarray:
+    """s^l: the off-diagonal of S with the level-l preferences on the diagonal."""
+    s = np.array(S, dtype=np.float64, copy=True)
+    np.fill_diagonal(s, pref_l)
+    return s
+
+
+def init_state(N: int, L: int, alpha0: np.ndarray | None = None) -> HapState:
+    """Algorithm 1 initialisation: alpha = rho = 0, tau = +inf, phi = c = 0."""
+    alpha = np.zeros((L, N, N)) if alpha0 is None else np.array(alpha0, dtype=np.float64, copy=True)
+    return HapState(rho=np.zeros((L, N, N)), alpha=alpha, c=np.zeros((L, N)),
+                    phi=np.zeros((L, N)), tau=np.full((L, N), np.inf))
+
+
+def responsibility(s: np.ndarray, alpha: np.ndarray, tau: np.ndarray | None) -> np.ndarray:
+    """Undamped Eq. 2.1 for one level: s_ij + min(tau_i, -max_{k!=j}(alpha_ik + s_ik)).
+
+    tau=None is the l = 1 case (tau = +inf), giving s_ij - max_{k!=j}(...).
+    """
+    N = s.shape[0]
+    rows = np.arange(N)
+    v = alpha + s
+    k1 = np.argmax(v, axis=1)                 # first maximum (lowest index)
+    M1 = v[rows, k1]
+    v[rows, k1] = -np.inf
+    M2 = np.max(v, axis=1)                    # maximum over k != k1
+    m = np.repeat(M1[:, None], N, axis=1)     # max_{k != j}: M1 unless j is the argmax
+    m[rows, k1] = M2
+    if tau is None:
+        return s - m
+    return s + np.minimum(tau[:, None], -m)
+
+
+def column_sums(rho: np.ndarray) -> np.ndarray:
+    """Q_j = rho_jj + sum_{k != j} max(0, rho_kj) (the common part of Eq. 2.2-2.4)."""
+    pos = np.maximum(rho, 0.0)
+    idx = np.arange(rho.shape[0])
+    pos[idx, idx] = rho[idx, idx]
+    return pos.sum(axis=0)
+
+
+def availability(rho: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """Undamped Eq. 2.2 (i != j) and Eq. 2.3 (i == j) given B_j = [c_j + phi_j +] Q_j."""
+    a = np.minimum(0.0, B[None, :] - np.maximum(rho, 0.0))
+    idx = np.arange(rho.shape[0])
+    a[idx, idx] = B - rho[idx, idx]
+    return a
+
+
+def labels_of(state: HapState) -> np.ndarray:
+    """Eq. 2.8 at every level: e^l_i = lowest argmax_j (alpha^l_ij + rho^l_ij)."""
+    return np.argmax(state.alpha + state.rho, axis=2)
+
+
+def hap(S, pref, levels: int, damping: float, max_iters: int, stable_iters: int = 0,
+        alpha0=None, state: HapState | None = None, record=None, c_zero: bool = False) -> HapResult:
+    """Run HAP (Algorithm 1) in FP64.
+
+    S      (N, N) similarity; its diagonal is ignored.
+    pref   preferences: scalar, (N,) shared by all levels, or (L, N).
+    alpha0 optional (L, N, N) initial availabilities (warm start); everything else starts
+           at the Algorithm 1 initial values.
+    state  optional state to continue from (checkpoint / resume).
+    record optional callable(t, l, state) called after every level update.
+    c_zero diagnosis switch: keep c = 0 (a constant cluster preference) instead of Eq. 2.6.
+    """
+    S = np.asarray(S, dtype=np.float64)
+    N = S.shape[0]
+    L = int(levels)
+    lam = float(damping)
+    p = np.asarray(pref, dtype=np.float64)
+    if p.ndim == 0:
+        p = np.full((L, N), float(p))
+    elif p.ndim == 1:
+        p = np.repeat(p[None, :], L, axis=0)
+    s = [level_similarity(S, p[l]) for l in range(L)]
+
+    st = init_state(N, L, alpha0) if state is None else state.copy()
+    Q = np.zeros((L, N))
+    converged = False
+    for _ in range(max_iters):
+        st.t += 1
+        for l in range(L):
+            # Eq. 2.1, then damp
+            rhat = responsibility(s[l], st.alpha[l], None if l == 0 else st.tau[l])
+            st.rho[l] = lam * st.rho[l] + (1.0 - lam) * rhat
+            # Eq. 2.2 / 2.3 with the damped rho, then damp
+            Q[l] = column_sums(st.rho[l])
+            B = (st.c[l] + st.phi[l]) + Q[l] if l < L - 1 else Q[l].copy()
+            st.alpha[l] = lam * st.alpha[l] + (1.0 - lam) * availability(st.rho[l], B)
+            # Eq. 2.4 (up, uses c^l before its update), Eq. 2.5 (down), Eq. 2.6
+            if l < L - 1:
+                st.tau[l + 1] = st.c[l] + Q[l]
+            if l > 0:
+                st.phi[l - 1] = np.max(st.alpha[l] + s[l], axis=1)
+            if l < L - 1 and not c_zero:
+                st.c[l] = np.max(st.alpha[l] + st.rho[l], axis=1)
+            if record is not None:
+                record(st.t, l, st)
+        if stable_iters > 0:
+            e = labels_of(st)
+            if st.labels is not None and st.t >= 2 and np.array_equal(e, st.labels):
+                st.stable += 1
+            else:
+                st.stable = 0
+            st.labels = e
+            if st.stable >= stable_iters:
+                converged = True
+                break
+    if st.labels is None or stable_iters == 0:
+        st.labels = labels_of(st)
+    return HapResult(labels=st.labels.copy(), iters=st.t, converged=converged, state=st, Q=Q)
+
+
+def exemplar_set(labels_l: np.ndarray) -> np.ndarray:
+    """Distinct exemplar indices at one level (sorted)."""
+    return np.unique(labels_l)

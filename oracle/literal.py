@@ -1,0 +1,111 @@
+"""Pure-Python HAP evaluated from the defining sums (test infrastructure).
+
+Every message is computed straight from its equation in Section 2, with explicit
+loops and no algebraic shortcut:
+  Eq. 2.1  rho_ij = s_ij + min(tau_i, -max_{k != j}(alpha_ik + s_ik))      (l > 1)
+           rho_ij = s_ij - max_{k != j}(alpha_ik + s_ik)                     (l = 1)
+  Eq. 2.2  alpha_ij = min(0, c_j + phi_j + rho_jj + sum_{k not in {i,j}} max(0, rho_kj))   (i != j)
+  Eq. 2.3  alpha_jj = c_j + phi_j + sum_{k != j} max(0, rho_kj)
+           (c and phi are dropped at the top level l = L)
+  Eq. 2.4  tau^{l+1}_j = c^l_j + rho^l_jj + sum_{k != j} max(0, rho^l_kj)
+  Eq. 2.5  phi^{l-1}_i = max_k(alpha^l_ik + s^l_ik)
+  Eq. 2.6  c^l_i = max_j(alpha^l_ij + rho^l_ij)
+  Eq. 2.8  e^l_i = argmax_j(alpha^l_ij + rho^l_ij), lowest index on ties
+The schedule and readings are the same as in ``hap_ref``.  The cost is O(L N^3)
+per iteration, so this is for N <= 8 only.
+
+The number type is a parameter.  With ``fractions.Fraction`` inputs (integer
+similarities, a rational damping such as 1/2 or 9/10) every operation (+, *,
+max, min) is exact, so the result is the exact rational trajectory; +inf is
+represented by None.
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+
+
+def _min_tau(tau, x):
+    return x if tau is None else (tau if tau < x else x)
+
+
+def hap_literal(S, pref, levels, damping, iters, num=Fraction):
+    """S: N x N nested lists/array (diagonal ignored); pref: L x N; damping: number.
+
+    Returns (labels, rho, alpha, c, phi, tau) as nested lists of `num`.
+    """
+    N = len(S)
+    L = int(levels)
+    lam = num(damping) if not isinstance(damping, num) else damping
+    one = num(1)
+    zero = num(0)
+    s = [[[num(pref[l][j]) if i == j else num(S[i][j]) for j in range(N)] for i in range(N)]
+         for l in range(L)]
+    rho = [[[zero] * N for _ in range(N)] for _ in range(L)]
+    alpha = [[[zero] * N for _ in range(N)] for _ in range(L)]
+    c = [[zero] * N for _ in range(L)]
+    phi = [[zero] * N for _ in range(L)]
+    tau = [[None] * N for _ in range(L)]
+
+    for _t in range(iters):
+        for l in range(L):
+            # Eq. 2.1 with damping
+            new_rho = [[None] * N for _ in range(N)]
+            for i in range(N):
+                for j in range(N):
+                    mx = None
+                    for k in range(N):
+                        if k == j:
+                            continue
+                        v = alpha[l][i][k] + s[l][i][k]
+                        if mx is None or v > mx:
+                            mx = v
+                    r = s[l][i][j] - mx if l == 0 else s[l][i][j] + _min_tau(tau[l][i], -mx)
+                    new_rho[i][j] = lam * rho[l][i][j] + (one - lam) * r
+            rho[l] = new_rho
+            # Eq. 2.2 / 2.3 with damping
+            top = (l == L - 1)
+            new_alpha = [[None] * N for _ in range(N)]
+            for j in range(N):
+                base = zero if top else c[l][j] + phi[l][j]
+                for i in range(N):
+                    if i == j:
+                        acc = base
+                        for k in range(N):
+                            if k != j:
+                                acc = acc + max(zero, rho[l][k][j])
+                        a = acc
+                    else:
+                        acc = base + rho[l][j][j]
+                        for k in range(N):
+                            if k != i and k != j:
+                                acc = acc + max(zero, rho[l][k][j])
+                        a = min(zero, acc)
+                    new_alpha[i][j] = lam * alpha[l][i][j] + (one - lam) * a
+            alpha[l] = new_alpha
+            # Eq. 2.4 (c^l from before its update), 2.5, 2.6
+            if l < L - 1:
+                nt = []
+                for j in range(N):
+                    acc = c[l][j] + rho[l][j][j]
+                    for k in range(N):
+                        if k != j:
+                            acc = acc + max(zero, rho[l][k][j])
+                    nt.append(acc)
+                tau[l + 1] = nt
+            if l > 0:
+                phi[l - 1] = [max(alpha[l][i][k] + s[l][i][k] for k in range(N)) for i in range(N)]
+            if l < L - 1:
+                c[l] = [max(alpha[l][i][j] + rho[l][i][j] for j in range(N)) for i in range(N)]
+
+    labels = []
+    for l in range(L):
+        row = []
+        for i in range(N):
+            best, arg = None, -1
+            for j in range(N):
+                v = alpha[l][i][j] + rho[l][i][j]
+                if best is None or v > best:
+                    best, arg = v, j
+            row.append(arg)
+        labels.append(row)
+    return labels, rho, alpha, c, phi, tau
