@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""HAP benchmark on one MI355X: N^2*L message updates per second.
+
+Workload: 8192 points in 2-D from 64 Gaussian blobs (centres U[-100,100]^2,
+sigma U[0.5,2], multinomial sizes), FP32 similarity, L = 3 levels, damping 0.9,
+median preference, up to 500 iterations or 50 iterations with unchanged labels.
+Synthetic data from paper_1403_7394_amd.synth (seed 1002).
+
+One step is one pass of the whole hot path with the points already on the GPU:
+similarity build, median preference and initial state, the sweeps until the
+stop rule, exemplars of every level and the FP64 net similarity.  `value` is
+N^2*L*(sweeps performed) / (wall time of the timed steps).
+
+The roofline entry is for the dominant kernel, the fused row pass: its
+algorithmic traffic (read S, R, A and write R, A: 5 N^2 words per level per
+sweep; 4 N^2 in the first sweep, which has no alpha to finish) divided by its
+average launch duration, measured with HIP events recorded on its own stream
+during the timed steps.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "HAP N²·L message updates/s and time-to-converge vs plain, same GPU"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "row_pass_traffic_plain8192.json")
+SWEEP_SRC = os.path.join(ROOT, "paper_1403_7394_amd", "csrc", "sweep.hip")
+
+
+def sweep_source_hash() -> str:
+    with open(SWEEP_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(bytes_per_launch_alg):
+    """HBM bytes per row-pass launch from the committed counter summary, if it was taken
+    on the current kernel source; otherwise None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("sweep_source_sha256_16") != sweep_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(X, rp, sweeps: int = 2):
+    """The FP64 NumPy oracle on the same workload: `sweeps` full sweeps (all levels), timed."""
+    import numpy as np
+
+    from oracle import hap_ref
+    from oracle import similarity as sim
+
+    S32 = sim.similarity(X).astype(np.float32)
+    p = float(sim.median_offdiag(S32, np.float32))
+    S64 = S32.astype(np.float64)
+    n = X.shape[0]
+    w0, c0 = time.perf_counter(), time.process_time()
+    hap_ref.hap(S64, p, rp.levels, rp.damping, sweeps)
+    wall, cpu = time.perf_counter() - w0, time.process_time() - c0
+    return {
+        "value": n * n * rp.levels * sweeps / wall,
+        "unit": "updates/s",
+        "cores": max(1, round(cpu / wall)),
+        "kind": "oracle",
+        "sample": f"first {sweeps} of up to {rp.max_iters} sweeps (all {rp.levels} levels) of the same "
+                  f"{n}-point workload, FP64 NumPy oracle; similarity build and median not timed",
+        "seconds": wall,
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--cpu-sweeps", type=int, default=2)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 1 GiB device copy (counter calibration under rocprofv3)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the row-block sharding is described in the design notes)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1403_7394_amd import hap, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    hap.load()
+    dev = torch.device("cuda:0")
+    blobs, rp = synth.workload_plain_f32()
+    n = blobs.X.shape[0]
+    L = rp.levels
+    X = torch.from_numpy(blobs.X).to(dev)
+    S = torch.empty((n, n), dtype=torch.float32, device=dev)
+    ws = torch.empty(hap.workspace_size(n, L, hap.HAP_F32), dtype=torch.uint8, device=dev)
+
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
+    def step(profile: bool):
+        hap.build_similarity(X, S)
+        h = hap.Hap(S, L, rp.damping, workspace=ws)
+        if profile:
+            h.profile(True)
+        res = h.iterate(rp.max_iters, rp.stable_iters)
+        prof = h.profile_read() if profile else None
+        counts = [h.exemplars(l)[1] for l in range(L)]
+        ns = h.net_similarity(-1)
+        launch = h.get_launch()
+        h.close()
+        return res, counts, ns, prof, launch
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sweeps = 0
+    row_ms = col_ms = 0.0
+    row_n = col_n = 0
+    first_sweeps = 0
+    for _ in range(args.steps):
+        res, counts, ns, prof, launch = step(True)
+        # an early stop is detected one sweep after the stop iteration; a stop at the cap is not
+        sweeps += res.iters + 1 if (res.converged and res.iters < rp.max_iters) else res.iters
+        first_sweeps += 1
+        row_ms += prof[0]
+        row_n += prof[1]
+        col_ms += prof[2]
+        col_n += prof[3]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    w = 4
+    # algorithmic bytes of all row-pass launches: 4 N^2 w in the first sweep, 5 N^2 w after
+    alg_bytes_total = (first_sweeps * L * 4 + (row_n - first_sweeps * L) * 5) * n * n * w
+    bytes_per_launch = alg_bytes_total / max(row_n, 1)
+    avg_launch_s = row_ms / max(row_n, 1) * 1e-3
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    traffic = measured_traffic(bytes_per_launch)
+    ms_per_step = elapsed / args.steps * 1e3
+    value = n * n * L * sweeps / elapsed
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "plain HAP, 8192 points in 2-D, 64 Gaussian blobs, FP32, L=3, damping 0.9, "
+                        "median preference, 500 iterations or 50 stable",
+            "n": n, "levels": L, "damping": rp.damping, "max_iters": rp.max_iters,
+            "stable_iters": rp.stable_iters, "seed": blobs.seed,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "row pass (sweep_kernel)",
+            "avg_launch_us": avg_launch_s * 1e6,
+            "alg_bytes_per_launch": bytes_per_launch,
+            "launches": row_n,
+        },
+        "sweeps_per_step": sweeps / args.steps,
+        "converged": bool(res.converged),
+        "time_to_converge_ms": ms_per_step,
+        "sweep_updates_per_s": n * n * L * sweeps / ((row_ms + col_ms) * 1e-3) if row_ms > 0 else None,
+        "colsum_avg_us": col_ms / max(col_n, 1) * 1e3,
+        "exemplars_per_level": counts,
+        "net_similarity": ns,
+        "launch": {"threads": launch[0], "chunks": launch[1], "rows_per_block": launch[2], "prefetch": launch[3]},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(blobs.X, rp, args.cpu_sweeps)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

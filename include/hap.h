@@ -1,0 +1,213 @@
+/*
+ * libhap -- Hierarchical Affinity Propagation (HAP) on AMD MI355X (gfx950).
+ *
+ * C ABI of the HIP library.  All pointers are plain addresses: "device" means
+ * memory the HIP runtime allocated on the GPU the stream belongs to (for
+ * example a torch tensor's data_ptr()), "host" means ordinary CPU memory.
+ * No call takes ownership of caller memory.
+ *
+ * Problem statement (Section 2 and Algorithm 1 of Rose et al., "Parallel
+ * Hierarchical Affinity Propagation with MapReduce", arXiv 1403.7394): the
+ * input is a dense N x N similarity S with s_ij <= 0 whose diagonal holds the
+ * preferences, a number of levels L and a damping factor lambda; the method
+ * iterates the responsibility / availability updates (Eq. 2.1-2.3) and the
+ * inter-level messages tau, phi and the cluster preference c (Eq. 2.4-2.6) at
+ * every level, and outputs the exemplar e^l_i = argmax_j (alpha^l_ij + rho^l_ij)
+ * of every point at every level (Eq. 2.8).
+ *
+ * Layout: matrices are row-major with a leading dimension (elements between the
+ * starts of consecutive rows).  A matrix argument of n rows and leading
+ * dimension ld must be a buffer of n*ld elements, 16-byte aligned, with ld >= n
+ * and ld a multiple of 4 (FP32) or 2 (FP64).
+ *
+ * Errors: every call returns a status; nothing throws or aborts across the ABI.
+ * Invalid arguments give HAP_E_ARG and change nothing.  A HIP failure gives
+ * HAP_E_HIP with the runtime's message in hap_last_error() (per host thread);
+ * after a device error the context refuses further iteration (HAP_E_STATE).
+ *
+ * Streams: every call is ordered on the stream given to hap_init (or to the
+ * standalone call).  Calls that return a host value (iteration counts, exemplar
+ * counts, net similarity, the preference) synchronise that stream.
+ * One host thread at a time may use a context; separate contexts on separate
+ * streams may run concurrently.
+ */
+#ifndef HAP_H
+#define HAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define HAP_API __attribute__((visibility("default")))
+#else
+#define HAP_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hap_status;
+enum {
+    HAP_OK = 0,
+    HAP_E_ARG = 1,          /* invalid argument; nothing was changed */
+    HAP_E_DTYPE = 2,        /* unsupported data type or type combination */
+    HAP_E_OOM = 3,          /* device allocation failed */
+    HAP_E_HIP = 4,          /* HIP runtime error; see hap_last_error() */
+    HAP_E_STATE = 5,        /* context unusable after an earlier device error */
+    HAP_E_UNSUPPORTED = 6   /* size or mode not supported by this build */
+};
+
+enum { HAP_F32 = 0, HAP_F64 = 1, HAP_BF16 = 2 };
+
+/* Similarity build modes (s_ij = -||x_i - x_j||^2, Section 2). */
+enum {
+    HAP_BUILD_DIRECT = 0,   /* sum of squared coordinate differences, accumulated in FP64,
+                               rounded once to the output type (VALU; any d) */
+    HAP_BUILD_GEMM = 1,     /* -(|x_i|^2 + |x_j|^2 - 2 x_i.x_j) with the Gram matrix on MFMA
+                               in the output precision (FP32 or FP64) */
+    HAP_BUILD_BF16 = 2,     /* Gram matrix on BF16 MFMA with FP32 accumulation (FP32 output) */
+    HAP_BUILD_BF16X3 = 3    /* split x = hi + lo in BF16, x.y ~ hi.hi + hi.lo + lo.hi on MFMA,
+                               FP32 accumulation (FP32 output) */
+};
+
+/* Preference (diagonal s^l_jj) sources. */
+enum {
+    HAP_PREF_MEDIAN = 0,    /* median of the N(N-1) off-diagonal entries of S, every level */
+    HAP_PREF_SCALAR = 1,    /* pref_scalar[l] for every point of level l */
+    HAP_PREF_VECTOR = 2     /* pref_vec[l*n + j], device, in the working type */
+};
+
+typedef struct {
+    uint32_t struct_size;       /* sizeof(hap_params) */
+    int32_t levels;             /* L >= 1 */
+    double damping;             /* lambda in [0, 1) */
+    int32_t pref_mode;          /* HAP_PREF_* */
+    int32_t reserved0;
+    const double *pref_scalar;  /* host [levels], HAP_PREF_SCALAR only */
+    const void *pref_vec;       /* device [levels*n] in the working type, HAP_PREF_VECTOR only */
+} hap_params;
+
+typedef struct hap_ctx hap_ctx;
+
+/* Library version string, e.g. "libhap 0.1.0 gfx950". */
+HAP_API const char *hap_version(void);
+HAP_API const char *hap_status_string(hap_status s);
+/* Message of the last failing call on this host thread ("" if none). */
+HAP_API const char *hap_last_error(void);
+
+/*
+ * Similarity build, Section 2: S[i*lds + j] = -||x_i - x_j||^2 for i, j < n.
+ * X: device, n x d row-major with leading dimension ldx (>= d), type x_dtype
+ * (HAP_F32 or HAP_F64).  S: device, n x lds, type s_dtype.  The diagonal is
+ * written as 0 and columns n..lds-1 are not touched.
+ * noise_rel > 0 (FP64 output only) adds the off-diagonal tie-break noise
+ * s_ij += (noise_rel * |s_ij|) * u_ij, u_ij = (splitmix64(seed ^ (i*n + j)) >> 11) * 2^-53,
+ * splitmix64(x) being the first output of a SplitMix64 generator started at x.
+ * Stream-ordered, does not synchronise.
+ */
+HAP_API hap_status hap_build_similarity(const void *X, int64_t n, int64_t d, int64_t ldx, int32_t x_dtype,
+                                void *S, int64_t lds, int32_t s_dtype, int32_t build_mode,
+                                double noise_rel, uint64_t seed, void *stream);
+
+/*
+ * Median of the n(n-1) off-diagonal entries of S (device, n x lds, type dtype):
+ * the mean of the two middle order statistics, formed in FP64 and rounded to
+ * dtype, written to *out_host as a double.  Exact (radix select on the bit
+ * patterns).  Synchronises the stream.
+ */
+HAP_API hap_status hap_median_offdiag(const void *S, int64_t n, int64_t lds, int32_t dtype,
+                              double *out_host, void *stream);
+
+/* Bytes of device workspace hap_init needs for this problem. */
+HAP_API hap_status hap_workspace_size(int64_t n, int32_t levels, int32_t dtype, size_t *bytes);
+
+/*
+ * Create a context for HAP on S (device, n x lds, type dtype, n >= 2).  The
+ * context borrows S: it must stay valid and unmodified until hap_destroy, and
+ * its diagonal is never read or written (the preferences take its place).
+ * workspace: device memory of at least hap_workspace_size() bytes, owned by the
+ * caller and 256-byte aligned, or NULL for the library to allocate (and free in
+ * hap_destroy).  Sets the Algorithm 1 initial state alpha = rho = 0, tau = +inf,
+ * phi = c = 0 and computes the preferences.  Stream-ordered.
+ */
+HAP_API hap_status hap_init(hap_ctx **out, const void *S, int64_t n, int64_t lds, int32_t dtype,
+                    const hap_params *params, void *workspace, size_t workspace_bytes,
+                    void *stream);
+
+/*
+ * Run up to max_iters more iterations of Algorithm 1 (every level, in order,
+ * per iteration).  stable_iters = K > 0 stops at the end of the first iteration
+ * whose labels at every level equal those of the K previous iterations;
+ * K = 0 runs exactly max_iters.  The iteration count and the stable count
+ * persist across calls, so a run can be continued.  iters_done (host, may be
+ * NULL) receives the total iterations completed (the stop iteration after an
+ * early stop); converged (host, may be NULL) is 1 when the stable count reached
+ * K.  Synchronises the stream.
+ */
+HAP_API hap_status hap_iterate(hap_ctx *ctx, int32_t max_iters, int32_t stable_iters,
+                       int32_t *iters_done, int32_t *converged);
+
+/*
+ * Exemplars of level `level` (0-based, 0 = bottom) after the last completed
+ * iteration, Eq. 2.8 (lowest index on ties): labels (device int32 [n], may be
+ * NULL) receives e^l_i; n_exemplars (host, may be NULL) the number of distinct
+ * exemplars.  Does not change the iteration state.  Synchronises if n_exemplars.
+ */
+HAP_API hap_status hap_exemplars(hap_ctx *ctx, int32_t level, int32_t *labels, int32_t *n_exemplars);
+
+/*
+ * Net similarity NS^l = sum_i s^l_{i, e^l_i} (s^l_ii = p^l_i), accumulated in
+ * FP64 on the GPU; level = -1 gives the sum over levels.  X (device, n x d,
+ * leading dimension ldx, type x_dtype) may be given to recompute the
+ * similarities -||x_i - x_e||^2 in FP64 instead of reading S.  Synchronises.
+ */
+HAP_API hap_status hap_net_similarity(hap_ctx *ctx, int32_t level, const void *X, int64_t d, int64_t ldx,
+                              int32_t x_dtype, double *out);
+
+/* Preference p^l_0 of every level (host double [levels]).  Synchronises. */
+HAP_API hap_status hap_preference(hap_ctx *ctx, double *out);
+
+/*
+ * Copy the messages of level `level` after the last completed iteration t:
+ * rho^{l,t} and alpha^{l,t} into device buffers (n x ld, working type; either may
+ * be NULL) and the vectors c^l, phi^l, tau^l (device [n], working type; any may
+ * be NULL).  Does not change the iteration state.  For inspection and tests.
+ */
+HAP_API hap_status hap_read_messages(hap_ctx *ctx, int32_t level, void *rho, void *alpha, int64_t ld,
+                             void *c, void *phi, void *tau);
+
+/*
+ * Override the sweep launch shape: threads per row (64..1024, power of two),
+ * 16-byte column chunks per thread (1, 2, 4 or 8; 4 needs <= 512 threads, 8 needs
+ * <= 256) and rows per workgroup (>= 1; 1 sums the column partials in row
+ * order).  threads * chunks * (16 / element size) must cover n.  0 keeps the
+ * library's choice for that field.  flags: HAP_LAUNCH_PREFETCH loads the next
+ * row while the current one is reduced; -1 keeps the current flags.  Returns
+ * HAP_E_ARG (and changes nothing) for a shape that does not fit.  For the
+ * autotuner.
+ */
+enum { HAP_LAUNCH_PREFETCH = 1 };
+HAP_API hap_status hap_set_launch(hap_ctx *ctx, int32_t threads, int32_t chunks, int32_t rows_per_block,
+                                  int32_t flags);
+HAP_API hap_status hap_get_launch(hap_ctx *ctx, int32_t *threads, int32_t *chunks, int32_t *rows_per_block,
+                                  int32_t *flags);
+
+/*
+ * Per-launch timing of the sweep kernels with HIP events recorded on the
+ * context's stream around every launch.  enable = 1 starts collecting (and
+ * clears the totals), 0 stops.  hap_profile_read returns the summed elapsed time
+ * (ms) and the launch count of the row pass (Eq. 2.1-2.6 fused, one launch per
+ * level and iteration) and of the column-sum epilogue (Eq. 2.4).  For the
+ * benchmark's roofline figure.
+ */
+HAP_API hap_status hap_profile(hap_ctx *ctx, int32_t enable);
+HAP_API hap_status hap_profile_read(hap_ctx *ctx, double *row_pass_ms, int64_t *row_pass_launches,
+                                    double *colsum_ms, int64_t *colsum_launches);
+
+HAP_API hap_status hap_destroy(hap_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HAP_H */

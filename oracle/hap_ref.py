@@ -67,18 +67,18 @@ class HapResult:
     history: list = field(default_factory=list)
 
 
-def level_similarity(S: np.ndarray, pref_l: np.ndarray) -> np.ndarray:
+def level_similarity(S: np.ndarray, pref_l: np.ndarray, dtype=np.float64) -> np.ndarray:
     """s^l: the off-diagonal of S with the level-l preferences on the diagonal."""
-    s = np.array(S, dtype=np.float64, copy=True)
+    s = np.array(S, dtype=dtype, copy=True)
     np.fill_diagonal(s, pref_l)
     return s
 
 
-def init_state(N: int, L: int, alpha0: np.ndarray | None = None) -> HapState:
+def init_state(N: int, L: int, alpha0: np.ndarray | None = None, dtype=np.float64) -> HapState:
     """Algorithm 1 initialisation: alpha = rho = 0, tau = +inf, phi = c = 0."""
-    alpha = np.zeros((L, N, N)) if alpha0 is None else np.array(alpha0, dtype=np.float64, copy=True)
-    return HapState(rho=np.zeros((L, N, N)), alpha=alpha, c=np.zeros((L, N)),
-                    phi=np.zeros((L, N)), tau=np.full((L, N), np.inf))
+    alpha = np.zeros((L, N, N), dtype) if alpha0 is None else np.array(alpha0, dtype=dtype, copy=True)
+    return HapState(rho=np.zeros((L, N, N), dtype), alpha=alpha, c=np.zeros((L, N), dtype),
+                    phi=np.zeros((L, N), dtype), tau=np.full((L, N), np.inf, dtype))
 
 
 def responsibility(s: np.ndarray, alpha: np.ndarray, tau: np.ndarray | None) -> np.ndarray:
@@ -102,7 +102,7 @@ def responsibility(s: np.ndarray, alpha: np.ndarray, tau: np.ndarray | None) -> 
 
 def column_sums(rho: np.ndarray) -> np.ndarray:
     """Q_j = rho_jj + sum_{k != j} max(0, rho_kj) (the common part of Eq. 2.2-2.4)."""
-    pos = np.maximum(rho, 0.0)
+    pos = np.maximum(rho, rho.dtype.type(0))
     idx = np.arange(rho.shape[0])
     pos[idx, idx] = rho[idx, idx]
     return pos.sum(axis=0)
@@ -110,7 +110,8 @@ def column_sums(rho: np.ndarray) -> np.ndarray:
 
 def availability(rho: np.ndarray, B: np.ndarray) -> np.ndarray:
     """Undamped Eq. 2.2 (i != j) and Eq. 2.3 (i == j) given B_j = [c_j + phi_j +] Q_j."""
-    a = np.minimum(0.0, B[None, :] - np.maximum(rho, 0.0))
+    zero = rho.dtype.type(0)
+    a = np.minimum(zero, B[None, :] - np.maximum(rho, zero))
     idx = np.arange(rho.shape[0])
     a[idx, idx] = B - rho[idx, idx]
     return a
@@ -122,8 +123,14 @@ def labels_of(state: HapState) -> np.ndarray:
 
 
 def hap(S, pref, levels: int, damping: float, max_iters: int, stable_iters: int = 0,
-        alpha0=None, state: HapState | None = None, record=None, c_zero: bool = False) -> HapResult:
-    """Run HAP (Algorithm 1) in FP64.
+        alpha0=None, state: HapState | None = None, record=None, c_zero: bool = False,
+        dtype=np.float64) -> HapResult:
+    """Run HAP (Algorithm 1), in FP64 unless `dtype` says otherwise.
+
+    The paper fixes no precision.  dtype=np.float32 evaluates the same steps with every
+    operation rounded to single precision (NumPy computes float32 arithmetic in float32,
+    and its column sum over axis 0 adds the rows one after another), which is the
+    arithmetic of an FP32 implementation that sums columns in row order.
 
     S      (N, N) similarity; its diagonal is ignored.
     pref   preferences: scalar, (N,) shared by all levels, or (L, N).
@@ -133,30 +140,32 @@ def hap(S, pref, levels: int, damping: float, max_iters: int, stable_iters: int 
     record optional callable(t, l, state) called after every level update.
     c_zero diagnosis switch: keep c = 0 (a constant cluster preference) instead of Eq. 2.6.
     """
-    S = np.asarray(S, dtype=np.float64)
+    dt = np.dtype(dtype).type
+    S = np.asarray(S, dtype=dt)
     N = S.shape[0]
     L = int(levels)
-    lam = float(damping)
-    p = np.asarray(pref, dtype=np.float64)
+    lam = dt(damping)
+    oml = dt(1.0 - float(damping))
+    p = np.asarray(pref, dtype=dt)
     if p.ndim == 0:
-        p = np.full((L, N), float(p))
+        p = np.full((L, N), p, dtype=dt)
     elif p.ndim == 1:
         p = np.repeat(p[None, :], L, axis=0)
-    s = [level_similarity(S, p[l]) for l in range(L)]
+    s = [level_similarity(S, p[l], dt) for l in range(L)]
 
-    st = init_state(N, L, alpha0) if state is None else state.copy()
-    Q = np.zeros((L, N))
+    st = init_state(N, L, alpha0, dt) if state is None else state.copy()
+    Q = np.zeros((L, N), dt)
     converged = False
     for _ in range(max_iters):
         st.t += 1
         for l in range(L):
             # Eq. 2.1, then damp
             rhat = responsibility(s[l], st.alpha[l], None if l == 0 else st.tau[l])
-            st.rho[l] = lam * st.rho[l] + (1.0 - lam) * rhat
+            st.rho[l] = lam * st.rho[l] + oml * rhat
             # Eq. 2.2 / 2.3 with the damped rho, then damp
             Q[l] = column_sums(st.rho[l])
             B = (st.c[l] + st.phi[l]) + Q[l] if l < L - 1 else Q[l].copy()
-            st.alpha[l] = lam * st.alpha[l] + (1.0 - lam) * availability(st.rho[l], B)
+            st.alpha[l] = lam * st.alpha[l] + oml * availability(st.rho[l], B)
             # Eq. 2.4 (up, uses c^l before its update), Eq. 2.5 (down), Eq. 2.6
             if l < L - 1:
                 st.tau[l + 1] = st.c[l] + Q[l]

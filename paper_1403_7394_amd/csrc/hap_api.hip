@@ -1,0 +1,698 @@
+// C ABI of libhap (declared in include/hap.h): argument checks, the context and its
+// workspace, and the host side of the iteration.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hap_internal.h"
+
+namespace hap {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+}  // namespace hap
+
+using hap::DevState;
+using hap::Launch;
+using hap::LevelPtrs;
+
+struct hap_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int64_t n = 0, lds = 0, ldw = 0;
+    int L = 0;
+    int dtype = HAP_F32;
+    size_t esz = 4;
+    double lam = 0.0;
+    const void *S = nullptr;
+
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool own_ws = false;
+
+    // workspace regions
+    char *R = nullptr, *A = nullptr, *pref = nullptr, *Q = nullptr, *phi = nullptr, *tau = nullptr, *C = nullptr;
+    int32_t *E = nullptr, *Efinal = nullptr, *mark = nullptr, *count = nullptr;
+    char *Qpart = nullptr;
+    DevState *ds = nullptr;
+    double *dbl = nullptr;        // [0] median, [1..] net similarity per level + total
+    void *select_scratch = nullptr;
+    int nb_cap = 0;
+
+    Launch lc{};
+    // per-launch event timing (hap_profile)
+    bool prof = false;
+    std::vector<hipEvent_t> ev;      // pairs: [2k] before, [2k+1] after launch k of the current chunk
+    std::vector<int> ev_kind;        // 0 = row pass, 1 = column sums
+    int ev_used = 0;
+    double prof_ms[2] = {0.0, 0.0};
+    long long prof_n[2] = {0, 0};
+    int t_host = 0;               // completed iterations, mirrored on the host
+    bool labels_ready = false;    // Efinal holds the labels of iteration t_host
+    bool failed = false;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+struct Layout {
+    size_t R, A, pref, Q, phi, tau, C, E, Efinal, mark, count, Qpart, ds, dbl, sel, total;
+    int64_t ldw;
+    int nb_cap;
+};
+
+Layout make_layout(int64_t n, int L, size_t esz) {
+    Layout lo{};
+    lo.ldw = (n + 63) / 64 * 64;
+    lo.nb_cap = (int)(n < 2048 ? n : 2048);
+    const size_t mat = (size_t)n * lo.ldw * esz;
+    const size_t vec = (size_t)lo.ldw * esz;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    lo.R = take(mat * L);
+    lo.A = take(mat * L);
+    lo.pref = take(vec * L);
+    lo.Q = take(vec * L);
+    lo.phi = take(vec * L);
+    lo.tau = take(vec * L);
+    lo.C = take(vec * 2 * L);
+    lo.E = take((size_t)lo.ldw * 4 * L);
+    lo.Efinal = take((size_t)lo.ldw * 4 * L);
+    lo.mark = take((size_t)lo.ldw * 4);
+    lo.count = take(64);
+    lo.Qpart = take((size_t)lo.nb_cap * vec);
+    lo.ds = take(sizeof(DevState));
+    lo.dbl = take(sizeof(double) * (size_t)(L + 4));
+    lo.sel = take(hap::select_scratch_bytes());
+    lo.total = off;
+    return lo;
+}
+
+hap_status fail_hip(hipError_t e, const char *where, hap_ctx *ctx = nullptr) {
+    std::string m = std::string(where) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+    hap::set_error(m);
+    if (ctx) ctx->failed = true;
+    return HAP_E_HIP;
+}
+
+hap_status fail_arg(const char *msg, hap_status code = HAP_E_ARG) {
+    hap::set_error(msg);
+    return code;
+}
+
+#define HIP_TRY(expr, ctx)                                   \
+    do {                                                     \
+        hipError_t _e = (expr);                              \
+        if (_e != hipSuccess) return fail_hip(_e, #expr, ctx); \
+    } while (0)
+
+template <typename T>
+LevelPtrs<T> level_ptrs(const hap_ctx *c, int l) {
+    LevelPtrs<T> p;
+    const size_t mat = (size_t)c->n * c->ldw;
+    p.R = (T *)c->R + mat * l;
+    p.A = (T *)c->A + mat * l;
+    p.pref = (T *)c->pref + (size_t)c->ldw * l;
+    p.Q = (T *)c->Q + (size_t)c->ldw * l;
+    p.phi = (T *)c->phi + (size_t)c->ldw * l;
+    p.tau = (T *)c->tau + (size_t)c->ldw * l;
+    p.C = (T *)c->C + (size_t)c->ldw * 2 * l;
+    p.E = c->E + (size_t)c->ldw * l;
+    p.Efinal = c->Efinal + (size_t)c->ldw * l;
+    return p;
+}
+
+Launch default_launch(int64_t n, size_t esz) {
+    const int vw = (int)(16 / esz);
+    Launch lc{64, 1, 1, false, false};
+    const int order[4] = {4, 2, 8, 1};
+    bool found = false;
+    for (int oi = 0; oi < 4 && !found; ++oi) {
+        const int nch = order[oi];
+        const int64_t need = (n + (int64_t)vw * nch - 1) / ((int64_t)vw * nch);
+        int nt = 64;
+        while (nt < need) nt <<= 1;
+        if (nt <= (nch == 8 ? 512 : 1024)) {
+            lc.threads = nt;
+            lc.chunks = nch;
+            found = true;
+        }
+    }
+    if (!found) {
+        lc.threads = 0;
+        return lc;
+    }
+    // About 256 workgroups (one per CU) on large problems.  Small problems (FP32 up to 512
+    // points, FP64 up to 2048) take one row per workgroup and sum the column partials in
+    // row order, which is the order of a plain sequential column sum.
+    int rb = (int)((n + 255) / 256);
+    if (rb < 1) rb = 1;
+    if (n <= (esz == 8 ? 2048 : 512)) rb = 1;
+    lc.rows_per_block = rb;
+    lc.ordered = (rb == 1);
+    return lc;
+}
+
+bool launch_fits(const Launch &lc, int64_t n, size_t esz, int nb_cap) {
+    if (!hap::launch_supported(lc.threads, lc.chunks, (int)esz)) return false;
+    if ((int64_t)lc.threads * lc.chunks * (int64_t)(16 / esz) < n) return false;
+    if (lc.rows_per_block < 1) return false;
+    const int64_t nb = (n + lc.rows_per_block - 1) / lc.rows_per_block;
+    return nb <= nb_cap;
+}
+
+bool dtype_ok(int32_t dt) { return dt == HAP_F32 || dt == HAP_F64; }
+size_t dtype_size(int32_t dt) { return dt == HAP_F64 ? 8 : 4; }
+
+bool ld_ok(int64_t n, int64_t ld, int32_t dt) {
+    const int64_t vw = (int64_t)(16 / dtype_size(dt));
+    return ld >= n && ld % vw == 0;
+}
+
+// Event pair around the next launch when profiling (the pool grows on demand).
+hipError_t prof_mark(hap_ctx *c, int kind, bool after) {
+    if (!c->prof) return hipSuccess;
+    if (!after) {
+        const size_t need = (size_t)(c->ev_used + 1) * 2;
+        while (c->ev.size() < need) {
+            hipEvent_t e;
+            hipError_t err = hipEventCreate(&e);
+            if (err != hipSuccess) return err;
+            c->ev.push_back(e);
+        }
+        if (c->ev_kind.size() < (size_t)c->ev_used + 1) c->ev_kind.resize(c->ev_used + 1);
+        c->ev_kind[c->ev_used] = kind;
+        return hipEventRecord(c->ev[2 * c->ev_used], c->stream);
+    }
+    hipError_t err = hipEventRecord(c->ev[2 * c->ev_used + 1], c->stream);
+    c->ev_used += 1;
+    return err;
+}
+
+// Accumulate the recorded pairs (the stream must have been synchronised).
+hipError_t prof_collect(hap_ctx *c) {
+    for (int k = 0; k < c->ev_used; ++k) {
+        float ms = 0.f;
+        hipError_t err = hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]);
+        if (err != hipSuccess) return err;
+        c->prof_ms[c->ev_kind[k]] += ms;
+        c->prof_n[c->ev_kind[k]] += 1;
+    }
+    c->ev_used = 0;
+    return hipSuccess;
+}
+
+template <typename T>
+hap_status run_sweeps(hap_ctx *c, int count, int K) {
+    const int L = c->L;
+    const int nb = (int)((c->n + c->lc.rows_per_block - 1) / c->lc.rows_per_block);
+    T *Qpart = (T *)c->Qpart;
+    for (int it = 0; it < count; ++it) {
+        for (int l = 0; l < L; ++l) {
+            LevelPtrs<T> lv = level_ptrs<T>(c, l);
+            T *phi_down = l > 0 ? level_ptrs<T>(c, l - 1).phi : nullptr;
+            const T *tau_l = l > 0 ? lv.tau : nullptr;
+            HIP_TRY(prof_mark(c, 0, false), c);
+            HIP_TRY(hap::launch_sweep_level<T>((const T *)c->S, c->lds, lv, phi_down, tau_l, (int)c->n, c->ldw, l, L,
+                                               c->lam, Qpart, c->lc, c->ds, c->stream),
+                    c);
+            HIP_TRY(prof_mark(c, 0, true), c);
+            T *tau_next = (l + 1 < L) ? level_ptrs<T>(c, l + 1).tau : nullptr;
+            HIP_TRY(prof_mark(c, 1, false), c);
+            HIP_TRY(hap::launch_colsum<T>(Qpart, c->ldw, nb, (int)c->n, lv, tau_next, l == L - 1, K, c->lc.ordered,
+                                          c->ds, c->stream),
+                    c);
+            HIP_TRY(prof_mark(c, 1, true), c);
+        }
+    }
+    return HAP_OK;
+}
+
+template <typename T>
+hap_status finalize_labels(hap_ctx *c) {
+    // labels of iteration t: alpha^t materialised on the fly, nothing in the state written
+    HIP_TRY(hipMemsetAsync(&c->ds->final_changed, 0, sizeof(int32_t), c->stream), c);
+    for (int l = 0; l < c->L; ++l) {
+        LevelPtrs<T> lv = level_ptrs<T>(c, l);
+        HIP_TRY(hap::launch_finalize<T>((const T *)c->S, c->lds, lv, (int)c->n, c->ldw, l, c->L, c->lam, c->t_host,
+                                        c->lc, lv.Efinal, nullptr, 0, nullptr, nullptr, c->ds, c->stream),
+                c);
+    }
+    return HAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hap_version(void) { return "libhap 0.1.0 gfx950"; }
+
+const char *hap_status_string(hap_status s) {
+    switch (s) {
+        case HAP_OK: return "ok";
+        case HAP_E_ARG: return "invalid argument";
+        case HAP_E_DTYPE: return "unsupported data type";
+        case HAP_E_OOM: return "device allocation failed";
+        case HAP_E_HIP: return "HIP runtime error";
+        case HAP_E_STATE: return "context unusable after an earlier device error";
+        case HAP_E_UNSUPPORTED: return "unsupported size or mode";
+        default: return "unknown status";
+    }
+}
+
+const char *hap_last_error(void) { return hap::g_last_error.c_str(); }
+
+hap_status hap_build_similarity(const void *X, int64_t n, int64_t d, int64_t ldx, int32_t x_dtype, void *S,
+                                int64_t lds, int32_t s_dtype, int32_t build_mode, double noise_rel, uint64_t seed,
+                                void *stream) {
+    if (!X || !S) return fail_arg("hap_build_similarity: null pointer");
+    if (n < 1 || d < 1 || ldx < d || lds < n) return fail_arg("hap_build_similarity: bad sizes");
+    if (n > (int64_t)1 << 20 || d > (int64_t)1 << 20) return fail_arg("hap_build_similarity: size too large", HAP_E_UNSUPPORTED);
+    if (!dtype_ok(x_dtype) || !dtype_ok(s_dtype)) return fail_arg("hap_build_similarity: dtype", HAP_E_DTYPE);
+    if (!(noise_rel >= 0.0) || !std::isfinite(noise_rel)) return fail_arg("hap_build_similarity: noise_rel");
+    if (noise_rel > 0.0 && s_dtype != HAP_F64) return fail_arg("hap_build_similarity: noise needs FP64 output", HAP_E_DTYPE);
+    if (build_mode != HAP_BUILD_DIRECT) return fail_arg("hap_build_similarity: build mode not available", HAP_E_UNSUPPORTED);
+    hipError_t e = hap::launch_build(X, n, d, ldx, x_dtype, S, lds, s_dtype, build_mode, noise_rel, seed,
+                                     (hipStream_t)stream);
+    if (e != hipSuccess) return fail_hip(e, "hap_build_similarity");
+    return HAP_OK;
+}
+
+hap_status hap_median_offdiag(const void *S, int64_t n, int64_t lds, int32_t dtype, double *out_host, void *stream) {
+    if (!S || !out_host) return fail_arg("hap_median_offdiag: null pointer");
+    if (!dtype_ok(dtype)) return fail_arg("hap_median_offdiag: dtype", HAP_E_DTYPE);
+    if (n < 2 || !ld_ok(n, lds, dtype)) return fail_arg("hap_median_offdiag: bad sizes");
+    if (n > (int64_t)1 << 20) return fail_arg("hap_median_offdiag: n too large", HAP_E_UNSUPPORTED);
+    hipStream_t st = (hipStream_t)stream;
+    void *scratch = nullptr;
+    const size_t bytes = hap::select_scratch_bytes() + 256;
+    hipError_t e = hipMallocAsync(&scratch, bytes, st);
+    if (e != hipSuccess) return fail_hip(e, "hap_median_offdiag: hipMallocAsync");
+    double *dev_out = (double *)((char *)scratch + hap::select_scratch_bytes());
+    e = hap::launch_median_offdiag(S, n, lds, dtype, scratch, dev_out, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(out_host, dev_out, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    hipError_t e2 = hipFreeAsync(scratch, st);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail_hip(e, "hap_median_offdiag");
+    return HAP_OK;
+}
+
+hap_status hap_workspace_size(int64_t n, int32_t levels, int32_t dtype, size_t *bytes) {
+    if (!bytes) return fail_arg("hap_workspace_size: null pointer");
+    if (n < 2 || levels < 1 || levels > 64) return fail_arg("hap_workspace_size: bad sizes");
+    if (!dtype_ok(dtype)) return fail_arg("hap_workspace_size: dtype", HAP_E_DTYPE);
+    *bytes = make_layout(n, levels, dtype_size(dtype)).total;
+    return HAP_OK;
+}
+
+hap_status hap_init(hap_ctx **out, const void *S, int64_t n, int64_t lds, int32_t dtype, const hap_params *p,
+                    void *workspace, size_t workspace_bytes, void *stream) {
+    if (!out || !S || !p) return fail_arg("hap_init: null pointer");
+    *out = nullptr;
+    if (p->struct_size < sizeof(hap_params)) return fail_arg("hap_init: hap_params.struct_size too small");
+    if (!dtype_ok(dtype)) return fail_arg("hap_init: dtype", HAP_E_DTYPE);
+    if (n < 2 || !ld_ok(n, lds, dtype)) return fail_arg("hap_init: need n >= 2, lds >= n, lds a multiple of 16 bytes");
+    if (((uintptr_t)S & 15u) != 0) return fail_arg("hap_init: S must be 16-byte aligned");
+    if (p->levels < 1 || p->levels > 64) return fail_arg("hap_init: levels must be in [1, 64]");
+    if (!(p->damping >= 0.0 && p->damping < 1.0)) return fail_arg("hap_init: damping must be in [0, 1)");
+    if (p->pref_mode == HAP_PREF_SCALAR) {
+        if (!p->pref_scalar) return fail_arg("hap_init: pref_scalar is null");
+        for (int l = 0; l < p->levels; ++l)
+            if (!std::isfinite(p->pref_scalar[l])) return fail_arg("hap_init: non-finite preference");
+    } else if (p->pref_mode == HAP_PREF_VECTOR) {
+        if (!p->pref_vec) return fail_arg("hap_init: pref_vec is null");
+    } else if (p->pref_mode != HAP_PREF_MEDIAN) {
+        return fail_arg("hap_init: pref_mode");
+    }
+    const size_t esz = dtype_size(dtype);
+    Layout lo = make_layout(n, p->levels, esz);
+    Launch lc = default_launch(n, esz);
+    if (lc.threads == 0 || !launch_fits(lc, n, esz, lo.nb_cap))
+        return fail_arg("hap_init: n too large for the register-resident row pass", HAP_E_UNSUPPORTED);
+    if (workspace) {
+        if (workspace_bytes < lo.total) return fail_arg("hap_init: workspace too small");
+        if (((uintptr_t)workspace & (kAlign - 1)) != 0) return fail_arg("hap_init: workspace must be 256-byte aligned");
+    }
+
+    hap_ctx *c = new (std::nothrow) hap_ctx();
+    if (!c) return fail_arg("hap_init: host allocation failed", HAP_E_OOM);
+    c->stream = (hipStream_t)stream;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) {
+        delete c;
+        return fail_hip(e, "hap_init: hipGetDevice");
+    }
+    c->n = n;
+    c->lds = lds;
+    c->ldw = lo.ldw;
+    c->L = p->levels;
+    c->dtype = dtype;
+    c->esz = esz;
+    c->lam = p->damping;
+    c->S = S;
+    c->lc = lc;
+    c->nb_cap = lo.nb_cap;
+    if (workspace) {
+        c->ws = workspace;
+        c->ws_bytes = workspace_bytes;
+    } else {
+        e = hipMalloc(&c->ws, lo.total);
+        if (e != hipSuccess) {
+            delete c;
+            (void)hipGetLastError();
+            return fail_arg("hap_init: hipMalloc of the workspace failed", HAP_E_OOM);
+        }
+        c->ws_bytes = lo.total;
+        c->own_ws = true;
+    }
+    char *base = (char *)c->ws;
+    c->R = base + lo.R;
+    c->A = base + lo.A;
+    c->pref = base + lo.pref;
+    c->Q = base + lo.Q;
+    c->phi = base + lo.phi;
+    c->tau = base + lo.tau;
+    c->C = base + lo.C;
+    c->E = (int32_t *)(base + lo.E);
+    c->Efinal = (int32_t *)(base + lo.Efinal);
+    c->mark = (int32_t *)(base + lo.mark);
+    c->count = (int32_t *)(base + lo.count);
+    c->Qpart = base + lo.Qpart;
+    c->ds = (DevState *)(base + lo.ds);
+    c->dbl = (double *)(base + lo.dbl);
+    c->select_scratch = base + lo.sel;
+
+    hipStream_t st = c->stream;
+    auto bail = [&](hipError_t err, const char *where) {
+        hap_status s = fail_hip(err, where);
+        if (c->own_ws) (void)hipFree(c->ws);
+        delete c;
+        return s;
+    };
+    // Algorithm 1 initial state: alpha = rho = 0, phi = c = 0, tau = +inf (tau^1 is never read;
+    // tau^l for l > 1 is written before it is read), labels 0, counters 0.
+    e = hipMemsetAsync(c->ws, 0, lo.Qpart, st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ds, 0, sizeof(DevState), st);
+    if (e == hipSuccess) {
+        // padding columns of alpha hold -inf so they never win a row maximum
+        if (dtype == HAP_F32)
+            e = hap::launch_alpha_pad<float>((float *)c->A, (int64_t)c->L * n, (int)n, c->ldw, st);
+        else
+            e = hap::launch_alpha_pad<double>((double *)c->A, (int64_t)c->L * n, (int)n, c->ldw, st);
+    }
+    if (e != hipSuccess) return bail(e, "hap_init: clear workspace");
+
+    const size_t vecb = (size_t)c->ldw * esz;
+    if (p->pref_mode == HAP_PREF_MEDIAN) {
+        e = hap::launch_median_offdiag(S, n, lds, dtype, c->select_scratch, c->dbl, st);
+        if (e == hipSuccess) e = hap::launch_fill_pref(c->pref, c->ldw, (int)n, c->L, dtype, c->dbl, st);
+    } else if (p->pref_mode == HAP_PREF_SCALAR) {
+        for (int l = 0; l < c->L && e == hipSuccess; ++l) {
+            e = hipMemcpyAsync(c->dbl + 1 + (l % 2), &p->pref_scalar[l], sizeof(double), hipMemcpyHostToDevice, st);
+            if (e == hipSuccess)
+                e = hap::launch_fill_pref(c->pref + vecb * l, c->ldw, (int)n, 1, dtype, c->dbl + 1 + (l % 2), st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+        }
+    } else {
+        for (int l = 0; l < c->L && e == hipSuccess; ++l)
+            e = hipMemcpyAsync(c->pref + vecb * l, (const char *)p->pref_vec + (size_t)n * esz * l, (size_t)n * esz,
+                               hipMemcpyDeviceToDevice, st);
+    }
+    if (e != hipSuccess) return bail(e, "hap_init: preferences");
+    e = hipGetLastError();
+    if (e != hipSuccess) return bail(e, "hap_init: launch");
+    *out = c;
+    return HAP_OK;
+}
+
+hap_status hap_iterate(hap_ctx *c, int32_t max_iters, int32_t stable_iters, int32_t *iters_done, int32_t *converged) {
+    if (!c) return fail_arg("hap_iterate: null context");
+    if (c->failed) return fail_arg("hap_iterate: context failed earlier", HAP_E_STATE);
+    if (max_iters < 0 || stable_iters < 0) return fail_arg("hap_iterate: negative count");
+    DevState hs;
+    // a previous early stop does not block continuing: clear the flag
+    HIP_TRY(hipMemsetAsync(&c->ds->done, 0, sizeof(int32_t), c->stream), c);
+    const int chunk = 16;
+    int left = max_iters;
+    bool stopped = false;
+    while (left > 0) {
+        const int now = left < chunk ? left : chunk;
+        hap_status s = (c->dtype == HAP_F32) ? run_sweeps<float>(c, now, stable_iters)
+                                             : run_sweeps<double>(c, now, stable_iters);
+        if (s != HAP_OK) return s;
+        left -= now;
+        if (c->prof) {
+            HIP_TRY(hipStreamSynchronize(c->stream), c);
+            HIP_TRY(prof_collect(c), c);
+        }
+        if (stable_iters > 0) {
+            HIP_TRY(hipMemcpyAsync(&hs, c->ds, sizeof(DevState), hipMemcpyDeviceToHost, c->stream), c);
+            HIP_TRY(hipStreamSynchronize(c->stream), c);
+            if (hs.done) {
+                stopped = true;
+                break;
+            }
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(&hs, c->ds, sizeof(DevState), hipMemcpyDeviceToHost, c->stream), c);
+    HIP_TRY(hipStreamSynchronize(c->stream), c);
+    c->t_host = hs.t;
+    int conv = 0, done_iter = hs.t;
+    if (stopped || hs.done) {
+        // labels of the stop iteration are the last ones the row pass recorded
+        HIP_TRY(hipMemcpyAsync(c->Efinal, c->E, (size_t)c->ldw * 4 * c->L, hipMemcpyDeviceToDevice, c->stream), c);
+        conv = 1;
+        done_iter = hs.stop_iter;
+    } else {
+        hap_status s = (c->dtype == HAP_F32) ? finalize_labels<float>(c) : finalize_labels<double>(c);
+        if (s != HAP_OK) return s;
+        HIP_TRY(hipMemcpyAsync(&hs, c->ds, sizeof(DevState), hipMemcpyDeviceToHost, c->stream), c);
+        HIP_TRY(hipStreamSynchronize(c->stream), c);
+        if (stable_iters > 0 && c->t_host >= 2) {
+            // stable count after comparing e^t with e^{t-1}; hs.stable is the count after iteration t-1
+            const int st_after = hs.final_changed ? 0 : hs.stable + 1;
+            conv = st_after >= stable_iters ? 1 : 0;
+        }
+    }
+    c->labels_ready = true;
+    if (iters_done) *iters_done = done_iter;
+    if (converged) *converged = conv;
+    return HAP_OK;
+}
+
+hap_status hap_exemplars(hap_ctx *c, int32_t level, int32_t *labels, int32_t *n_exemplars) {
+    if (!c) return fail_arg("hap_exemplars: null context");
+    if (level < 0 || level >= c->L) return fail_arg("hap_exemplars: level out of range");
+    if (c->failed) return fail_arg("hap_exemplars: context failed earlier", HAP_E_STATE);
+    if (!c->labels_ready) {
+        hap_status s = (c->dtype == HAP_F32) ? finalize_labels<float>(c) : finalize_labels<double>(c);
+        if (s != HAP_OK) return s;
+        c->labels_ready = true;
+    }
+    const int32_t *src = c->Efinal + (size_t)c->ldw * level;
+    if (labels) HIP_TRY(hipMemcpyAsync(labels, src, (size_t)c->n * 4, hipMemcpyDeviceToDevice, c->stream), c);
+    if (n_exemplars) {
+        HIP_TRY(hap::launch_count_distinct(src, (int)c->n, c->mark, c->count, c->stream), c);
+        HIP_TRY(hipMemcpyAsync(n_exemplars, c->count, 4, hipMemcpyDeviceToHost, c->stream), c);
+        HIP_TRY(hipStreamSynchronize(c->stream), c);
+    }
+    return HAP_OK;
+}
+
+hap_status hap_net_similarity(hap_ctx *c, int32_t level, const void *X, int64_t d, int64_t ldx, int32_t x_dtype,
+                              double *out) {
+    if (!c || !out) return fail_arg("hap_net_similarity: null pointer");
+    if (level < -1 || level >= c->L) return fail_arg("hap_net_similarity: level out of range");
+    if (X && (d < 1 || ldx < d || !dtype_ok(x_dtype))) return fail_arg("hap_net_similarity: bad X");
+    if (c->failed) return fail_arg("hap_net_similarity: context failed earlier", HAP_E_STATE);
+    if (!c->labels_ready) {
+        hap_status s = (c->dtype == HAP_F32) ? finalize_labels<float>(c) : finalize_labels<double>(c);
+        if (s != HAP_OK) return s;
+        c->labels_ready = true;
+    }
+    double *dev = c->dbl + 1;
+    HIP_TRY(hap::launch_net_similarity(c->S, c->lds, c->dtype, c->pref, c->ldw, c->Efinal, (int)c->n, c->L, X, d,
+                                       ldx, x_dtype, dev, c->stream),
+            c);
+    const int slot = level < 0 ? c->L : level;
+    HIP_TRY(hipMemcpyAsync(out, dev + slot, sizeof(double), hipMemcpyDeviceToHost, c->stream), c);
+    HIP_TRY(hipStreamSynchronize(c->stream), c);
+    return HAP_OK;
+}
+
+hap_status hap_preference(hap_ctx *c, double *out) {
+    if (!c || !out) return fail_arg("hap_preference: null pointer");
+    for (int l = 0; l < c->L; ++l) {
+        const char *src = c->pref + (size_t)c->ldw * c->esz * l;
+        if (c->dtype == HAP_F32) {
+            float f;
+            HIP_TRY(hipMemcpyAsync(&f, src, 4, hipMemcpyDeviceToHost, c->stream), c);
+            HIP_TRY(hipStreamSynchronize(c->stream), c);
+            out[l] = f;
+        } else {
+            HIP_TRY(hipMemcpyAsync(&out[l], src, 8, hipMemcpyDeviceToHost, c->stream), c);
+            HIP_TRY(hipStreamSynchronize(c->stream), c);
+        }
+    }
+    return HAP_OK;
+}
+
+hap_status hap_read_messages(hap_ctx *c, int32_t level, void *rho, void *alpha, int64_t ld, void *cvec, void *phi,
+                             void *tau) {
+    if (!c) return fail_arg("hap_read_messages: null context");
+    if (level < 0 || level >= c->L) return fail_arg("hap_read_messages: level out of range");
+    if ((rho || alpha) && ld < c->n) return fail_arg("hap_read_messages: ld < n");
+    if (c->failed) return fail_arg("hap_read_messages: context failed earlier", HAP_E_STATE);
+    const size_t esz = c->esz;
+    hipStream_t st = c->stream;
+    if (rho) {
+        const char *src = c->R + (size_t)c->n * c->ldw * esz * level;
+        HIP_TRY(hipMemcpy2DAsync(rho, (size_t)ld * esz, src, (size_t)c->ldw * esz, (size_t)c->n * esz, (size_t)c->n,
+                                 hipMemcpyDeviceToDevice, st),
+                c);
+    }
+    // alpha^{l,t} and c^l = max_j(alpha + rho) of the top level are not part of the method's state
+    // (c is unused there); c of the top level is reported as 0.
+    const bool top = level == c->L - 1;
+    if (alpha || (cvec && !top)) {
+        if (c->dtype == HAP_F32) {
+            LevelPtrs<float> lv = level_ptrs<float>(c, level);
+            HIP_TRY(hap::launch_finalize<float>((const float *)c->S, c->lds, lv, (int)c->n, c->ldw, level, c->L, c->lam,
+                                                c->t_host, c->lc, nullptr, (float *)alpha, ld,
+                                                top ? nullptr : (float *)cvec, nullptr, c->ds, st),
+                    c);
+        } else {
+            LevelPtrs<double> lv = level_ptrs<double>(c, level);
+            HIP_TRY(hap::launch_finalize<double>((const double *)c->S, c->lds, lv, (int)c->n, c->ldw, level, c->L,
+                                                 c->lam, c->t_host, c->lc, nullptr, (double *)alpha, ld,
+                                                 top ? nullptr : (double *)cvec, nullptr, c->ds, st),
+                    c);
+        }
+    }
+    if (cvec && top) HIP_TRY(hipMemsetAsync(cvec, 0, (size_t)c->n * esz, st), c);
+    if (cvec && c->t_host == 0) HIP_TRY(hipMemsetAsync(cvec, 0, (size_t)c->n * esz, st), c);
+    if (phi) {
+        // phi^l after iteration t is max_k(alpha^{l+1,t}_ik + s_ik); 0 at the top level and before iteration 1
+        if (top || c->t_host == 0) {
+            HIP_TRY(hipMemsetAsync(phi, 0, (size_t)c->n * esz, st), c);
+        } else if (c->dtype == HAP_F32) {
+            LevelPtrs<float> up = level_ptrs<float>(c, level + 1);
+            HIP_TRY(hap::launch_finalize<float>((const float *)c->S, c->lds, up, (int)c->n, c->ldw, level + 1, c->L,
+                                                c->lam, c->t_host, c->lc, nullptr, nullptr, 0, nullptr, (float *)phi,
+                                                c->ds, st),
+                    c);
+        } else {
+            LevelPtrs<double> up = level_ptrs<double>(c, level + 1);
+            HIP_TRY(hap::launch_finalize<double>((const double *)c->S, c->lds, up, (int)c->n, c->ldw, level + 1, c->L,
+                                                 c->lam, c->t_host, c->lc, nullptr, nullptr, 0, nullptr,
+                                                 (double *)phi, c->ds, st),
+                    c);
+        }
+    }
+    if (tau) {
+        if (level == 0 || c->t_host == 0) {
+            // tau^1 = +inf (and every tau before iteration 1)
+            const size_t cnt = (size_t)c->n;
+            if (c->dtype == HAP_F32) {
+                float *h = new float[cnt];
+                for (size_t k = 0; k < cnt; ++k) h[k] = INFINITY;
+                hipError_t e = hipMemcpyAsync(tau, h, cnt * 4, hipMemcpyHostToDevice, st);
+                if (e == hipSuccess) e = hipStreamSynchronize(st);
+                delete[] h;
+                if (e != hipSuccess) return fail_hip(e, "hap_read_messages: tau", c);
+            } else {
+                double *h = new double[cnt];
+                for (size_t k = 0; k < cnt; ++k) h[k] = INFINITY;
+                hipError_t e = hipMemcpyAsync(tau, h, cnt * 8, hipMemcpyHostToDevice, st);
+                if (e == hipSuccess) e = hipStreamSynchronize(st);
+                delete[] h;
+                if (e != hipSuccess) return fail_hip(e, "hap_read_messages: tau", c);
+            }
+        } else {
+            const char *src = c->tau + (size_t)c->ldw * esz * level;
+            HIP_TRY(hipMemcpyAsync(tau, src, (size_t)c->n * esz, hipMemcpyDeviceToDevice, st), c);
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(st), c);
+    return HAP_OK;
+}
+
+hap_status hap_set_launch(hap_ctx *c, int32_t threads, int32_t chunks, int32_t rows_per_block, int32_t flags) {
+    if (!c) return fail_arg("hap_set_launch: null context");
+    Launch lc = c->lc;
+    if (threads) lc.threads = threads;
+    if (chunks) lc.chunks = chunks;
+    if (rows_per_block) lc.rows_per_block = rows_per_block;
+    if (flags >= 0) lc.prefetch = (flags & HAP_LAUNCH_PREFETCH) != 0;
+    lc.ordered = (lc.rows_per_block == 1);
+    if (!launch_fits(lc, c->n, c->esz, c->nb_cap)) return fail_arg("hap_set_launch: shape does not fit this problem");
+    c->lc = lc;
+    return HAP_OK;
+}
+
+hap_status hap_get_launch(hap_ctx *c, int32_t *threads, int32_t *chunks, int32_t *rows_per_block, int32_t *flags) {
+    if (!c) return fail_arg("hap_get_launch: null context");
+    if (flags) *flags = c->lc.prefetch ? HAP_LAUNCH_PREFETCH : 0;
+    if (threads) *threads = c->lc.threads;
+    if (chunks) *chunks = c->lc.chunks;
+    if (rows_per_block) *rows_per_block = c->lc.rows_per_block;
+    return HAP_OK;
+}
+
+hap_status hap_profile(hap_ctx *c, int32_t enable) {
+    if (!c) return fail_arg("hap_profile: null context");
+    if (c->prof) {
+        HIP_TRY(hipStreamSynchronize(c->stream), c);
+        HIP_TRY(prof_collect(c), c);
+    }
+    if (enable) {
+        c->prof_ms[0] = c->prof_ms[1] = 0.0;
+        c->prof_n[0] = c->prof_n[1] = 0;
+    }
+    c->prof = enable != 0;
+    return HAP_OK;
+}
+
+hap_status hap_profile_read(hap_ctx *c, double *row_ms, int64_t *row_n, double *col_ms, int64_t *col_n) {
+    if (!c) return fail_arg("hap_profile_read: null context");
+    if (c->ev_used) {
+        HIP_TRY(hipStreamSynchronize(c->stream), c);
+        HIP_TRY(prof_collect(c), c);
+    }
+    if (row_ms) *row_ms = c->prof_ms[0];
+    if (row_n) *row_n = c->prof_n[0];
+    if (col_ms) *col_ms = c->prof_ms[1];
+    if (col_n) *col_n = c->prof_n[1];
+    return HAP_OK;
+}
+
+hap_status hap_destroy(hap_ctx *c) {
+    if (!c) return HAP_OK;
+    hap_status s = HAP_OK;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) s = fail_hip(e, "hap_destroy: synchronize");
+    for (hipEvent_t ev : c->ev) (void)hipEventDestroy(ev);
+    if (c->own_ws) {
+        e = hipFree(c->ws);
+        if (e != hipSuccess && s == HAP_OK) s = fail_hip(e, "hap_destroy: hipFree");
+    }
+    delete c;
+    return s;
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// Internal declarations shared by the libhap HIP sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/hap.h"
+
+namespace hap {
+
+// Device-resident iteration state.  Kernels read the iteration counter from here
+// (not from a launch argument) so that a captured sweep can be replayed.
+struct DevState {
+    int32_t t;              // completed iterations (sweeps)
+    int32_t stable;         // consecutive iterations with unchanged labels (as of label iteration t-1)
+    int32_t done;           // 1 once the stable count reached K: later sweeps do nothing
+    int32_t stop_iter;      // iteration at which the run stopped
+    int32_t changed;        // set by the row pass when any label changed in the current sweep
+    int32_t final_changed;  // set by the finalize pass when e^t differs from e^{t-1}
+    int32_t pad[2];
+};
+
+// 16-byte vectors: 4 floats or 2 doubles per lane access.
+template <typename T> struct Vec;
+template <> struct Vec<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+    static constexpr int N = 4;
+};
+template <> struct Vec<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+    static constexpr int N = 2;
+};
+
+template <typename T> __device__ __forceinline__ T neg_inf();
+template <> __device__ __forceinline__ float neg_inf<float>() { return -__builtin_huge_valf(); }
+template <> __device__ __forceinline__ double neg_inf<double>() { return -__builtin_huge_val(); }
+template <typename T> __device__ __forceinline__ T pos_inf() { return -neg_inf<T>(); }
+
+// Launch shape of the row pass.
+struct Launch {
+    int threads;        // threads per workgroup (one row at a time per workgroup)
+    int chunks;         // 16-byte column chunks per thread
+    int rows_per_block; // rows handled by one workgroup (column partials are per workgroup)
+    bool ordered;       // column partials summed strictly in workgroup order
+    bool prefetch;      // load the next row before reducing the current one
+};
+
+// Pointers of one level inside the workspace.
+template <typename T>
+struct LevelPtrs {
+    T *R, *A;          // n x ldw
+    T *pref;           // [ldw]
+    T *Q;              // [ldw] column sums of the last sweep
+    T *phi;            // [ldw] phi^l (sent down by level l+1)
+    T *tau;            // [ldw] tau^l (sent up by level l-1); unused at l = 0
+    T *C;              // [2][ldw] cluster preference, ping-pong by iteration parity
+    int32_t *E;        // [ldw] labels of the last label pass
+    int32_t *Efinal;   // [ldw] labels reported by hap_exemplars
+};
+
+// Host launchers (defined in the .hip files).
+template <typename T>
+hipError_t launch_sweep_level(const T *S, int64_t lds, const LevelPtrs<T> &lv, T *phi_down,
+                              const T *tau_l, int n, int64_t ldw, int level, int levels, double lam,
+                              T *Qpart, const Launch &lc, DevState *ds, hipStream_t st);
+template <typename T>
+hipError_t launch_colsum(const T *Qpart, int64_t ldw, int nb, int n, const LevelPtrs<T> &lv,
+                         T *tau_next, bool last, int K, bool ordered, DevState *ds, hipStream_t st);
+template <typename T>
+hipError_t launch_finalize(const T *S, int64_t lds, const LevelPtrs<T> &lv, int n, int64_t ldw,
+                           int level, int levels, double lam, int t, const Launch &lc,
+                           int32_t *labels_out, T *alpha_out, int64_t lda, T *c_out, T *phi_out,
+                           DevState *ds, hipStream_t st);
+bool launch_supported(int threads, int chunks, int elem_size);
+template <typename T>
+hipError_t launch_alpha_pad(T *A, int64_t rows, int n, int64_t ldw, hipStream_t st);
+
+hipError_t launch_count_distinct(const int32_t *labels, int n, int32_t *mark, int32_t *out, hipStream_t st);
+hipError_t launch_net_similarity(const void *S, int64_t lds, int dtype, const void *pref_base,
+                                 int64_t ldw, const int32_t *Efinal_base, int n, int levels,
+                                 const void *X, int64_t d, int64_t ldx, int x_dtype, double *out,
+                                 hipStream_t st);
+hipError_t launch_fill_pref(void *pref_base, int64_t ldw, int n, int levels, int dtype,
+                            const double *value_dev, hipStream_t st);
+
+// Radix select of the two middle off-diagonal order statistics; writes their FP64 mean,
+// rounded to the working type, to *median_dev (as double).
+size_t select_scratch_bytes();
+hipError_t launch_median_offdiag(const void *S, int64_t n, int64_t lds, int dtype, void *scratch,
+                                 double *median_dev, hipStream_t st);
+
+hipError_t launch_build(const void *X, int64_t n, int64_t d, int64_t ldx, int x_dtype, void *S,
+                        int64_t lds, int s_dtype, int mode, double noise_rel, uint64_t seed,
+                        hipStream_t st);
+
+void set_error(const std::string &msg);
+
+}  // namespace hap

@@ -1,0 +1,285 @@
+"""ctypes binding of libhap (include/hap.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+torch supplies device memory (tensors) and the stream (torch's current stream).
+The library must have been built (``python -m paper_1403_7394_amd.build``);
+``load()`` raises if it is missing, and nothing here falls back to another path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhap.so")
+
+HAP_OK, HAP_E_ARG, HAP_E_DTYPE, HAP_E_OOM, HAP_E_HIP, HAP_E_STATE, HAP_E_UNSUPPORTED = range(7)
+HAP_F32, HAP_F64 = 0, 1
+BUILD_DIRECT, BUILD_GEMM, BUILD_BF16, BUILD_BF16X3 = 0, 1, 2, 3
+PREF_MEDIAN, PREF_SCALAR, PREF_VECTOR = 0, 1, 2
+LAUNCH_PREFETCH = 1
+
+# every symbol include/hap.h declares
+EXPORTS = (
+    "hap_version", "hap_status_string", "hap_last_error", "hap_build_similarity",
+    "hap_median_offdiag", "hap_workspace_size", "hap_init", "hap_iterate", "hap_exemplars",
+    "hap_net_similarity", "hap_preference", "hap_read_messages", "hap_set_launch",
+    "hap_get_launch", "hap_profile", "hap_profile_read", "hap_destroy",
+)
+
+
+class HapError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__(f"{fn} failed with status {status}: {msg}")
+        self.status = status
+
+
+class hap_params(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("levels", ctypes.c_int32),
+        ("damping", ctypes.c_double),
+        ("pref_mode", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("pref_scalar", ctypes.POINTER(ctypes.c_double)),
+        ("pref_vec", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+_c_i32p = ctypes.POINTER(ctypes.c_int32)
+_c_dblp = ctypes.POINTER(ctypes.c_double)
+
+
+def _declare(lib):
+    V, I32, I64, U64, D, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t
+    sig = {
+        "hap_version": (ctypes.c_char_p, []),
+        "hap_status_string": (ctypes.c_char_p, [I32]),
+        "hap_last_error": (ctypes.c_char_p, []),
+        "hap_build_similarity": (I32, [V, I64, I64, I64, I32, V, I64, I32, I32, D, U64, V]),
+        "hap_median_offdiag": (I32, [V, I64, I64, I32, _c_dblp, V]),
+        "hap_workspace_size": (I32, [I64, I32, I32, ctypes.POINTER(SZ)]),
+        "hap_init": (I32, [ctypes.POINTER(V), V, I64, I64, I32, ctypes.POINTER(hap_params), V, SZ, V]),
+        "hap_iterate": (I32, [V, I32, I32, _c_i32p, _c_i32p]),
+        "hap_exemplars": (I32, [V, I32, V, _c_i32p]),
+        "hap_net_similarity": (I32, [V, I32, V, I64, I64, I32, _c_dblp]),
+        "hap_preference": (I32, [V, _c_dblp]),
+        "hap_read_messages": (I32, [V, I32, V, V, I64, V, V, V]),
+        "hap_set_launch": (I32, [V, I32, I32, I32, I32]),
+        "hap_get_launch": (I32, [V, _c_i32p, _c_i32p, _c_i32p, _c_i32p]),
+        "hap_profile": (I32, [V, I32]),
+        "hap_profile_read": (I32, [V, _c_dblp, ctypes.POINTER(I64), _c_dblp, ctypes.POINTER(I64)]),
+        "hap_destroy": (I32, [V]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+
+
+def load(path: str | None = None):
+    """Load libhap.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"libhap not built: {p} is missing (run python -m paper_1403_7394_amd.build)")
+    lib = ctypes.CDLL(p)
+    _declare(lib)
+    _lib = lib
+    return lib
+
+
+def _check(fn, status):
+    if status != HAP_OK:
+        msg = _lib.hap_last_error().decode(errors="replace")
+        raise HapError(fn, status, msg)
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float32:
+        return HAP_F32
+    if t.dtype == torch.float64:
+        return HAP_F64
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _stream(stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ld(t):
+    """Leading dimension (elements) of a row-major 2-D tensor view."""
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("expected a row-major 2-D tensor")
+    return t.stride(0)
+
+
+def version() -> str:
+    return load().hap_version().decode()
+
+
+def build_similarity(X, S, mode: int = BUILD_DIRECT, noise_rel: float = 0.0, seed: int = 0, stream=None):
+    """S[:n, :n] <- -||x_i - x_j||^2 (see hap_build_similarity)."""
+    lib = load()
+    n, d = X.shape
+    _check("hap_build_similarity", lib.hap_build_similarity(
+        ctypes.c_void_p(X.data_ptr()), n, d, _ld(X), _dtype_code(X), ctypes.c_void_p(S.data_ptr()), _ld(S),
+        _dtype_code(S), mode, float(noise_rel), ctypes.c_uint64(seed & ((1 << 64) - 1)), _stream(stream)))
+    return S
+
+
+def median_offdiag(S, stream=None) -> float:
+    lib = load()
+    out = ctypes.c_double()
+    _check("hap_median_offdiag", lib.hap_median_offdiag(
+        ctypes.c_void_p(S.data_ptr()), S.shape[0], _ld(S), _dtype_code(S), ctypes.byref(out), _stream(stream)))
+    return out.value
+
+
+def workspace_size(n: int, levels: int, dtype_code: int) -> int:
+    lib = load()
+    b = ctypes.c_size_t()
+    _check("hap_workspace_size", lib.hap_workspace_size(n, levels, dtype_code, ctypes.byref(b)))
+    return b.value
+
+
+@dataclass
+class IterResult:
+    iters: int
+    converged: bool
+
+
+class Hap:
+    """One HAP problem on the GPU (wraps a hap_ctx).  S must outlive this object."""
+
+    def __init__(self, S, levels: int, damping: float, pref=None, workspace=None, stream=None):
+        import torch
+        lib = load()
+        self._lib = lib
+        self.S = S                      # keep the borrowed similarity alive
+        self.n = S.shape[0]
+        self.levels = levels
+        self.dtype = S.dtype
+        self._stream_obj = stream if stream is not None else torch.cuda.current_stream()
+        p = hap_params()
+        p.struct_size = ctypes.sizeof(hap_params)
+        p.levels = levels
+        p.damping = float(damping)
+        self._pref_keep = None
+        if pref is None:
+            p.pref_mode = PREF_MEDIAN
+        elif isinstance(pref, torch.Tensor):
+            if pref.dim() == 1:
+                pref = pref.reshape(1, -1).expand(levels, -1)
+            pref = pref.to(device=S.device, dtype=S.dtype).contiguous()
+            self._pref_keep = pref
+            p.pref_mode = PREF_VECTOR
+            p.pref_vec = ctypes.c_void_p(pref.data_ptr())
+        else:
+            vals = [float(pref)] * levels if not hasattr(pref, "__len__") else [float(v) for v in pref]
+            arr = (ctypes.c_double * levels)(*vals)
+            self._pref_keep = arr
+            p.pref_mode = PREF_SCALAR
+            p.pref_scalar = ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))
+        ws_ptr, ws_bytes = None, 0
+        if workspace is not None:
+            ws_ptr, ws_bytes = ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()
+            self._ws_keep = workspace
+        ctx = ctypes.c_void_p()
+        _check("hap_init", lib.hap_init(ctypes.byref(ctx), ctypes.c_void_p(S.data_ptr()), self.n, _ld(S),
+                                        _dtype_code(S), ctypes.byref(p), ws_ptr, ws_bytes,
+                                        ctypes.c_void_p(self._stream_obj.cuda_stream)))
+        self._ctx = ctx
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            _check("hap_destroy", self._lib.hap_destroy(self._ctx))
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def iterate(self, max_iters: int, stable_iters: int = 0) -> IterResult:
+        it, cv = ctypes.c_int32(), ctypes.c_int32()
+        _check("hap_iterate", self._lib.hap_iterate(self._ctx, max_iters, stable_iters, ctypes.byref(it), ctypes.byref(cv)))
+        return IterResult(it.value, bool(cv.value))
+
+    def exemplars(self, level: int, out=None):
+        """(labels tensor int32 [n] on the device, number of distinct exemplars)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.int32, device=self.S.device)
+        k = ctypes.c_int32()
+        _check("hap_exemplars", self._lib.hap_exemplars(self._ctx, level, ctypes.c_void_p(out.data_ptr()), ctypes.byref(k)))
+        return out, k.value
+
+    def labels(self):
+        import torch
+        return torch.stack([self.exemplars(l)[0] for l in range(self.levels)])
+
+    def net_similarity(self, level: int = -1, X=None) -> float:
+        out = ctypes.c_double()
+        if X is None:
+            st = self._lib.hap_net_similarity(self._ctx, level, None, 0, 0, 0, ctypes.byref(out))
+        else:
+            st = self._lib.hap_net_similarity(self._ctx, level, ctypes.c_void_p(X.data_ptr()), X.shape[1], _ld(X),
+                                              _dtype_code(X), ctypes.byref(out))
+        _check("hap_net_similarity", st)
+        return out.value
+
+    def preference(self):
+        arr = (ctypes.c_double * self.levels)()
+        _check("hap_preference", self._lib.hap_preference(self._ctx, arr))
+        return list(arr)
+
+    def messages(self, level: int):
+        """dict of rho, alpha (n x n) and c, phi, tau (n) of `level` after the last sweep."""
+        import torch
+        dev = self.S.device
+        rho = torch.empty(self.n, self.n, dtype=self.dtype, device=dev)
+        alpha = torch.empty_like(rho)
+        c = torch.empty(self.n, dtype=self.dtype, device=dev)
+        phi = torch.empty_like(c)
+        tau = torch.empty_like(c)
+        P = lambda t: ctypes.c_void_p(t.data_ptr())
+        _check("hap_read_messages", self._lib.hap_read_messages(self._ctx, level, P(rho), P(alpha), self.n, P(c), P(phi), P(tau)))
+        return dict(rho=rho, alpha=alpha, c=c, phi=phi, tau=tau)
+
+    def set_launch(self, threads=0, chunks=0, rows_per_block=0, prefetch=None):
+        flags = -1 if prefetch is None else (LAUNCH_PREFETCH if prefetch else 0)
+        _check("hap_set_launch", self._lib.hap_set_launch(self._ctx, threads, chunks, rows_per_block, flags))
+
+    def profile(self, enable: bool):
+        _check("hap_profile", self._lib.hap_profile(self._ctx, 1 if enable else 0))
+
+    def profile_read(self):
+        """(row pass ms, row pass launches, column-sum ms, column-sum launches)."""
+        a, b, c, d = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
+        _check("hap_profile_read", self._lib.hap_profile_read(self._ctx, ctypes.byref(a), ctypes.byref(b),
+                                                              ctypes.byref(c), ctypes.byref(d)))
+        return a.value, b.value, c.value, d.value
+
+    def get_launch(self):
+        """(threads, chunks, rows_per_block, prefetch)."""
+        a, b, c, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check("hap_get_launch", self._lib.hap_get_launch(self._ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                                          ctypes.byref(f)))
+        return a.value, b.value, c.value, bool(f.value & LAUNCH_PREFETCH)

@@ -1,0 +1,102 @@
+"""The C-ABI library loads on a machine without a GPU and exports every symbol
+include/hap.h declares; argument checks that need no device answer correctly."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1403_7394_amd import hap
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hap.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hap_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(hap.LIB_PATH):
+        pytest.fail("libhap.so is not built (run python -m paper_1403_7394_amd.build)")
+    return hap.load()
+
+
+def test_header_declares_the_binding_exports():
+    assert _declared_functions() == sorted(hap.EXPORTS)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [name for name in _declared_functions() if not hasattr(lib, name)]
+    assert not missing
+
+
+def test_version_and_status_strings(lib):
+    assert b"gfx950" in lib.hap_version()
+    assert lib.hap_status_string(hap.HAP_OK) == b"ok"
+    assert lib.hap_status_string(hap.HAP_E_ARG) == b"invalid argument"
+
+
+def test_workspace_size_checks_arguments(lib):
+    b = ctypes.c_size_t()
+    assert lib.hap_workspace_size(1, 3, hap.HAP_F32, ctypes.byref(b)) == hap.HAP_E_ARG
+    assert lib.hap_workspace_size(100, 0, hap.HAP_F32, ctypes.byref(b)) == hap.HAP_E_ARG
+    assert lib.hap_workspace_size(100, 3, 7, ctypes.byref(b)) == hap.HAP_E_DTYPE
+    assert lib.hap_workspace_size(100, 3, hap.HAP_F32, None) == hap.HAP_E_ARG
+    assert lib.hap_workspace_size(8192, 3, hap.HAP_F32, ctypes.byref(b)) == hap.HAP_OK
+    # two N x N message matrices per level dominate
+    assert b.value >= 2 * 3 * 8192 * 8192 * 4
+    assert b.value < 2 * 3 * 8192 * 8192 * 4 * 1.1
+
+
+def test_init_rejects_bad_arguments_without_touching_the_device(lib):
+    p = hap.hap_params()
+    p.struct_size = ctypes.sizeof(hap.hap_params)
+    p.levels = 3
+    p.damping = 0.5
+    p.pref_mode = hap.PREF_MEDIAN
+    ctx = ctypes.c_void_p()
+    fake = ctypes.c_void_p(4096)  # never dereferenced: every call below fails its checks first
+    assert lib.hap_init(None, fake, 10, 12, hap.HAP_F32, ctypes.byref(p), None, 0, None) == hap.HAP_E_ARG
+    assert lib.hap_init(ctypes.byref(ctx), fake, 1, 12, hap.HAP_F32, ctypes.byref(p), None, 0, None) == hap.HAP_E_ARG
+    assert lib.hap_init(ctypes.byref(ctx), fake, 10, 9, hap.HAP_F32, ctypes.byref(p), None, 0, None) == hap.HAP_E_ARG
+    assert lib.hap_init(ctypes.byref(ctx), fake, 10, 10, hap.HAP_F32, ctypes.byref(p), None, 0, None) == hap.HAP_E_ARG
+    assert lib.hap_init(ctypes.byref(ctx), fake, 10, 12, 5, ctypes.byref(p), None, 0, None) == hap.HAP_E_DTYPE
+    p.damping = 1.0
+    assert lib.hap_init(ctypes.byref(ctx), fake, 10, 12, hap.HAP_F32, ctypes.byref(p), None, 0, None) == hap.HAP_E_ARG
+    p.damping = 0.5
+    p.levels = 0
+    assert lib.hap_init(ctypes.byref(ctx), fake, 10, 12, hap.HAP_F32, ctypes.byref(p), None, 0, None) == hap.HAP_E_ARG
+    p.levels = 2
+    p.pref_mode = hap.PREF_SCALAR
+    bad = (ctypes.c_double * 2)(1.0, float("nan"))
+    p.pref_scalar = ctypes.cast(bad, ctypes.POINTER(ctypes.c_double))
+    assert lib.hap_init(ctypes.byref(ctx), fake, 10, 12, hap.HAP_F32, ctypes.byref(p), None, 0, None) == hap.HAP_E_ARG
+    assert b"non-finite" in lib.hap_last_error()
+    p.pref_mode = hap.PREF_MEDIAN
+    p.struct_size = 8
+    assert lib.hap_init(ctypes.byref(ctx), fake, 10, 12, hap.HAP_F32, ctypes.byref(p), None, 0, None) == hap.HAP_E_ARG
+    assert not ctx.value
+
+
+def test_null_context_calls_fail_cleanly(lib):
+    out = ctypes.c_int32()
+    assert lib.hap_iterate(None, 1, 0, ctypes.byref(out), None) == hap.HAP_E_ARG
+    assert lib.hap_exemplars(None, 0, None, None) == hap.HAP_E_ARG
+    assert lib.hap_destroy(None) == hap.HAP_OK
+    d = ctypes.c_double()
+    assert lib.hap_net_similarity(None, 0, None, 0, 0, 0, ctypes.byref(d)) == hap.HAP_E_ARG
+
+
+def test_build_and_median_check_arguments(lib):
+    fake = ctypes.c_void_p(4096)
+    assert lib.hap_build_similarity(None, 10, 2, 2, 0, fake, 12, 0, 0, 0.0, 0, None) == hap.HAP_E_ARG
+    assert lib.hap_build_similarity(fake, 10, 2, 1, 0, fake, 12, 0, 0, 0.0, 0, None) == hap.HAP_E_ARG
+    # noise is defined for FP64 output only
+    assert lib.hap_build_similarity(fake, 10, 2, 2, 0, fake, 12, 0, 0, 1e-12, 0, None) == hap.HAP_E_DTYPE
+    d = ctypes.c_double()
+    assert lib.hap_median_offdiag(fake, 1, 4, 0, ctypes.byref(d), None) == hap.HAP_E_ARG
+    assert lib.hap_median_offdiag(fake, 10, 10, 0, ctypes.byref(d), None) == hap.HAP_E_ARG
