@@ -79,6 +79,73 @@ def cpu_baseline(X, rp, sweeps: int = 2):
     }
 
 
+def run_precision_form(args, torch, hap, synth) -> dict:
+    """Precision form: the similarity of the 32768-point, 64-dimensional workload built four
+    ways (FP64-accumulated direct build = plain; FP32 GEMM, BF16 and BF16x3 on the matrix
+    cores), each followed by the same HAP run (L=4, damping 0.9, 300 iterations)."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    blobs, rp = synth.workload_precision()
+    n, d = blobs.X.shape
+    L = rp.levels
+    iters = args.form_iters if args.form_iters else rp.max_iters
+    X = torch.from_numpy(blobs.X).to(dev)
+    S = torch.empty((n, n), dtype=torch.float32, device=dev)
+    ws = torch.empty(hap.workspace_size(n, L, hap.HAP_F32), dtype=torch.uint8, device=dev)
+    rng = np.random.default_rng(7)
+    pi = rng.integers(0, n, size=1_000_000)
+    pj = rng.integers(0, n, size=1_000_000)
+    keep = pi != pj
+    pi, pj = pi[keep], pj[keep]
+    X64 = blobs.X.astype(np.float64)
+    ref = -np.sum((X64[pi] - X64[pj]) ** 2, axis=1)
+    same = blobs.truth[pi] == blobs.truth[pj]
+    pit, pjt = torch.from_numpy(pi).to(dev), torch.from_numpy(pj).to(dev)
+    modes = [("direct", hap.BUILD_DIRECT), ("gemm_f32", hap.BUILD_GEMM), ("bf16", hap.BUILD_BF16),
+             ("bf16x3", hap.BUILD_BF16X3)]
+    results = {}
+    base_labels = None
+    for name, mode in modes:
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        hap.build_similarity(X, S, mode=mode)
+        e1.record()
+        torch.cuda.synchronize()
+        build_ms = e0.elapsed_time(e1)
+        got = S[pit, pjt].double().cpu().numpy()
+        err = np.abs(got - ref)
+        t0 = time.perf_counter()
+        hap.build_similarity(X, S, mode=mode)
+        h = hap.Hap(S, L, rp.damping, workspace=ws)
+        h.iterate(iters, 0)
+        labels = h.labels()
+        counts = [h.exemplars(l)[1] for l in range(L)]
+        ns = [h.net_similarity(l, X=X) for l in range(L)]
+        torch.cuda.synchronize()
+        ttc = time.perf_counter() - t0
+        h.close()
+        if base_labels is None:
+            base_labels, base_ns = labels, ns
+        agree = [(labels[l] == base_labels[l]).float().mean().item() for l in range(L)]
+        flops = 2.0 * n * n * d * (3 if mode == hap.BUILD_BF16X3 else 1)
+        results[name] = {
+            "build_ms": build_ms,
+            "build_write_GBs": n * n * 4 / (build_ms * 1e-3) / 1e9,
+            "build_TFLOPs": flops / (build_ms * 1e-3) / 1e12 if mode != hap.BUILD_DIRECT else None,
+            "S_max_abs_err": float(err.max()),
+            "S_max_rel_err": float((err / np.abs(ref)).max()),
+            "S_within_blob_max_rel_err": float((err[same] / np.abs(ref[same])).max()) if same.any() else None,
+            "time_to_converge_s": ttc,
+            "label_agreement_vs_direct": agree,
+            "net_similarity_rel_diff_vs_direct": [abs(a - b) / abs(b) for a, b in zip(ns, base_ns)],
+            "exemplars_per_level": counts,
+        }
+        print(json.dumps({"form": "precision", "mode": name, **results[name]}), file=sys.stderr, flush=True)
+    return {"form": "precision", "workload": "32768 points, d=64, 256 blobs, FP32, L=4, damping 0.9, "
+            f"{iters} iterations", "n": n, "d": d, "results": results}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +155,9 @@ def main() -> int:
     ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration under rocprofv3)")
+    ap.add_argument("--form", choices=["plain", "precision"], default="plain",
+                    help="plain: the headline line; precision: the similarity build forms")
+    ap.add_argument("--form-iters", type=int, default=0, help="iterations for a form run (0 = the workload's)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -104,6 +174,9 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     hap.load()
+    if args.form == "precision":
+        print(json.dumps(run_precision_form(args, torch, hap, synth)), flush=True)
+        return 0
     dev = torch.device("cuda:0")
     blobs, rp = synth.workload_plain_f32()
     n = blobs.X.shape[0]
@@ -200,7 +273,8 @@ def main() -> int:
         "colsum_avg_us": col_ms / max(col_n, 1) * 1e3,
         "exemplars_per_level": counts,
         "net_similarity": ns,
-        "launch": {"threads": launch[0], "chunks": launch[1], "rows_per_block": launch[2], "prefetch": launch[3]},
+        "launch": {"threads": launch[0], "chunks": launch[1], "rows_per_block": launch[2],
+                   "streaming": launch[3]},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(blobs.X, rp, args.cpu_sweeps)

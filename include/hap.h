@@ -182,12 +182,14 @@ HAP_API hap_status hap_read_messages(hap_ctx *ctx, int32_t level, void *rho, voi
  * 16-byte column chunks per thread (1, 2, 4 or 8; 4 needs <= 512 threads, 8 needs
  * <= 256) and rows per workgroup (>= 1; 1 sums the column partials in row
  * order).  threads * chunks * (16 / element size) must cover n.  0 keeps the
- * library's choice for that field.  flags: HAP_LAUNCH_PREFETCH loads the next
- * row while the current one is reduced; -1 keeps the current flags.  Returns
- * HAP_E_ARG (and changes nothing) for a shape that does not fit.  For the
- * autotuner.
+ * library's choice for that field.  flags: HAP_LAUNCH_STREAM selects the
+ * streaming row pass for long rows (1024 threads, 1 to 16 chunks; the row is
+ * read again from the caches in its second phase); 0 selects the
+ * register-resident row pass; -1 keeps the current choice.
+ * Returns HAP_E_ARG (and changes nothing) for a shape that does not fit.  For
+ * the autotuner.
  */
-enum { HAP_LAUNCH_PREFETCH = 1 };
+enum { HAP_LAUNCH_STREAM = 2 };
 HAP_API hap_status hap_set_launch(hap_ctx *ctx, int32_t threads, int32_t chunks, int32_t rows_per_block,
                                   int32_t flags);
 HAP_API hap_status hap_get_launch(hap_ctx *ctx, int32_t *threads, int32_t *chunks, int32_t *rows_per_block,

@@ -1,4 +1,5 @@
-// Similarity build S = -||x_i - x_j||^2 (Section 2) for gfx950.
+// Similarity build S = -||x_i - x_j||^2 (Section 2) for gfx950: a direct FP64-accumulated
+// form on the vector ALUs and Gram-matrix forms on the matrix cores (MFMA).
 //
 // HAP_BUILD_DIRECT: sum over coordinates of (x_ik - x_jk)^2, accumulated in FP64
 // in coordinate order with separate multiply and add roundings (no contraction),
@@ -89,21 +90,283 @@ __global__ __launch_bounds__(256) void build_direct_kernel(const TX *__restrict_
     }
 }
 
+// ---------------------------------------------------------------------------
+// Gram-matrix builds on MFMA: S_ij = min(0, -((n_i + n_j) - 2 g_ij)), g = X X^T, S_ii = 0.
+// n_i is the squared norm of the operand the matrix cores see (x itself for FP32/FP64,
+// bf16(x) for BF16, hi + lo for BF16x3), summed in FP64, so that the diagonal cancels.
+// The clamp keeps S <= 0 where cancellation leaves a tiny positive value.
+//
+// One 256-thread workgroup owns a 128 x 128 tile of S; each wavefront a 64 x 64 quarter
+// as 4 x 4 blocks of 16 x 16 MFMA outputs (lane l, register r holds row 4*(l/16) + r,
+// column l%16 of a block).  Both operands are rows of X: the A fragment of a lane is
+// row (l%16) of the row block, the B fragment row (l%16) of the column block, with the
+// same k slots, so the k order inside a fragment does not matter.
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// float -> bf16, round to nearest even (finite inputs)
+__device__ __forceinline__ __bf16 to_bf16(float x) {
+    unsigned int u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    const unsigned short h = (unsigned short)(u >> 16);
+    return __builtin_bit_cast(__bf16, h);
+}
+__device__ __forceinline__ float from_bf16(__bf16 h) {
+    return __uint_as_float(((unsigned int)__builtin_bit_cast(unsigned short, h)) << 16);
+}
+
+enum { kModeF32 = 0, kModeBF16 = 1, kModeBF16x3 = 2 };
+
+template <int MODE>
+__global__ __launch_bounds__(256) void norms_kernel(const float *__restrict__ X, int n, int d, int64_t ldx,
+                                                    float *__restrict__ out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int k = 0; k < d; ++k) {
+        const float x = X[(int64_t)i * ldx + k];
+        if (MODE == kModeF32) {
+            acc += (double)x * (double)x;
+        } else if (MODE == kModeBF16) {
+            const double h = (double)from_bf16(to_bf16(x));
+            acc += h * h;
+        } else {
+            const float hf = from_bf16(to_bf16(x));
+            const double h = (double)hf, lo = (double)from_bf16(to_bf16(x - hf));
+            acc += h * h + 2.0 * h * lo;   // what hi.hi + hi.lo + lo.hi gives on the diagonal
+        }
+    }
+    out[i] = (float)acc;
+}
+
+__global__ __launch_bounds__(256) void norms_kernel_f64(const double *__restrict__ X, int n, int d, int64_t ldx,
+                                                        double *__restrict__ out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int k = 0; k < d; ++k) {
+        const double x = X[(int64_t)i * ldx + k];
+        acc += x * x;
+    }
+    out[i] = acc;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void build_mfma_f32_kernel(const float *__restrict__ X, int n, int d, int64_t ldx,
+                                                             const float *__restrict__ norms, float *__restrict__ S,
+                                                             int64_t lds) {
+#pragma clang fp contract(off)
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lg = lane >> 4;
+    const int i0 = blockIdx.y * 128 + (wave >> 1) * 64;
+    const int j0 = blockIdx.x * 128 + (wave & 1) * 64;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = (f32x4)(0.f);
+    // rows this lane feeds into the A and B fragments (clamped; results past n are not stored)
+    const float *ra[4], *rb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        ra[q] = X + (int64_t)min(i0 + 16 * q + lr, n - 1) * ldx;
+        rb[q] = X + (int64_t)min(j0 + 16 * q + lr, n - 1) * ldx;
+    }
+    if (MODE == kModeF32) {
+        for (int k0 = 0; k0 < d; k0 += 4) {
+            const int k = k0 + lg;
+            float fa[4], fb[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                fa[q] = k < d ? ra[q][k] : 0.f;
+                fb[q] = k < d ? rb[q][k] : 0.f;
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a], fb[b], acc[a][b], 0, 0, 0);
+        }
+    } else {
+        for (int k0 = 0; k0 < d; k0 += 32) {
+            const int kb = k0 + 8 * lg;
+            bf16x8 ha[4], hb[4], la[4], lb[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int k = kb + e;
+                    const float xa = k < d ? ra[q][k] : 0.f;
+                    const float xb = k < d ? rb[q][k] : 0.f;
+                    const __bf16 ya = to_bf16(xa), yb = to_bf16(xb);
+                    ha[q][e] = ya;
+                    hb[q][e] = yb;
+                    if (MODE == kModeBF16x3) {
+                        la[q][e] = to_bf16(xa - from_bf16(ya));
+                        lb[q][e] = to_bf16(xb - from_bf16(yb));
+                    }
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    if (MODE == kModeBF16x3) {
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(la[a], hb[b], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[a], lb[b], acc[a][b], 0, 0, 0);
+                    }
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[a], hb[b], acc[a][b], 0, 0, 0);
+                }
+        }
+    }
+    // Epilogue: form S in the MFMA layout into an LDS tile, then write the 128 x 128 tile
+    // row by row with 16-byte stores (each row segment is 512 contiguous bytes).
+    __shared__ float tile[128][128 + 4];
+    const int ti = (wave >> 1) * 64, tj = (wave & 1) * 64;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int il = ti + 16 * a + 4 * lg + r;
+            const int i = blockIdx.y * 128 + il;
+            const float ni = norms[min(i, n - 1)];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int jl = tj + 16 * b + lr;
+                const int j = blockIdx.x * 128 + jl;
+                const float v = -((ni + norms[min(j, n - 1)]) - 2.f * acc[a][b][r]);
+                tile[il][jl] = (i == j) ? 0.f : fminf(0.f, v);
+            }
+        }
+    }
+    __syncthreads();
+    const int col4 = (threadIdx.x & 31) * 4;
+    const int jg = blockIdx.x * 128 + col4;
+    const bool vec_ok = ((lds & 3) == 0) && ((((uintptr_t)S) & 15) == 0);
+    for (int rr = threadIdx.x >> 5; rr < 128; rr += 8) {
+        const int i = blockIdx.y * 128 + rr;
+        if (i >= n) break;
+        float *dst = S + (int64_t)i * lds + jg;
+        if (vec_ok && jg + 3 < n) {
+            f32x4 v;
+            v[0] = tile[rr][col4];
+            v[1] = tile[rr][col4 + 1];
+            v[2] = tile[rr][col4 + 2];
+            v[3] = tile[rr][col4 + 3];
+            *(f32x4 *)dst = v;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (jg + e < n) dst[e] = tile[rr][col4 + e];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void build_mfma_f64_kernel(const double *__restrict__ X, int n, int d, int64_t ldx,
+                                                             const double *__restrict__ norms, double *__restrict__ S,
+                                                             int64_t lds, double noise_rel, unsigned long long seed) {
+#pragma clang fp contract(off)
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lg = lane >> 4;
+    const int i0 = blockIdx.y * 128 + (wave >> 1) * 64;
+    const int j0 = blockIdx.x * 128 + (wave & 1) * 64;
+    f64x4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = (f64x4)(0.0);
+    const double *ra[4], *rb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        ra[q] = X + (int64_t)min(i0 + 16 * q + lr, n - 1) * ldx;
+        rb[q] = X + (int64_t)min(j0 + 16 * q + lr, n - 1) * ldx;
+    }
+    for (int k0 = 0; k0 < d; k0 += 4) {
+        const int k = k0 + lg;
+        double fa[4], fb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            fa[q] = k < d ? ra[q][k] : 0.0;
+            fb[q] = k < d ? rb[q][k] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+    }
+    // the FP64 16x16x4 output interleaves rows by register: lane l, register r holds row
+    // (l/16) + 4r, column l%16 of a block
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = i0 + 16 * a + lg + 4 * r;
+            if (i >= n) continue;
+            const double ni = norms[i];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int j = j0 + 16 * b + lr;
+                if (j >= n) continue;
+                double v = fmin(0.0, -((ni + norms[j]) - 2.0 * acc[a][b][r]));
+                if (i == j) {
+                    v = 0.0;
+                } else if (noise_rel > 0.0) {
+                    const unsigned long long ctr = (unsigned long long)i * (unsigned long long)n + (unsigned long long)j;
+                    const double u = (double)(splitmix64_first(seed ^ ctr) >> 11) * 0x1.0p-53;
+                    v = v + (noise_rel * fabs(v)) * u;
+                }
+                S[(int64_t)i * lds + j] = v;
+            }
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_build(const void *X, int64_t n, int64_t d, int64_t ldx, int x_dtype, void *S, int64_t lds,
                         int s_dtype, int mode, double noise_rel, uint64_t seed, hipStream_t st) {
-    if (mode != HAP_BUILD_DIRECT) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((n + kTile - 1) / kTile), (unsigned)((n + kTile - 1) / kTile));
-#define HAP_BD(TX, TS)                                                                                      \
-    hipLaunchKernelGGL((build_direct_kernel<TX, TS>), grid, dim3(256), 0, st, (const TX *)X, (int)n, (int)d, \
+    if (mode == HAP_BUILD_DIRECT) {
+        const dim3 grid((unsigned)((n + kTile - 1) / kTile), (unsigned)((n + kTile - 1) / kTile));
+#define HAP_BD(TX, TS)                                                                                          \
+    hipLaunchKernelGGL((build_direct_kernel<TX, TS>), grid, dim3(256), 0, st, (const TX *)X, (int)n, (int)d,    \
                        ldx, (TS *)S, lds, noise_rel, (unsigned long long)seed)
-    if (x_dtype == HAP_F32 && s_dtype == HAP_F32) HAP_BD(float, float);
-    else if (x_dtype == HAP_F32 && s_dtype == HAP_F64) HAP_BD(float, double);
-    else if (x_dtype == HAP_F64 && s_dtype == HAP_F32) HAP_BD(double, float);
-    else HAP_BD(double, double);
+        if (x_dtype == HAP_F32 && s_dtype == HAP_F32) HAP_BD(float, float);
+        else if (x_dtype == HAP_F32 && s_dtype == HAP_F64) HAP_BD(float, double);
+        else if (x_dtype == HAP_F64 && s_dtype == HAP_F32) HAP_BD(double, float);
+        else HAP_BD(double, double);
 #undef HAP_BD
-    return hipGetLastError();
+        return hipGetLastError();
+    }
+    // Gram-matrix builds: the squared norms go to a stream-ordered scratch allocation
+    const dim3 grid((unsigned)((n + 127) / 128), (unsigned)((n + 127) / 128));
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    void *norms = nullptr;
+    hipError_t e = hipMallocAsync(&norms, (size_t)n * 8, st);
+    if (e != hipSuccess) return e;
+    if (mode == HAP_BUILD_GEMM && s_dtype == HAP_F64) {
+        hipLaunchKernelGGL(norms_kernel_f64, dim3(nb), dim3(256), 0, st, (const double *)X, (int)n, (int)d, ldx,
+                           (double *)norms);
+        hipLaunchKernelGGL(build_mfma_f64_kernel, grid, dim3(256), 0, st, (const double *)X, (int)n, (int)d, ldx,
+                           (const double *)norms, (double *)S, lds, noise_rel, (unsigned long long)seed);
+    } else {
+#define HAP_BM(MODE)                                                                                            \
+    do {                                                                                                        \
+        hipLaunchKernelGGL((norms_kernel<MODE>), dim3(nb), dim3(256), 0, st, (const float *)X, (int)n, (int)d,  \
+                           ldx, (float *)norms);                                                                 \
+        hipLaunchKernelGGL((build_mfma_f32_kernel<MODE>), grid, dim3(256), 0, st, (const float *)X, (int)n,     \
+                           (int)d, ldx, (const float *)norms, (float *)S, lds);                                  \
+    } while (0)
+        if (mode == HAP_BUILD_GEMM) HAP_BM(kModeF32);
+        else if (mode == HAP_BUILD_BF16) HAP_BM(kModeBF16);
+        else HAP_BM(kModeBF16x3);
+#undef HAP_BM
+    }
+    e = hipGetLastError();
+    const hipError_t e2 = hipFreeAsync(norms, st);
+    return e != hipSuccess ? e : e2;
 }
 
 }  // namespace hap

@@ -38,7 +38,8 @@ struct hap_ctx {
     bool own_ws = false;
 
     // workspace regions
-    char *R = nullptr, *A = nullptr, *pref = nullptr, *Q = nullptr, *phi = nullptr, *tau = nullptr, *C = nullptr;
+    char *R = nullptr, *A = nullptr, *pref = nullptr, *Q = nullptr, *phi = nullptr, *tau = nullptr, *C = nullptr,
+         *B = nullptr;
     int32_t *E = nullptr, *Efinal = nullptr, *mark = nullptr, *count = nullptr;
     char *Qpart = nullptr;
     DevState *ds = nullptr;
@@ -65,7 +66,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-    size_t R, A, pref, Q, phi, tau, C, E, Efinal, mark, count, Qpart, ds, dbl, sel, total;
+    size_t R, A, pref, Q, phi, tau, C, B, E, Efinal, mark, count, Qpart, ds, dbl, sel, total;
     int64_t ldw;
     int nb_cap;
 };
@@ -88,7 +89,8 @@ Layout make_layout(int64_t n, int L, size_t esz) {
     lo.Q = take(vec * L);
     lo.phi = take(vec * L);
     lo.tau = take(vec * L);
-    lo.C = take(vec * 2 * L);
+    lo.C = take(vec * L);
+    lo.B = take(vec * L);
     lo.E = take((size_t)lo.ldw * 4 * L);
     lo.Efinal = take((size_t)lo.ldw * 4 * L);
     lo.mark = take((size_t)lo.ldw * 4);
@@ -129,7 +131,8 @@ LevelPtrs<T> level_ptrs(const hap_ctx *c, int l) {
     p.Q = (T *)c->Q + (size_t)c->ldw * l;
     p.phi = (T *)c->phi + (size_t)c->ldw * l;
     p.tau = (T *)c->tau + (size_t)c->ldw * l;
-    p.C = (T *)c->C + (size_t)c->ldw * 2 * l;
+    p.C = (T *)c->C + (size_t)c->ldw * l;
+    p.B = (T *)c->B + (size_t)c->ldw * l;
     p.E = c->E + (size_t)c->ldw * l;
     p.Efinal = c->Efinal + (size_t)c->ldw * l;
     return p;
@@ -145,15 +148,21 @@ Launch default_launch(int64_t n, size_t esz) {
         const int64_t need = (n + (int64_t)vw * nch - 1) / ((int64_t)vw * nch);
         int nt = 64;
         while (nt < need) nt <<= 1;
-        if (nt <= (nch == 8 ? 512 : 1024)) {
+        if (hap::launch_supported(nt, nch, (int)esz)) {
             lc.threads = nt;
             lc.chunks = nch;
             found = true;
         }
     }
     if (!found) {
-        lc.threads = 0;
-        return lc;
+        // rows too long for registers: stream them with 1024 threads and 2..16 chunks
+        lc.threads = 1024;
+        lc.streaming = true;
+        lc.chunks = (int)((n + 1024 * vw - 1) / (1024 * vw));
+        if (lc.chunks > 16) {
+            lc.threads = 0;
+            return lc;
+        }
     }
     // About 256 workgroups (one per CU) on large problems.  Small problems (FP32 up to 512
     // points, FP64 up to 2048) take one row per workgroup and sum the column partials in
@@ -167,8 +176,14 @@ Launch default_launch(int64_t n, size_t esz) {
 }
 
 bool launch_fits(const Launch &lc, int64_t n, size_t esz, int nb_cap) {
-    if (!hap::launch_supported(lc.threads, lc.chunks, (int)esz)) return false;
-    if ((int64_t)lc.threads * lc.chunks * (int64_t)(16 / esz) < n) return false;
+    const int64_t vw = (int64_t)(16 / esz);
+    if (lc.streaming) {
+        if (lc.threads != 1024) return false;
+        if (lc.chunks < 1 || lc.chunks > 16) return false;
+    } else if (!hap::launch_supported(lc.threads, lc.chunks, (int)esz)) {
+        return false;
+    }
+    if ((int64_t)lc.threads * lc.chunks * vw < n) return false;
     if (lc.rows_per_block < 1) return false;
     const int64_t nb = (n + lc.rows_per_block - 1) / lc.rows_per_block;
     return nb <= nb_cap;
@@ -223,17 +238,18 @@ hap_status run_sweeps(hap_ctx *c, int count, int K) {
     for (int it = 0; it < count; ++it) {
         for (int l = 0; l < L; ++l) {
             LevelPtrs<T> lv = level_ptrs<T>(c, l);
-            T *phi_down = l > 0 ? level_ptrs<T>(c, l - 1).phi : nullptr;
+            LevelPtrs<T> down = level_ptrs<T>(c, l > 0 ? l - 1 : 0);
+            T *phi_down = l > 0 ? down.phi : nullptr;
             const T *tau_l = l > 0 ? lv.tau : nullptr;
             HIP_TRY(prof_mark(c, 0, false), c);
-            HIP_TRY(hap::launch_sweep_level<T>((const T *)c->S, c->lds, lv, phi_down, tau_l, (int)c->n, c->ldw, l, L,
-                                               c->lam, Qpart, c->lc, c->ds, c->stream),
+            HIP_TRY(hap::launch_sweep_level<T>((const T *)c->S, c->lds, lv, phi_down, tau_l, (int)c->n, c->ldw, c->lam,
+                                               Qpart, c->lc, c->ds, c->stream),
                     c);
             HIP_TRY(prof_mark(c, 0, true), c);
             T *tau_next = (l + 1 < L) ? level_ptrs<T>(c, l + 1).tau : nullptr;
             HIP_TRY(prof_mark(c, 1, false), c);
-            HIP_TRY(hap::launch_colsum<T>(Qpart, c->ldw, nb, (int)c->n, lv, tau_next, l == L - 1, K, c->lc.ordered,
-                                          c->ds, c->stream),
+            HIP_TRY(hap::launch_colsum<T>(Qpart, c->ldw, nb, (int)c->n, lv, l > 0 ? &down : nullptr, tau_next,
+                                          l == L - 1, l == L - 1, K, c->lc.ordered, c->ds, c->stream),
                     c);
             HIP_TRY(prof_mark(c, 1, true), c);
         }
@@ -247,8 +263,8 @@ hap_status finalize_labels(hap_ctx *c) {
     HIP_TRY(hipMemsetAsync(&c->ds->final_changed, 0, sizeof(int32_t), c->stream), c);
     for (int l = 0; l < c->L; ++l) {
         LevelPtrs<T> lv = level_ptrs<T>(c, l);
-        HIP_TRY(hap::launch_finalize<T>((const T *)c->S, c->lds, lv, (int)c->n, c->ldw, l, c->L, c->lam, c->t_host,
-                                        c->lc, lv.Efinal, nullptr, 0, nullptr, nullptr, c->ds, c->stream),
+        HIP_TRY(hap::launch_finalize<T>((const T *)c->S, c->lds, lv, (int)c->n, c->ldw, c->lam, c->t_host, lv.Efinal,
+                                        nullptr, 0, nullptr, nullptr, c->ds, c->stream),
                 c);
     }
     return HAP_OK;
@@ -284,7 +300,14 @@ hap_status hap_build_similarity(const void *X, int64_t n, int64_t d, int64_t ldx
     if (!dtype_ok(x_dtype) || !dtype_ok(s_dtype)) return fail_arg("hap_build_similarity: dtype", HAP_E_DTYPE);
     if (!(noise_rel >= 0.0) || !std::isfinite(noise_rel)) return fail_arg("hap_build_similarity: noise_rel");
     if (noise_rel > 0.0 && s_dtype != HAP_F64) return fail_arg("hap_build_similarity: noise needs FP64 output", HAP_E_DTYPE);
-    if (build_mode != HAP_BUILD_DIRECT) return fail_arg("hap_build_similarity: build mode not available", HAP_E_UNSUPPORTED);
+    if (build_mode < HAP_BUILD_DIRECT || build_mode > HAP_BUILD_BF16X3)
+        return fail_arg("hap_build_similarity: unknown build mode");
+    if (build_mode == HAP_BUILD_GEMM && x_dtype != s_dtype)
+        return fail_arg("hap_build_similarity: the GEMM build needs X and S of the same type", HAP_E_DTYPE);
+    if ((build_mode == HAP_BUILD_BF16 || build_mode == HAP_BUILD_BF16X3) && (x_dtype != HAP_F32 || s_dtype != HAP_F32))
+        return fail_arg("hap_build_similarity: BF16 builds take FP32 X and give FP32 S", HAP_E_DTYPE);
+    if (noise_rel > 0.0 && (build_mode == HAP_BUILD_BF16 || build_mode == HAP_BUILD_BF16X3))
+        return fail_arg("hap_build_similarity: noise needs FP64 output", HAP_E_DTYPE);
     hipError_t e = hap::launch_build(X, n, d, ldx, x_dtype, S, lds, s_dtype, build_mode, noise_rel, seed,
                                      (hipStream_t)stream);
     if (e != hipSuccess) return fail_hip(e, "hap_build_similarity");
@@ -343,7 +366,7 @@ hap_status hap_init(hap_ctx **out, const void *S, int64_t n, int64_t lds, int32_
     Layout lo = make_layout(n, p->levels, esz);
     Launch lc = default_launch(n, esz);
     if (lc.threads == 0 || !launch_fits(lc, n, esz, lo.nb_cap))
-        return fail_arg("hap_init: n too large for the register-resident row pass", HAP_E_UNSUPPORTED);
+        return fail_arg("hap_init: n too large (at most 65536 points in FP32, 32768 in FP64)", HAP_E_UNSUPPORTED);
     if (workspace) {
         if (workspace_bytes < lo.total) return fail_arg("hap_init: workspace too small");
         if (((uintptr_t)workspace & (kAlign - 1)) != 0) return fail_arg("hap_init: workspace must be 256-byte aligned");
@@ -388,6 +411,7 @@ hap_status hap_init(hap_ctx **out, const void *S, int64_t n, int64_t lds, int32_
     c->phi = base + lo.phi;
     c->tau = base + lo.tau;
     c->C = base + lo.C;
+    c->B = base + lo.B;
     c->E = (int32_t *)(base + lo.E);
     c->Efinal = (int32_t *)(base + lo.Efinal);
     c->mark = (int32_t *)(base + lo.mark);
@@ -572,15 +596,15 @@ hap_status hap_read_messages(hap_ctx *c, int32_t level, void *rho, void *alpha, 
     if (alpha || (cvec && !top)) {
         if (c->dtype == HAP_F32) {
             LevelPtrs<float> lv = level_ptrs<float>(c, level);
-            HIP_TRY(hap::launch_finalize<float>((const float *)c->S, c->lds, lv, (int)c->n, c->ldw, level, c->L, c->lam,
-                                                c->t_host, c->lc, nullptr, (float *)alpha, ld,
-                                                top ? nullptr : (float *)cvec, nullptr, c->ds, st),
+            HIP_TRY(hap::launch_finalize<float>((const float *)c->S, c->lds, lv, (int)c->n, c->ldw, c->lam, c->t_host,
+                                                nullptr, (float *)alpha, ld, top ? nullptr : (float *)cvec, nullptr,
+                                                c->ds, st),
                     c);
         } else {
             LevelPtrs<double> lv = level_ptrs<double>(c, level);
-            HIP_TRY(hap::launch_finalize<double>((const double *)c->S, c->lds, lv, (int)c->n, c->ldw, level, c->L,
-                                                 c->lam, c->t_host, c->lc, nullptr, (double *)alpha, ld,
-                                                 top ? nullptr : (double *)cvec, nullptr, c->ds, st),
+            HIP_TRY(hap::launch_finalize<double>((const double *)c->S, c->lds, lv, (int)c->n, c->ldw, c->lam, c->t_host,
+                                                 nullptr, (double *)alpha, ld, top ? nullptr : (double *)cvec, nullptr,
+                                                 c->ds, st),
                     c);
         }
     }
@@ -592,15 +616,13 @@ hap_status hap_read_messages(hap_ctx *c, int32_t level, void *rho, void *alpha, 
             HIP_TRY(hipMemsetAsync(phi, 0, (size_t)c->n * esz, st), c);
         } else if (c->dtype == HAP_F32) {
             LevelPtrs<float> up = level_ptrs<float>(c, level + 1);
-            HIP_TRY(hap::launch_finalize<float>((const float *)c->S, c->lds, up, (int)c->n, c->ldw, level + 1, c->L,
-                                                c->lam, c->t_host, c->lc, nullptr, nullptr, 0, nullptr, (float *)phi,
-                                                c->ds, st),
+            HIP_TRY(hap::launch_finalize<float>((const float *)c->S, c->lds, up, (int)c->n, c->ldw, c->lam, c->t_host,
+                                                nullptr, nullptr, 0, nullptr, (float *)phi, c->ds, st),
                     c);
         } else {
             LevelPtrs<double> up = level_ptrs<double>(c, level + 1);
-            HIP_TRY(hap::launch_finalize<double>((const double *)c->S, c->lds, up, (int)c->n, c->ldw, level + 1, c->L,
-                                                 c->lam, c->t_host, c->lc, nullptr, nullptr, 0, nullptr,
-                                                 (double *)phi, c->ds, st),
+            HIP_TRY(hap::launch_finalize<double>((const double *)c->S, c->lds, up, (int)c->n, c->ldw, c->lam, c->t_host,
+                                                 nullptr, nullptr, 0, nullptr, (double *)phi, c->ds, st),
                     c);
         }
     }
@@ -638,7 +660,7 @@ hap_status hap_set_launch(hap_ctx *c, int32_t threads, int32_t chunks, int32_t r
     if (threads) lc.threads = threads;
     if (chunks) lc.chunks = chunks;
     if (rows_per_block) lc.rows_per_block = rows_per_block;
-    if (flags >= 0) lc.prefetch = (flags & HAP_LAUNCH_PREFETCH) != 0;
+    if (flags >= 0) lc.streaming = (flags & HAP_LAUNCH_STREAM) != 0;
     lc.ordered = (lc.rows_per_block == 1);
     if (!launch_fits(lc, c->n, c->esz, c->nb_cap)) return fail_arg("hap_set_launch: shape does not fit this problem");
     c->lc = lc;
@@ -647,7 +669,7 @@ hap_status hap_set_launch(hap_ctx *c, int32_t threads, int32_t chunks, int32_t r
 
 hap_status hap_get_launch(hap_ctx *c, int32_t *threads, int32_t *chunks, int32_t *rows_per_block, int32_t *flags) {
     if (!c) return fail_arg("hap_get_launch: null context");
-    if (flags) *flags = c->lc.prefetch ? HAP_LAUNCH_PREFETCH : 0;
+    if (flags) *flags = c->lc.streaming ? HAP_LAUNCH_STREAM : 0;
     if (threads) *threads = c->lc.threads;
     if (chunks) *chunks = c->lc.chunks;
     if (rows_per_block) *rows_per_block = c->lc.rows_per_block;

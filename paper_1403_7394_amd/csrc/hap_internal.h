@@ -44,7 +44,7 @@ struct Launch {
     int chunks;         // 16-byte column chunks per thread
     int rows_per_block; // rows handled by one workgroup (column partials are per workgroup)
     bool ordered;       // column partials summed strictly in workgroup order
-    bool prefetch;      // load the next row before reducing the current one
+    bool streaming;     // large rows: 1024 threads, phase 2 re-reads S and R (chunks 2..16)
 };
 
 // Pointers of one level inside the workspace.
@@ -55,7 +55,8 @@ struct LevelPtrs {
     T *Q;              // [ldw] column sums of the last sweep
     T *phi;            // [ldw] phi^l (sent down by level l+1)
     T *tau;            // [ldw] tau^l (sent up by level l-1); unused at l = 0
-    T *C;              // [2][ldw] cluster preference, ping-pong by iteration parity
+    T *C;              // [ldw] cluster preference c^l
+    T *B;              // [ldw] availability base c + phi + Q (Q at the top level) of the last sweep
     int32_t *E;        // [ldw] labels of the last label pass
     int32_t *Efinal;   // [ldw] labels reported by hap_exemplars
 };
@@ -63,16 +64,16 @@ struct LevelPtrs {
 // Host launchers (defined in the .hip files).
 template <typename T>
 hipError_t launch_sweep_level(const T *S, int64_t lds, const LevelPtrs<T> &lv, T *phi_down,
-                              const T *tau_l, int n, int64_t ldw, int level, int levels, double lam,
-                              T *Qpart, const Launch &lc, DevState *ds, hipStream_t st);
+                              const T *tau_l, int n, int64_t ldw, double lam, T *Qpart, const Launch &lc,
+                              DevState *ds, hipStream_t st);
 template <typename T>
 hipError_t launch_colsum(const T *Qpart, int64_t ldw, int nb, int n, const LevelPtrs<T> &lv,
-                         T *tau_next, bool last, int K, bool ordered, DevState *ds, hipStream_t st);
+                         const LevelPtrs<T> *down, T *tau_next, bool top, bool last, int K, bool ordered,
+                         DevState *ds, hipStream_t st);
 template <typename T>
-hipError_t launch_finalize(const T *S, int64_t lds, const LevelPtrs<T> &lv, int n, int64_t ldw,
-                           int level, int levels, double lam, int t, const Launch &lc,
-                           int32_t *labels_out, T *alpha_out, int64_t lda, T *c_out, T *phi_out,
-                           DevState *ds, hipStream_t st);
+hipError_t launch_finalize(const T *S, int64_t lds, const LevelPtrs<T> &lv, int n, int64_t ldw, double lam, int t,
+                           int32_t *labels_out, T *alpha_out, int64_t lda, T *c_out, T *phi_out, DevState *ds,
+                           hipStream_t st);
 bool launch_supported(int threads, int chunks, int elem_size);
 template <typename T>
 hipError_t launch_alpha_pad(T *A, int64_t rows, int n, int64_t ldw, hipStream_t st);

@@ -40,16 +40,14 @@ struct SweepArgs {
     T *__restrict__ A;
     int64_t ldw;
     const T *__restrict__ pref;
-    T *C;                 // [2][ldw]
-    const T *__restrict__ phi;
+    T *C;                 // [ldw] c^l, written by the row pass
     T *phi_down;          // phi^{l-1}, nullptr at l = 0
-    const T *__restrict__ Q;
+    const T *__restrict__ B;    // B^{l,t-1}_j = c_j + phi_j + Q_j (Q_j at the top level), formed by the column sums
     const T *__restrict__ tau;  // nullptr at l = 0 (tau^1 = +inf)
     int32_t *E;
     T *__restrict__ Qpart;
     int n;
     int rb;
-    int top;              // level == L-1: B = Q (no c, no phi)
     T lam, oml;
     DevState *ds;
 };
@@ -96,7 +94,7 @@ struct RowRegs {
 // never win a maximum); inside the last partial vector the padding columns of A hold -inf
 // from initialisation and stay -inf or NaN, which '>' and fmax ignore.  Padding columns of
 // R, A and the column partials are never read back as results.
-template <typename T, int NT, int NCH>
+template <typename T, int NT, int NCH, bool TAIL>
 __device__ __forceinline__ void load_row(const SweepArgs<T> &a, int i, RowRegs<T, NT, NCH> &x) {
     using V = typename Vec<T>::type;
     constexpr int VW = Vec<T>::N;
@@ -106,7 +104,7 @@ __device__ __forceinline__ void load_row(const SweepArgs<T> &a, int i, RowRegs<T
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         const int j0 = c * NT * VW + threadIdx.x * VW;
-        if (j0 < a.n) {
+        if (!TAIL || j0 < a.n) {
             // S streams through once per level: non-temporal, so it does not displace R/A lines
             x.s[c] = __builtin_nontemporal_load((const V *)(Srow + j0));
             x.r[c] = *(const V *)(Rrow + j0);
@@ -120,9 +118,9 @@ __device__ __forceinline__ void load_row(const SweepArgs<T> &a, int i, RowRegs<T
 }
 
 // The rows of one workgroup.  FIRST: iteration 1, alpha is the initial value (nothing to
-// finish, c and phi keep their initial 0).  PF: the next row's S, R, A are loaded before the
-// current row is reduced, so memory traffic overlaps the reductions and the barrier.
-template <typename T, int NT, int NCH, bool FIRST, bool PF>
+// finish, c and phi keep their initial 0).  TAIL: n is not exactly threads*chunks*VW, so
+// accesses past n are guarded (an exact fit needs no guard at all).
+template <typename T, int NT, int NCH, bool FIRST, bool TAIL>
 __device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, const int row0, const int row1,
                                            const typename Vec<T>::type (&Bv)[NCH], typename Vec<T>::type (&qv)[NCH],
                                            T (*sh_m1)[NT / 64], int (*sh_k1)[NT / 64], T (*sh_m2)[NT / 64],
@@ -136,33 +134,29 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, c
     const int64_t ldw = a.ldw;
     const T lam = a.lam, oml = a.oml;
     const T zero = T(0), ninf = neg_inf<T>();
-    const int cur = t & 1;
     const bool has_tau = a.tau != nullptr;
 
     RowRegs<T, NT, NCH> x;
-    if (PF) load_row<T, NT, NCH>(a, row0, x);
     int buf = 0;
     for (int i = row0; i < row1; ++i, buf ^= 1) {
-        RowRegs<T, NT, NCH> nx;
-        if (PF) {
-            if (i + 1 < row1) load_row<T, NT, NCH>(a, i + 1, nx);
-        } else {
-            load_row<T, NT, NCH>(a, i, x);
-        }
+        load_row<T, NT, NCH, TAIL>(a, i, x);
         T *Rrow = a.R + (int64_t)i * ldw;
         T *Arow = a.A + (int64_t)i * ldw;
         const T p_i = a.pref[i];
-        int dcol = i - tid * VW;  // the diagonal sits at chunk c, lane v iff dcol == c*NT*VW + v
+        // Column indices are handled relative to this thread's base tid*VW: element (c, v) is
+        // column base + c*NT*VW + v, so compares and selects use compile-time offsets.
+        const int base = tid * VW;
+        int dcol = i - base;  // the diagonal sits at offset dcol
         T m1 = ninf, m2 = ninf, cv = ninf;
-        int k1 = INT_MAX, ck = INT_MAX;
+        int k1 = INT_MAX, ck = INT_MAX;   // offsets until the reduction
         // phase 1: finish alpha^{t-1}, reduce c/e over alpha + rho and the top two of alpha + s
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            const int j0 = c * NT * VW + tid * VW;
+            const int j0 = c * NT * VW + base;
 #pragma unroll
             for (int v = 0; v < VW; ++v) {
-                const int j = j0 + v;
-                const bool diag = dcol == c * NT * VW + v;
+                const int j = c * NT * VW + v;
+                const bool diag = dcol == j;
                 const T sj = diag ? p_i : x.s[c][v];
                 x.s[c][v] = sj;
                 const T rj = x.r[c][v];
@@ -184,9 +178,11 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, c
                 m1 = g1 ? y : m1;
             }
             if constexpr (!FIRST) {
-                if (j0 < n) __builtin_nontemporal_store(x.a[c], (V *)(Arow + j0));
+                if (!TAIL || j0 < n) __builtin_nontemporal_store(x.a[c], (V *)(Arow + j0));
             }
         }
+        k1 = (k1 == INT_MAX) ? INT_MAX : k1 + base;
+        ck = (ck == INT_MAX) ? INT_MAX : ck + base;
         wave_reduce<T, !FIRST>(m1, k1, m2, cv, ck);
         if (lane == 0) {
             sh_m1[buf][wid] = m1;
@@ -208,7 +204,7 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, c
                 cv = sh_cv[buf][0];
                 ck = sh_ck[buf][0];
                 for (int w = 1; w < NW; ++w) argmax_merge(cv, ck, sh_cv[buf][w], sh_ck[buf][w]);
-                a.C[cur * ldw + i] = cv;
+                a.C[i] = cv;
                 if (a.phi_down) a.phi_down[i] = m1;
                 const int old = a.E[i];
                 a.E[i] = ck;
@@ -218,28 +214,27 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, c
         // phase 2: rho^t, column partials.  dcol is made opaque so the diagonal masks are
         // recomputed here instead of being kept alive across the barrier.
         asm volatile("" : "+v"(dcol));
+        const int k1r = k1 - base;
         const T tau_i = has_tau ? a.tau[i] : zero;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            const int j0 = c * NT * VW + tid * VW;
+            const int j0 = c * NT * VW + base;
             V out;
 #pragma unroll
             for (int v = 0; v < VW; ++v) {
-                const int j = j0 + v;
-                const T m = (j == k1) ? m2 : m1;
+                const int j = c * NT * VW + v;
+                const T m = (j == k1r) ? m2 : m1;
                 const T rh = has_tau ? x.s[c][v] + fmin(tau_i, -m) : x.s[c][v] - m;
                 const T rn = lam * x.r[c][v] + oml * rh;
                 out[v] = rn;
-                const bool diag = dcol == c * NT * VW + v;
-                qv[c][v] += diag ? rn : fmax(zero, rn);
+                qv[c][v] += (dcol == j) ? rn : fmax(zero, rn);
             }
-            if (j0 < n) __builtin_nontemporal_store(out, (V *)(Rrow + j0));
+            if (!TAIL || j0 < n) __builtin_nontemporal_store(out, (V *)(Rrow + j0));
         }
-        if (PF) x = nx;
     }
 }
 
-template <typename T, int NT, int NCH, bool PF>
+template <typename T, int NT, int NCH, bool TAIL>
 __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
 #pragma clang fp contract(off)
     using V = typename Vec<T>::type;
@@ -252,7 +247,6 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
     if (ds->done) return;
     const int t = ds->t + 1;
     const bool first = (t == 1);
-    const int prev = (t & 1) ^ 1;
     const int tid = threadIdx.x;
     const int n = a.n;
     const int64_t ldw = a.ldw;
@@ -262,33 +256,199 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         const int j0 = c * NT * VW + tid * VW;
-        V bv = (V)(T(0));
-        if (!first && j0 < n) {
-            const V q = *(const V *)(a.Q + j0);
-            if (a.top) {
-                bv = q;
-            } else {
-                const V cc = *(const V *)(a.C + prev * ldw + j0);
-                const V pv = *(const V *)(a.phi + j0);
-                bv = (cc + pv) + q;
-            }
-        }
-        Bv[c] = bv;
+        Bv[c] = (!first && (!TAIL || j0 < n)) ? *(const V *)(a.B + j0) : (V)(T(0));
         qv[c] = (V)(T(0));
     }
     const int row0 = blockIdx.x * a.rb;
     const int row1 = min(n, row0 + a.rb);
     if (first)
-        sweep_rows<T, NT, NCH, true, PF>(a, t, row0, row1, Bv, qv, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
+        sweep_rows<T, NT, NCH, true, TAIL>(a, t, row0, row1, Bv, qv, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
     else
-        sweep_rows<T, NT, NCH, false, PF>(a, t, row0, row1, Bv, qv, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
+        sweep_rows<T, NT, NCH, false, TAIL>(a, t, row0, row1, Bv, qv, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
 
     T *qrow = a.Qpart + (int64_t)blockIdx.x * ldw;
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         const int j0 = c * NT * VW + tid * VW;
-        if (j0 < n) *(V *)(qrow + j0) = qv[c];
+        if (!TAIL || j0 < n) *(V *)(qrow + j0) = qv[c];
     }
+}
+
+// Buffer-resource accesses (raw buffer instructions): a per-row resource, the lane's byte
+// offset in a VGPR and the chunk offset as a scalar, so a chunk costs no address registers.
+// Loads past the resource's range return 0 and stores past it are dropped.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *p, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename V, int AUX>
+__device__ __forceinline__ V buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
+}
+template <typename V, int AUX>
+__device__ __forceinline__ void buf_store(V v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    typedef unsigned int U4 __attribute__((ext_vector_type(4)));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, v), r, voff, soff, AUX);
+}
+constexpr int kNT = 2;  // cache-policy operand: non-temporal
+
+// Row pass for rows too long to keep in registers (large N, 1024 threads).  Same arithmetic
+// as sweep_rows.  The chunks of a row are visited by a runtime loop: phase 1 streams S, R,
+// A and B; phase 2 reads the row's S and R again (normal loads, so the second read is
+// served by the caches the first read filled).  Column partials live in thread-private LDS
+// slots (up to kLdsChunks chunks); further chunks keep theirs in this workgroup's own row
+// of Qpart, read and written by the owning thread only.
+constexpr int kLdsChunks = 8;
+
+template <typename T, int NT, bool FIRST, bool TAIL>
+__device__ __forceinline__ void stream_rows(const SweepArgs<T> &a, const int t, const int row0, const int row1,
+                                            const int nch, typename Vec<T>::type (*qs)[NT],
+                                            const __amdgpu_buffer_rsrc_t rQ, T (*sh_m1)[NT / 64],
+                                            int (*sh_k1)[NT / 64], T (*sh_m2)[NT / 64], T (*sh_cv)[NT / 64],
+                                            int (*sh_ck)[NT / 64]) {
+#pragma clang fp contract(off)
+    using V = typename Vec<T>::type;
+    constexpr int VW = Vec<T>::N;
+    constexpr int NW = NT / 64;
+    constexpr int CB = NT * VW * (int)sizeof(T);  // bytes per chunk
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int n = a.n;
+    const int64_t ldw = a.ldw;
+    const T lam = a.lam, oml = a.oml;
+    const T zero = T(0), ninf = neg_inf<T>();
+    const bool has_tau = a.tau != nullptr;
+    const int base = tid * VW;
+    const int voff = tid * 16;
+    const __amdgpu_buffer_rsrc_t rB = row_rsrc(a.B, ldw * (int64_t)sizeof(T));
+    int buf = 0;
+    for (int i = row0; i < row1; ++i, buf ^= 1) {
+        const __amdgpu_buffer_rsrc_t rS = row_rsrc(a.S + (int64_t)i * a.lds, a.lds * (int64_t)sizeof(T));
+        const __amdgpu_buffer_rsrc_t rR = row_rsrc(a.R + (int64_t)i * ldw, ldw * (int64_t)sizeof(T));
+        const __amdgpu_buffer_rsrc_t rA = row_rsrc(a.A + (int64_t)i * ldw, ldw * (int64_t)sizeof(T));
+        const T p_i = a.pref[i];
+        const int dcol = i - base;
+        T m1 = ninf, m2 = ninf, cv = ninf;
+        int k1 = INT_MAX, ck = INT_MAX;   // offsets from base until the reduction
+        // phase 1
+        for (int c = 0; c < nch; ++c) {
+            const int off0 = c * NT * VW;   // this chunk's column offset from base
+            const V sv = buf_load<V, 0>(rS, voff, c * CB);
+            const V rv = buf_load<V, 0>(rR, voff, c * CB);
+            V av = buf_load<V, 0>(rA, voff, c * CB);
+            V bv = (V)(zero);
+            if constexpr (!FIRST) bv = buf_load<V, 0>(rB, voff, c * CB);
+            if constexpr (TAIL) {
+                // columns past n: alpha reads as -inf so they never win a maximum
+                if (off0 + base >= n) av = (V)(ninf);
+            }
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                const int j = off0 + v;
+                const bool diag = dcol == j;
+                const T sj = diag ? p_i : sv[v];
+                const T rj = rv[v];
+                T al = av[v];
+                if constexpr (!FIRST) {
+                    const T ah = diag ? bv[v] - rj : fmin(zero, bv[v] - fmax(zero, rj));
+                    al = lam * al + oml * ah;
+                    av[v] = al;
+                    const T cx = al + rj;
+                    const bool gg = cx > cv;
+                    cv = gg ? cx : cv;
+                    ck = gg ? j : ck;
+                }
+                const T y = al + sj;
+                const bool g1 = y > m1;
+                m2 = g1 ? m1 : fmax(m2, y);
+                k1 = g1 ? j : k1;
+                m1 = g1 ? y : m1;
+            }
+            if constexpr (!FIRST) buf_store<V, kNT>(av, rA, voff, c * CB);
+        }
+        k1 = (k1 == INT_MAX) ? INT_MAX : k1 + base;
+        ck = (ck == INT_MAX) ? INT_MAX : ck + base;
+        wave_reduce<T, !FIRST>(m1, k1, m2, cv, ck);
+        if (lane == 0) {
+            sh_m1[buf][wid] = m1;
+            sh_k1[buf][wid] = k1;
+            sh_m2[buf][wid] = m2;
+            if constexpr (!FIRST) {
+                sh_cv[buf][wid] = cv;
+                sh_ck[buf][wid] = ck;
+            }
+        }
+        __syncthreads();
+        m1 = sh_m1[buf][0];
+        k1 = sh_k1[buf][0];
+        m2 = sh_m2[buf][0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) top2_merge(m1, k1, m2, sh_m1[buf][w], sh_k1[buf][w], sh_m2[buf][w]);
+        if constexpr (!FIRST) {
+            if (tid == 0) {
+                cv = sh_cv[buf][0];
+                ck = sh_ck[buf][0];
+                for (int w = 1; w < NW; ++w) argmax_merge(cv, ck, sh_cv[buf][w], sh_ck[buf][w]);
+                a.C[i] = cv;
+                if (a.phi_down) a.phi_down[i] = m1;
+                const int old = a.E[i];
+                a.E[i] = ck;
+                if (t >= 3 && old != ck) atomicOr(&a.ds->changed, 1);
+            }
+        }
+        // phase 2
+        const int k1r = k1 - base;
+        const T tau_i = has_tau ? a.tau[i] : zero;
+        for (int c = 0; c < nch; ++c) {
+            const int off0 = c * NT * VW;
+            const V sv = buf_load<V, 0>(rS, voff, c * CB);
+            const V rv = buf_load<V, 0>(rR, voff, c * CB);
+            V out;
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                const int j = off0 + v;
+                const T sj = (dcol == j) ? p_i : sv[v];
+                const T m = (j == k1r) ? m2 : m1;
+                const T rh = has_tau ? sj + fmin(tau_i, -m) : sj - m;
+                out[v] = lam * rv[v] + oml * rh;
+            }
+            buf_store<V, kNT>(out, rR, voff, c * CB);
+            V q = (c < kLdsChunks) ? qs[c][tid] : buf_load<V, 0>(rQ, voff, c * CB);
+#pragma unroll
+            for (int v = 0; v < VW; ++v) q[v] += (dcol == off0 + v) ? out[v] : fmax(zero, out[v]);
+            if (c < kLdsChunks)
+                qs[c][tid] = q;
+            else
+                buf_store<V, 0>(q, rQ, voff, c * CB);
+        }
+    }
+}
+
+template <typename T, int NT, bool TAIL>
+__global__ __launch_bounds__(NT) void sweep_stream_kernel(SweepArgs<T> a, int nch) {
+#pragma clang fp contract(off)
+    using V = typename Vec<T>::type;
+    constexpr int VW = Vec<T>::N;
+    constexpr int NW = NT / 64;
+    constexpr int CB = NT * VW * (int)sizeof(T);
+    __shared__ T sh_m1[2][NW], sh_m2[2][NW], sh_cv[2][NW];
+    __shared__ int sh_k1[2][NW], sh_ck[2][NW];
+    __shared__ V qs[kLdsChunks][NT];
+    const DevState *ds = a.ds;
+    if (ds->done) return;
+    const int t = ds->t + 1;
+    const __amdgpu_buffer_rsrc_t rQ = row_rsrc(a.Qpart + (int64_t)blockIdx.x * a.ldw, a.ldw * (int64_t)sizeof(T));
+    for (int c = 0; c < nch; ++c) {
+        if (c < kLdsChunks)
+            qs[c][threadIdx.x] = (V)(T(0));
+        else
+            buf_store<V, 0>((V)(T(0)), rQ, threadIdx.x * 16, c * CB);
+    }
+    const int row0 = blockIdx.x * a.rb;
+    const int row1 = min(a.n, row0 + a.rb);
+    if (t == 1)
+        stream_rows<T, NT, true, TAIL>(a, t, row0, row1, nch, qs, rQ, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
+    else
+        stream_rows<T, NT, false, TAIL>(a, t, row0, row1, nch, qs, rQ, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
+    for (int c = 0; c < nch && c < kLdsChunks; ++c) buf_store<V, 0>(qs[c][threadIdx.x], rQ, threadIdx.x * 16, c * CB);
 }
 
 // Padding columns [n, ldw) of every A row of every level start at -inf.
@@ -304,14 +464,28 @@ __global__ void alpha_pad_kernel(T *A, int64_t rows, int n, int64_t ldw) {
 
 // Column sums Q_j = sum over workgroups of the partials, in a fixed order (NG = 1:
 // strictly in workgroup order, which with one row per workgroup is plain row order);
-// then
-// tau^{l+1}_j = c^l_j + Q_j (Eq. 2.4, c^l from before this iteration's update).
-// The launch for the top level also advances the iteration counter and applies
-// the stop rule (in workgroup 0, thread 0).
+// then tau^{l+1}_j = c^l_j + Q^l_j (Eq. 2.4, c^l from before this iteration's update),
+// and the availability base of the next pass: B^{l-1}_j = c^{l-1}_j + phi^{l-1}_j + Q^{l-1}_j
+// (phi^{l-1} was just sent down by this level's row pass), or B^l_j = Q^l_j at the top
+// level.  The launch for the top level also advances the iteration counter and applies
+// the stop rule (workgroup 0, thread 0).
+template <typename T>
+struct ColArgs {
+    const T *__restrict__ Qpart;
+    int64_t ldw;
+    int nb, n;
+    T *Q;                // Q^l (written)
+    const T *C;          // c^l
+    T *tau_next;         // tau^{l+1} or nullptr at the top level
+    T *B_top;            // B^l = Q^l at the top level, else nullptr
+    T *B_down;           // B^{l-1}, nullptr at l = 0
+    const T *C_down, *phi_down, *Q_down;
+    int last, K;
+    DevState *ds;
+};
+
 template <typename T, int NG>
-__global__ __launch_bounds__(16 * NG) void colsum_kernel(const T *__restrict__ Qpart, int64_t ldw, int nb, int n,
-                                                         T *__restrict__ Q, const T *__restrict__ C,
-                                                         T *__restrict__ tau_next, int last, int K, DevState *ds) {
+__global__ __launch_bounds__(16 * NG) void colsum_kernel(ColArgs<T> a) {
 #pragma clang fp contract(off)
     using V = typename Vec<T>::type;
     constexpr int VW = Vec<T>::N;
@@ -319,15 +493,16 @@ __global__ __launch_bounds__(16 * NG) void colsum_kernel(const T *__restrict__ Q
     // 16 column vectors per workgroup; group g sums partial rows g, g+NG, g+2NG, ... in order
     const int col = threadIdx.x & 15, g = threadIdx.x >> 4;
     const int j0 = (blockIdx.x * 16 + col) * VW;
+    const int n = a.n, nb = a.nb;
     V acc = (V)(T(0));
     if (j0 < n) {
         if (NG == 1) {
             // strictly sequential adds; the loads are issued 16 ahead
 #pragma unroll 16
-            for (int b = 0; b < nb; ++b) acc += *(const V *)(Qpart + (int64_t)b * ldw + j0);
+            for (int b = 0; b < nb; ++b) acc += *(const V *)(a.Qpart + (int64_t)b * a.ldw + j0);
         } else {
 #pragma unroll 4
-            for (int b = g; b < nb; b += NG) acc += *(const V *)(Qpart + (int64_t)b * ldw + j0);
+            for (int b = g; b < nb; b += NG) acc += *(const V *)(a.Qpart + (int64_t)b * a.ldw + j0);
         }
     }
     if (NG > 1) {
@@ -338,27 +513,31 @@ __global__ __launch_bounds__(16 * NG) void colsum_kernel(const T *__restrict__ Q
         V tot = acc;
 #pragma unroll
         for (int k = 1; k < NG; ++k) tot += sh[k][col];
-        *(V *)(Q + j0) = tot;
-        if (tau_next != nullptr) {
-            const int cur = (ds->t + 1) & 1;
-            *(V *)(tau_next + j0) = *(const V *)(C + cur * ldw + j0) + tot;
-        }
+        *(V *)(a.Q + j0) = tot;
+        if (a.tau_next != nullptr) *(V *)(a.tau_next + j0) = *(const V *)(a.C + j0) + tot;
+        if (a.B_top != nullptr) *(V *)(a.B_top + j0) = tot;
+        if (a.B_down != nullptr)
+            *(V *)(a.B_down + j0) =
+                (*(const V *)(a.C_down + j0) + *(const V *)(a.phi_down + j0)) + *(const V *)(a.Q_down + j0);
     }
-    if (last && blockIdx.x == 0 && threadIdx.x == 0 && !ds->done) {
-        const int tcur = ds->t + 1;
-        if (tcur >= 2) {
-            const int it = tcur - 1;  // label iteration compared during this sweep
-            if (it >= 2 && !ds->changed)
-                ds->stable += 1;
-            else
-                ds->stable = 0;
-            if (K > 0 && ds->stable >= K) {
-                ds->done = 1;
-                ds->stop_iter = it;
+    if (a.last && blockIdx.x == 0 && threadIdx.x == 0) {
+        DevState *ds = a.ds;
+        if (!ds->done) {
+            const int tcur = ds->t + 1;
+            if (tcur >= 2) {
+                const int it = tcur - 1;  // label iteration compared during this sweep
+                if (it >= 2 && !ds->changed)
+                    ds->stable += 1;
+                else
+                    ds->stable = 0;
+                if (a.K > 0 && ds->stable >= a.K) {
+                    ds->done = 1;
+                    ds->stop_iter = it;
+                }
             }
+            ds->changed = 0;
+            ds->t = tcur;
         }
-        ds->changed = 0;
-        ds->t = tcur;
     }
 }
 
@@ -373,32 +552,29 @@ struct FinArgs {
     const T *__restrict__ A;
     int64_t ldw;
     const T *__restrict__ pref;
-    const T *__restrict__ C;
-    const T *__restrict__ phi;
-    const T *__restrict__ Q;
+    const T *__restrict__ B;
     const int32_t *__restrict__ E;
     int32_t *labels;
     T *alpha_out;
     int64_t lda;
     T *c_out;
     T *phi_out;
-    int n, t, top;
+    int n, t;
     T lam, oml;
     DevState *ds;
 };
 
-template <typename T, int NT, int NCH>
-__global__ __launch_bounds__(NT) void finalize_kernel(FinArgs<T> a) {
+template <typename T>
+__global__ __launch_bounds__(256) void finalize_kernel(FinArgs<T> a) {
 #pragma clang fp contract(off)
     using V = typename Vec<T>::type;
     constexpr int VW = Vec<T>::N;
-    constexpr int NW = NT / 64;
+    constexpr int NT = 256, NW = NT / 64;
     __shared__ T sh_m[NW], sh_cv[NW];
     __shared__ int sh_ck[NW];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int n = a.n;
     const int i = blockIdx.x;
-    const int cur = a.t & 1;
     const bool mat = a.t >= 1;
     const T zero = T(0);
     const T *Srow = a.S + (int64_t)i * a.lds;
@@ -407,15 +583,11 @@ __global__ __launch_bounds__(NT) void finalize_kernel(FinArgs<T> a) {
     const T p_i = a.pref[i];
     T mx = neg_inf<T>(), cv = neg_inf<T>();
     int ck = INT_MAX;
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-        const int j0 = c * NT * VW + tid * VW;
-        if (j0 >= n) continue;
+    for (int j0 = tid * VW; j0 < n; j0 += NT * VW) {
         const V sv = *(const V *)(Srow + j0);
         const V rv = *(const V *)(Rrow + j0);
         V av = *(const V *)(Arow + j0);
-        V bv = *(const V *)(a.Q + j0);
-        if (!a.top) bv = (*(const V *)(a.C + cur * a.ldw + j0) + *(const V *)(a.phi + j0)) + bv;
+        const V bv = *(const V *)(a.B + j0);
 #pragma unroll
         for (int v = 0; v < VW; ++v) {
             const int j = j0 + v;
@@ -512,8 +684,8 @@ bool launch_supported(int threads, int chunks, int elem_size) {
 
 template <typename T>
 hipError_t launch_sweep_level(const T *S, int64_t lds, const LevelPtrs<T> &lv, T *phi_down,
-                              const T *tau_l, int n, int64_t ldw, int level, int levels, double lam,
-                              T *Qpart, const Launch &lc, DevState *ds, hipStream_t st) {
+                              const T *tau_l, int n, int64_t ldw, double lam, T *Qpart, const Launch &lc,
+                              DevState *ds, hipStream_t st) {
     SweepArgs<T> a;
     a.S = S;
     a.lds = lds;
@@ -522,25 +694,32 @@ hipError_t launch_sweep_level(const T *S, int64_t lds, const LevelPtrs<T> &lv, T
     a.ldw = ldw;
     a.pref = lv.pref;
     a.C = lv.C;
-    a.phi = lv.phi;
     a.phi_down = phi_down;
-    a.Q = lv.Q;
+    a.B = lv.B;
     a.tau = tau_l;
     a.E = lv.E;
     a.Qpart = Qpart;
     a.n = n;
     a.rb = lc.rows_per_block;
-    a.top = (level == levels - 1);
     a.lam = (T)lam;
     a.oml = (T)(1.0 - lam);
     a.ds = ds;
     const int nb = (n + lc.rows_per_block - 1) / lc.rows_per_block;
-#define HAP_LAUNCH_SWEEP(NTC, NCHC)                                                        \
-    do {                                                                                   \
-        if (lc.prefetch)                                                                   \
-            hipLaunchKernelGGL((sweep_kernel<T, NTC, NCHC, true>), dim3(nb), dim3(NTC), 0, st, a); \
-        else                                                                               \
-            hipLaunchKernelGGL((sweep_kernel<T, NTC, NCHC, false>), dim3(nb), dim3(NTC), 0, st, a); \
+    const bool tail = (int64_t)lc.threads * lc.chunks * Vec<T>::N != n;
+    if (lc.streaming) {
+        if (lc.threads != 1024 || lc.chunks < 1 || lc.chunks > 16) return hipErrorInvalidValue;
+        if (tail)
+            hipLaunchKernelGGL((sweep_stream_kernel<T, 1024, true>), dim3(nb), dim3(1024), 0, st, a, lc.chunks);
+        else
+            hipLaunchKernelGGL((sweep_stream_kernel<T, 1024, false>), dim3(nb), dim3(1024), 0, st, a, lc.chunks);
+        return hipGetLastError();
+    }
+#define HAP_LAUNCH_SWEEP(NTC, NCHC)                                                                    \
+    do {                                                                                               \
+        if (tail)                                                                                      \
+            hipLaunchKernelGGL((sweep_kernel<T, NTC, NCHC, true>), dim3(nb), dim3(NTC), 0, st, a);     \
+        else                                                                                           \
+            hipLaunchKernelGGL((sweep_kernel<T, NTC, NCHC, false>), dim3(nb), dim3(NTC), 0, st, a);    \
     } while (0)
     HAP_DISPATCH_NT_NCH(lc.threads, lc.chunks, HAP_LAUNCH_SWEEP);
 #undef HAP_LAUNCH_SWEEP
@@ -549,23 +728,37 @@ hipError_t launch_sweep_level(const T *S, int64_t lds, const LevelPtrs<T> &lv, T
 
 template <typename T>
 hipError_t launch_colsum(const T *Qpart, int64_t ldw, int nb, int n, const LevelPtrs<T> &lv,
-                         T *tau_next, bool last, int K, bool ordered, DevState *ds, hipStream_t st) {
+                         const LevelPtrs<T> *down, T *tau_next, bool top, bool last, int K, bool ordered,
+                         DevState *ds, hipStream_t st) {
     constexpr int VW = Vec<T>::N;
+    ColArgs<T> a;
+    a.Qpart = Qpart;
+    a.ldw = ldw;
+    a.nb = nb;
+    a.n = n;
+    a.Q = lv.Q;
+    a.C = lv.C;
+    a.tau_next = tau_next;
+    a.B_top = top ? lv.B : nullptr;
+    a.B_down = down ? down->B : nullptr;
+    a.C_down = down ? down->C : nullptr;
+    a.phi_down = down ? down->phi : nullptr;
+    a.Q_down = down ? down->Q : nullptr;
+    a.last = last ? 1 : 0;
+    a.K = K;
+    a.ds = ds;
     const int blocks = (n + 16 * VW - 1) / (16 * VW);
     if (ordered)
-        hipLaunchKernelGGL((colsum_kernel<T, 1>), dim3(blocks), dim3(16), 0, st, Qpart, ldw, nb, n, lv.Q, lv.C,
-                           tau_next, last ? 1 : 0, K, ds);
+        hipLaunchKernelGGL((colsum_kernel<T, 1>), dim3(blocks), dim3(16), 0, st, a);
     else
-        hipLaunchKernelGGL((colsum_kernel<T, 64>), dim3(blocks), dim3(16 * 64), 0, st, Qpart, ldw, nb, n, lv.Q,
-                           lv.C, tau_next, last ? 1 : 0, K, ds);
+        hipLaunchKernelGGL((colsum_kernel<T, 64>), dim3(blocks), dim3(16 * 64), 0, st, a);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_finalize(const T *S, int64_t lds, const LevelPtrs<T> &lv, int n, int64_t ldw,
-                           int level, int levels, double lam, int t, const Launch &lc,
-                           int32_t *labels_out, T *alpha_out, int64_t lda, T *c_out, T *phi_out,
-                           DevState *ds, hipStream_t st) {
+hipError_t launch_finalize(const T *S, int64_t lds, const LevelPtrs<T> &lv, int n, int64_t ldw, double lam, int t,
+                           int32_t *labels_out, T *alpha_out, int64_t lda, T *c_out, T *phi_out, DevState *ds,
+                           hipStream_t st) {
     FinArgs<T> a;
     a.S = S;
     a.lds = lds;
@@ -573,9 +766,7 @@ hipError_t launch_finalize(const T *S, int64_t lds, const LevelPtrs<T> &lv, int 
     a.A = lv.A;
     a.ldw = ldw;
     a.pref = lv.pref;
-    a.C = lv.C;
-    a.phi = lv.phi;
-    a.Q = lv.Q;
+    a.B = lv.B;
     a.E = labels_out ? lv.E : nullptr;
     a.labels = labels_out;
     a.alpha_out = alpha_out;
@@ -584,14 +775,10 @@ hipError_t launch_finalize(const T *S, int64_t lds, const LevelPtrs<T> &lv, int 
     a.phi_out = phi_out;
     a.n = n;
     a.t = t;
-    a.top = (level == levels - 1);
     a.lam = (T)lam;
     a.oml = (T)(1.0 - lam);
     a.ds = ds;
-#define HAP_LAUNCH_FIN(NTC, NCHC) \
-    hipLaunchKernelGGL((finalize_kernel<T, NTC, NCHC>), dim3(n), dim3(NTC), 0, st, a)
-    HAP_DISPATCH_NT_NCH(lc.threads, lc.chunks, HAP_LAUNCH_FIN);
-#undef HAP_LAUNCH_FIN
+    hipLaunchKernelGGL((finalize_kernel<T>), dim3(n), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
@@ -603,24 +790,17 @@ hipError_t launch_alpha_pad(T *A, int64_t rows, int n, int64_t ldw, hipStream_t 
     hipLaunchKernelGGL((alpha_pad_kernel<T>), dim3(grid), dim3(256), 0, st, A, rows, n, ldw);
     return hipGetLastError();
 }
-template hipError_t launch_alpha_pad<float>(float *, int64_t, int, int64_t, hipStream_t);
-template hipError_t launch_alpha_pad<double>(double *, int64_t, int, int64_t, hipStream_t);
 
-template hipError_t launch_sweep_level<float>(const float *, int64_t, const LevelPtrs<float> &, float *,
-                                              const float *, int, int64_t, int, int, double, float *,
-                                              const Launch &, DevState *, hipStream_t);
-template hipError_t launch_sweep_level<double>(const double *, int64_t, const LevelPtrs<double> &, double *,
-                                               const double *, int, int64_t, int, int, double, double *,
-                                               const Launch &, DevState *, hipStream_t);
-template hipError_t launch_colsum<float>(const float *, int64_t, int, int, const LevelPtrs<float> &, float *,
-                                         bool, int, bool, DevState *, hipStream_t);
-template hipError_t launch_colsum<double>(const double *, int64_t, int, int, const LevelPtrs<double> &,
-                                          double *, bool, int, bool, DevState *, hipStream_t);
-template hipError_t launch_finalize<float>(const float *, int64_t, const LevelPtrs<float> &, int, int64_t, int,
-                                           int, double, int, const Launch &, int32_t *, float *, int64_t,
-                                           float *, float *, DevState *, hipStream_t);
-template hipError_t launch_finalize<double>(const double *, int64_t, const LevelPtrs<double> &, int, int64_t,
-                                            int, int, double, int, const Launch &, int32_t *, double *,
-                                            int64_t, double *, double *, DevState *, hipStream_t);
+#define HAP_INSTANTIATE(T)                                                                                        \
+    template hipError_t launch_alpha_pad<T>(T *, int64_t, int, int64_t, hipStream_t);                             \
+    template hipError_t launch_sweep_level<T>(const T *, int64_t, const LevelPtrs<T> &, T *, const T *, int,      \
+                                              int64_t, double, T *, const Launch &, DevState *, hipStream_t);     \
+    template hipError_t launch_colsum<T>(const T *, int64_t, int, int, const LevelPtrs<T> &, const LevelPtrs<T> *, \
+                                         T *, bool, bool, int, bool, DevState *, hipStream_t);                    \
+    template hipError_t launch_finalize<T>(const T *, int64_t, const LevelPtrs<T> &, int, int64_t, double, int,   \
+                                           int32_t *, T *, int64_t, T *, T *, DevState *, hipStream_t);
+HAP_INSTANTIATE(float)
+HAP_INSTANTIATE(double)
+#undef HAP_INSTANTIATE
 
 }  // namespace hap

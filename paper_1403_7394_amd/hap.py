@@ -18,7 +18,7 @@ HAP_OK, HAP_E_ARG, HAP_E_DTYPE, HAP_E_OOM, HAP_E_HIP, HAP_E_STATE, HAP_E_UNSUPPO
 HAP_F32, HAP_F64 = 0, 1
 BUILD_DIRECT, BUILD_GEMM, BUILD_BF16, BUILD_BF16X3 = 0, 1, 2, 3
 PREF_MEDIAN, PREF_SCALAR, PREF_VECTOR = 0, 1, 2
-LAUNCH_PREFETCH = 1
+LAUNCH_STREAM = 2
 
 # every symbol include/hap.h declares
 EXPORTS = (
@@ -263,8 +263,8 @@ class Hap:
         _check("hap_read_messages", self._lib.hap_read_messages(self._ctx, level, P(rho), P(alpha), self.n, P(c), P(phi), P(tau)))
         return dict(rho=rho, alpha=alpha, c=c, phi=phi, tau=tau)
 
-    def set_launch(self, threads=0, chunks=0, rows_per_block=0, prefetch=None):
-        flags = -1 if prefetch is None else (LAUNCH_PREFETCH if prefetch else 0)
+    def set_launch(self, threads=0, chunks=0, rows_per_block=0, streaming=None):
+        flags = -1 if streaming is None else (LAUNCH_STREAM if streaming else 0)
         _check("hap_set_launch", self._lib.hap_set_launch(self._ctx, threads, chunks, rows_per_block, flags))
 
     def profile(self, enable: bool):
@@ -278,8 +278,8 @@ class Hap:
         return a.value, b.value, c.value, d.value
 
     def get_launch(self):
-        """(threads, chunks, rows_per_block, prefetch)."""
+        """(threads, chunks, rows_per_block, streaming)."""
         a, b, c, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check("hap_get_launch", self._lib.hap_get_launch(self._ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
                                                           ctypes.byref(f)))
-        return a.value, b.value, c.value, bool(f.value & LAUNCH_PREFETCH)
+        return a.value, b.value, c.value, bool(f.value & LAUNCH_STREAM)

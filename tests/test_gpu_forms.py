@@ -1,0 +1,85 @@
+"""GPU tests of the Gram-matrix (MFMA) similarity builds against the FP64 oracle.
+
+Error bounds are derived from each build's arithmetic (u = 2^-24, FP32 unit roundoff):
+  GEMM FP32   S = -((n_i + n_j) - 2 g): FP32 rounding of the norms, of the d-term dot product
+              and of the combination: |dS| <= (d + 4) u (n_i + n_j).
+  BF16        coordinates rounded to BF16 (8 significant bits: relative error <= 2^-8), norms
+              of the rounded points: S is the FP32 distance of the rounded points, so
+              |dS| <= 2 |x_i - x_j| |d_i - d_j| + |d_i - d_j|^2 + (d + 4) u (n_i + n_j),
+              with |d_i| <= 2^-8 |x_i|.
+  BF16x3      x = hi + lo + r, |x - hi| <= 2^-8 |x|, |r| <= 2^-8 |x - hi| <= 2^-16 |x|; r and the
+              dropped lo.lo term change g by at most 4 * 2^-16 |x_i| |x_j|; three passes of d
+              FP32 accumulations: |dS| <= 8 * 2^-16 |x_i| |x_j| + (3d + 4) u (n_i + n_j).
+  GEMM FP64   (d + 4) 2^-53 (n_i + n_j).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import similarity as sim
+from paper_1403_7394_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+U32 = 2.0 ** -24
+
+
+def _build(hap, X, mode, dtype=torch.float32):
+    n = X.shape[0]
+    S = torch.full((n, n + 4), 5.0, dtype=dtype, device=DEV)
+    hap.build_similarity(X, S[:, :n], mode=mode)
+    out = S.cpu().numpy()
+    assert np.all(out[:, n:] == 5.0)   # columns past n untouched
+    return out[:, :n]
+
+
+@pytest.mark.parametrize("n,d,seed", [(1000, 64, 1), (257, 33, 2), (130, 5, 3), (64, 2, 4)])
+def test_gram_builds_within_derived_bounds(hap_gpu, n, d, seed):
+    b = synth.gaussian_blobs(seed, n, d, 7, centre="normal", centre_scale=2.0, sigma_lo=1.0, sigma_hi=1.0,
+                             sizes="multinomial", dtype=np.float32)
+    X64 = b.X.astype(np.float64)
+    ref = sim.similarity(X64)
+    nrm = np.sum(X64 * X64, axis=1)
+    norm_sum = nrm[:, None] + nrm[None, :]
+    xn = np.sqrt(nrm)
+    X = torch.from_numpy(b.X).to(DEV)
+    dist = np.sqrt(-ref)
+
+    got = _build(hap_gpu, X, hap_gpu.BUILD_GEMM)
+    assert np.all(np.abs(got - ref) <= (d + 4) * U32 * norm_sum + 1e-30)
+
+    got = _build(hap_gpu, X, hap_gpu.BUILD_BF16)
+    dlt = 2.0 ** -8 * (xn[:, None] + xn[None, :])
+    assert np.all(np.abs(got - ref) <= 2 * dist * dlt + dlt ** 2 + (d + 4) * U32 * norm_sum)
+
+    got3 = _build(hap_gpu, X, hap_gpu.BUILD_BF16X3)
+    assert np.all(np.abs(got3 - ref) <= 8 * 2.0 ** -16 * np.outer(xn, xn) + (3 * d + 4) * U32 * norm_sum)
+    # the split-precision build is much closer than a single BF16 pass
+    assert np.max(np.abs(got3 - ref)) < np.max(np.abs(got - ref)) / 16
+
+    X64t = torch.from_numpy(X64).to(DEV)
+    got64 = _build(hap_gpu, X64t, hap_gpu.BUILD_GEMM, torch.float64)
+    assert np.all(np.abs(got64 - ref) <= (d + 4) * 2.0 ** -53 * norm_sum)
+
+    for g in (got, got3, got64):
+        assert np.all(np.diag(g) == 0) and np.all(g <= 0)
+
+
+def test_gemm_build_f64_with_noise_within_bound(hap_gpu):
+    """The FP64 GEMM build adds the counter-based tie-break noise: within the FP64 GEMM bound
+    (plus the noise of that rounding difference) of the oracle's noised similarity."""
+    b = synth.small_blobs(9, 200, k=3)
+    X64 = b.X.astype(np.float64)
+    X = torch.from_numpy(X64).to(DEV)
+    S1 = torch.empty((200, 200), dtype=torch.float64, device=DEV)
+    hap_gpu.build_similarity(X, S1, mode=hap_gpu.BUILD_GEMM, noise_rel=1e-6, seed=5)
+    ref = sim.add_noise(sim.similarity(X64), 1e-6, 5)
+    nrm = np.sum(X64 * X64, axis=1)
+    bound = (2 + 4) * 2.0 ** -53 * (nrm[:, None] + nrm[None, :]) * (1 + 2e-6)
+    assert np.all(np.abs(S1.cpu().numpy() - ref) <= bound)
+    # and the noise is there: the noise-free build differs by about 1e-6 relative
+    S0 = torch.empty_like(S1)
+    hap_gpu.build_similarity(X, S0, mode=hap_gpu.BUILD_GEMM)
+    rel = np.abs(S1.cpu().numpy() - S0.cpu().numpy()) / np.maximum(np.abs(ref), 1e-300)
+    off = ~np.eye(200, dtype=bool)
+    assert 0.3e-6 < np.median(rel[off]) < 0.7e-6

@@ -295,6 +295,73 @@ def test_f32_bit_identical_to_fp32_oracle(hap_gpu, n, lam, T, rb):
         assert np.array_equal(g["msgs"][l]["alpha"], r.state.alpha[l])
 
 
+@pytest.mark.parametrize("n,chunks,lam,T", [(1000, 1, 0.9, 60), (300, 10, 0.5, 40), (1500, 3, 0.7, 30)])
+def test_streaming_row_pass_bit_identical_to_fp32_oracle(hap_gpu, n, chunks, lam, T):
+    """The streaming row pass (long rows: 1024 threads, the row re-read in phase 2, column
+    partials in LDS and, past eight chunks, in the workgroup's own partial row) forced on
+    small problems; one row per workgroup keeps the column sums in row order."""
+    b, _ = synth.workload_plain_f32(n=n)
+    S32 = oracle_S(b.X, np.float32)
+    p = sim.median_offdiag(S32, np.float32)
+    r = hap_ref.hap(S32, p, 3, lam, T, dtype=np.float32)
+    St = to_device(S32)
+    h = hap_gpu.Hap(St, 3, lam)
+    h.set_launch(1024, chunks, 1, streaming=True)
+    assert h.get_launch() == (1024, chunks, 1, True)
+    h.iterate(T)
+    labels = h.labels().cpu().numpy()
+    assert np.array_equal(labels, r.labels)
+    for l in range(3):
+        m = h.messages(l)
+        assert np.array_equal(m["rho"].cpu().numpy(), r.state.rho[l])
+        assert np.array_equal(m["alpha"].cpu().numpy(), r.state.alpha[l])
+    h.close()
+
+
+def test_streaming_matches_resident_exact_fit(hap_gpu):
+    """n = threads * chunks * 4 (no tail): the streaming and the register-resident row passes
+    sum the same rows in the same order, so they agree bit for bit."""
+    n = 4096
+    b, _ = synth.workload_plain_f32(n=n)
+    St = to_device(oracle_S(b.X, np.float32))
+    out = []
+    for shape in [(1024, 1, 2, True), (256, 4, 2, False)]:
+        h = hap_gpu.Hap(St, 3, 0.9)
+        h.set_launch(*shape[:3], streaming=shape[3])
+        h.iterate(15)
+        out.append([h.messages(l) for l in range(3)] + [h.labels()])
+        h.close()
+    for l in range(3):
+        for k in ("rho", "alpha", "c", "phi"):
+            assert torch.equal(out[0][l][k], out[1][l][k]), (l, k)
+    assert torch.equal(out[0][3], out[1][3])
+
+
+def test_streaming_row_pass_f64(hap_gpu):
+    b = synth.small_blobs(77, 700, k=5)
+    S = oracle_S(b.X, np.float64, 1e-12, 77)
+    p = sim.median_offdiag(S)
+    r = hap_ref.hap(S, p, 2, 0.5, 25)
+    St = to_device(S)
+    h = hap_gpu.Hap(St, 2, 0.5)
+    h.set_launch(1024, 1, 1, streaming=True)
+    h.iterate(25)
+    assert np.array_equal(h.labels().cpu().numpy(), r.labels)
+    for l in range(2):
+        assert np.array_equal(h.messages(l)["rho"].cpu().numpy(), r.state.rho[l])
+    h.close()
+
+
+def test_default_launch_for_long_rows_streams(hap_gpu):
+    """Rows longer than the register-resident pass allows select the streaming pass."""
+    n = 9000
+    S = torch.zeros((n, n + 8), dtype=torch.float32, device=DEV)[:, :n]
+    h = hap_gpu.Hap(S, 1, 0.5, pref=-1.0)
+    threads, chunks, rb, streaming = h.get_launch()
+    assert streaming and threads == 1024 and chunks == 3
+    h.close()
+
+
 def test_f32_stop_rule_matches_fp32_oracle(hap_gpu):
     b, _ = synth.workload_plain_f32(n=400)
     S32 = oracle_S(b.X, np.float32)
@@ -310,7 +377,7 @@ def test_f32_launch_shapes(hap_gpu):
     b, _ = synth.workload_plain_f32(n=1000)
     S32 = oracle_S(b.X, np.float32)
     base = run_gpu(hap_gpu, S32, 3, 0.9, 20)
-    for shape in [(256, 1, 0), (64, 4, 0), (128, 2, 0)]:
+    for shape in [(256, 1, 0), (64, 4, 0), (128, 2, 0), (1024, 1, 0)]:
         g = run_gpu(hap_gpu, S32, 3, 0.9, 20, launch=shape)
         for l in range(3):
             assert np.array_equal(g["msgs"][l]["rho"], base["msgs"][l]["rho"])
