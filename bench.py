@@ -146,6 +146,66 @@ def run_precision_form(args, torch, hap, synth) -> dict:
             f"{iters} iterations", "n": n, "d": d, "results": results}
 
 
+def run_batched_form(args, torch, hap, synth) -> dict:
+    """Batched form: 512 independent problems (N ~ U{64..2048}, d=16, L=3, damping 0.8,
+    200 iterations) in one persistent launch, against the plain single-problem path run
+    problem by problem on the same GPU (with its column sums in row order, the batch's
+    order, so the two compute the same trajectory)."""
+    import numpy as np
+
+    from paper_1403_7394_amd import autotune
+    dev = torch.device("cuda:0")
+    problems, rp = synth.workload_batched()
+    iters = args.form_iters if args.form_iters else rp.max_iters
+    sizes = [b.X.shape[0] for b in problems]
+    X = torch.from_numpy(np.concatenate([b.X for b in problems])).to(dev)
+    L = rp.levels
+    bt = hap.HapBatch(sizes, 16, L)
+    shape = autotune.tune_batch(bt, X, rp.damping)
+    out = bt.outputs(dev)
+    bt.run(X, rp.damping, iters, out=out)          # warm-up
+    torch.cuda.synchronize()
+    reps = max(1, args.steps)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        bt.run(X, rp.damping, iters, out=out)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    labels_b, ns_b, iters_b = out
+    # the plain path, one problem after another, with one reused workspace and S buffer
+    nmax = max(sizes)
+    S = torch.empty((nmax, nmax), dtype=torch.float32, device=dev)
+    ws = torch.empty(hap.workspace_size(nmax, L, hap.HAP_F32), dtype=torch.uint8, device=dev)
+    agree, ns_rel = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for bidx, prob in enumerate(problems):
+        n = sizes[bidx]
+        o = bt.offsets[bidx]
+        Sv = S[:n, :n]
+        hap.build_similarity(X[o:o + n], Sv)
+        h = hap.Hap(Sv, L, rp.damping, workspace=ws)
+        h.set_launch(rows_per_block=1)     # column sums in row order, as inside the batch
+        h.iterate(iters, 0)
+        lab = h.labels()
+        ns = h.net_similarity(-1)
+        h.close()
+        agree.append((lab == bt.labels_of(labels_b, bidx)).float().mean().item())
+        ns_rel.append(abs(ns - ns_b[bidx, L].item()) / abs(ns))
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    upd = float(sum(n * n for n in sizes)) * L * iters
+    bt.close()
+    return {"form": "batched", "workload": f"{len(sizes)} problems, N ~ U{{64..2048}}, d=16, L={L}, "
+            f"damping {rp.damping}, {iters} iterations", "sum_n2": int(sum(n * n for n in sizes)),
+            "launch": {"threads": shape[0], "workgroups": shape[1]},
+            "batched_s": t_batch, "plain_s": t_plain, "speedup_vs_plain": t_plain / t_batch,
+            "batched_updates_per_s": upd / t_batch, "plain_updates_per_s": upd / t_plain,
+            "label_agreement_min": min(agree), "label_agreement_mean": float(np.mean(agree)),
+            "problems_identical_labels": int(sum(a == 1.0 for a in agree)),
+            "net_similarity_rel_diff_max": max(ns_rel)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,8 +215,9 @@ def main() -> int:
     ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration under rocprofv3)")
-    ap.add_argument("--form", choices=["plain", "precision"], default="plain",
-                    help="plain: the headline line; precision: the similarity build forms")
+    ap.add_argument("--form", choices=["plain", "precision", "batched"], default="plain",
+                    help="plain: the headline line; precision: the similarity build forms; "
+                         "batched: many problems in one launch")
     ap.add_argument("--form-iters", type=int, default=0, help="iterations for a form run (0 = the workload's)")
     args = ap.parse_args()
 
@@ -176,6 +237,9 @@ def main() -> int:
     hap.load()
     if args.form == "precision":
         print(json.dumps(run_precision_form(args, torch, hap, synth)), flush=True)
+        return 0
+    if args.form == "batched":
+        print(json.dumps(run_batched_form(args, torch, hap, synth)), flush=True)
         return 0
     dev = torch.device("cuda:0")
     blobs, rp = synth.workload_plain_f32()

@@ -209,6 +209,42 @@ HAP_API hap_status hap_profile_read(hap_ctx *ctx, double *row_pass_ms, int64_t *
 
 HAP_API hap_status hap_destroy(hap_ctx *ctx);
 
+/*
+ * Batched form: many independent HAP problems of up to 2048 points each (FP32), run
+ * by ONE persistent kernel launch in which every workgroup takes whole problems from
+ * a queue (largest first) and performs the similarity build (as HAP_BUILD_DIRECT),
+ * the median preference, the Algorithm 1 initial state, the sweeps, the final labels
+ * (Eq. 2.8) and the FP64 net similarity.  Problem b is point rows
+ * [off_b, off_b + n[b]) of the packed X (off_b = n[0] + ... + n[b-1]).
+ *
+ * hap_batch_create plans the batch (offsets, queue order) and copies the plan into
+ * the workspace (device, hap_batch_workspace_size bytes, 256-byte aligned, owned by the
+ * caller; NULL = the library allocates); it synchronises the stream.  d <= 32.
+ */
+typedef struct hap_batch hap_batch;
+HAP_API hap_status hap_batch_workspace_size(int32_t count, const int32_t *n, int64_t d, int32_t levels,
+                                            size_t *bytes);
+HAP_API hap_status hap_batch_create(hap_batch **out, int32_t count, const int32_t *n /* host [count] */,
+                                    int64_t d, int32_t levels, void *workspace, size_t workspace_bytes,
+                                    void *stream);
+/*
+ * Run the whole batch: X device FP32 (sum n) x d row-major; labels device int32,
+ * problem b's labels at [levels * off_b, levels * (off_b + n[b])) level-major (level l,
+ * point i at levels*off_b + l*n[b] + i); net_similarity device double [count][levels+1]
+ * (per level, then the total); iters device int32 [count] (iterations performed, the
+ * stop iteration after an early stop).  Launches two kernels and nothing else: no
+ * allocation, no copy, no synchronisation, so the call can be captured in a graph.
+ * A second run of the same batch starts again from the initial state.
+ */
+HAP_API hap_status hap_batch_run(hap_batch *batch, const void *X, double damping, int32_t max_iters,
+                                 int32_t stable_iters, int32_t *labels, double *net_similarity, int32_t *iters,
+                                 void *stream);
+/* Launch shape of the persistent kernel: threads per workgroup (256 or 512) and the
+ * number of workgroups (>= 1).  0 keeps the current value.  For the autotuner. */
+HAP_API hap_status hap_batch_set_launch(hap_batch *batch, int32_t threads, int32_t workgroups);
+HAP_API hap_status hap_batch_get_launch(hap_batch *batch, int32_t *threads, int32_t *workgroups);
+HAP_API hap_status hap_batch_destroy(hap_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,365 @@
+// Batched HAP: many independent instances of up to 2048 points in ONE persistent launch.
+//
+// Every workgroup pulls instances from an atomic queue (the host orders them by
+// decreasing size, so the largest start first) and runs each one completely: the
+// similarity build (FP64-accumulated, as HAP_BUILD_DIRECT), the median preference
+// (radix select in LDS), the Algorithm 1 initial state, the sweeps (the same fused row
+// pass as the single-problem path, over all rows of the instance, so the column partials
+// are complete column sums in row order), the labels of the final iteration (Eq. 2.8) and
+// the FP64 net similarity.  A workgroup never waits for another one, so there is no
+// inter-workgroup dependency and nothing to deadlock; every workgroup exits once the
+// queue is empty.
+#include "rowpass.h"
+
+namespace hap {
+
+struct BatchArgs {
+    const float *X;
+    int64_t d;
+    const BatchDesc *desc;
+    const int *order;       // instances in the order they are handed out
+    int count;
+    int levels;
+    float lam, oml;
+    int max_iters, stable_iters;
+    float *wsf;             // float workspace
+    int32_t *wsi;           // int workspace
+    int32_t *queue;         // [0]: next index handed out
+    int32_t *labels;        // output labels
+    double *ns;             // [count][levels + 1]
+    int32_t *iters;         // [count]
+};
+
+namespace {
+
+constexpr int kBins = 2048;
+
+__device__ __forceinline__ unsigned int fkey(float f) {
+    const unsigned int u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float fval(unsigned int k) {
+    return __uint_as_float((k & 0x80000000u) ? (k ^ 0x80000000u) : ~k);
+}
+
+template <int NT>
+__device__ void build_instance(const float *__restrict__ X, int64_t d, int n, int ld, float *__restrict__ S,
+                               double *xs /* LDS [64 * d] */) {
+#pragma clang fp contract(off)
+    // thread t computes column j = t + NT*c; the rows come through LDS in blocks of 64
+    for (int j0 = 0; j0 < n; j0 += NT) {
+        const int j = j0 + threadIdx.x;
+        for (int i0 = 0; i0 < n; i0 += 64) {
+            const int rows = min(64, n - i0);
+            __syncthreads();
+            for (int e = threadIdx.x; e < rows * d; e += NT) xs[e] = (double)X[(int64_t)(i0 + e / d) * d + e % d];
+            __syncthreads();
+            if (j < n) {
+                const float *xj = X + (int64_t)j * d;
+                for (int r = 0; r < rows; ++r) {
+                    double acc = 0.0;
+                    for (int k = 0; k < d; ++k) {
+                        const double df = xs[r * d + k] - (double)xj[k];
+                        const double sq = df * df;
+                        acc = acc + sq;
+                    }
+                    const int i = i0 + r;
+                    S[(int64_t)i * ld + j] = (i == j) ? 0.f : (float)(-acc);
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Median of the off-diagonal entries: mean of the two middle order statistics (FP64),
+// rounded to FP32.  Radix select on order-preserving keys with an LDS histogram.
+template <int NT>
+__device__ float median_instance(const float *__restrict__ S, int n, int ld, unsigned int *hist, int *sh) {
+    const long long M = (long long)n * (n - 1);
+    long long krem = M / 2 - 1;
+    unsigned int prefix = 0, mask = 0;
+    long long eqcount = 0;
+    int hi = 32;
+    while (hi > 0) {
+        const int width = hi >= 11 ? 11 : hi;
+        const int shift = hi - width;
+        for (int b = threadIdx.x; b < kBins; b += NT) hist[b] = 0u;
+        __syncthreads();
+        for (long long e = threadIdx.x; e < (long long)n * n; e += NT) {
+            const int i = (int)(e / n), j = (int)(e % n);
+            if (i == j) continue;
+            const unsigned int k = fkey(S[(int64_t)i * ld + j]);
+            if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & ((1u << width) - 1u)], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            long long cum = 0;
+            for (int b = 0; b < (1 << width); ++b) {
+                const long long c = hist[b];
+                if (krem < cum + c) {
+                    sh[0] = b;
+                    sh[1] = (int)(krem - cum);
+                    sh[2] = (int)c;
+                    break;
+                }
+                cum += c;
+            }
+        }
+        __syncthreads();
+        prefix |= ((unsigned int)sh[0]) << shift;
+        mask |= ((1u << width) - 1u) << shift;
+        krem = sh[1];
+        eqcount = sh[2];
+        __syncthreads();
+        hi = shift;
+    }
+    const float lo = fval(prefix);
+    float hi_v = lo;
+    if (krem + 1 >= eqcount) {
+        // smallest key above the selected one
+        if (threadIdx.x == 0) hist[0] = 0xFFFFFFFFu;
+        __syncthreads();
+        unsigned int best = 0xFFFFFFFFu;
+        for (long long e = threadIdx.x; e < (long long)n * n; e += NT) {
+            const int i = (int)(e / n), j = (int)(e % n);
+            if (i == j) continue;
+            const unsigned int k = fkey(S[(int64_t)i * ld + j]);
+            if (k > prefix && k < best) best = k;
+        }
+        atomicMin(&hist[0], best);
+        __syncthreads();
+        hi_v = fval(hist[0]);
+        __syncthreads();
+    }
+    return (float)(((double)lo + (double)hi_v) / 2.0);
+}
+
+template <int NT, int CH>
+__global__ __launch_bounds__(NT) void batch_kernel(BatchArgs g) {
+#pragma clang fp contract(off)
+    using V = Vec<float>::type;
+    constexpr int VW = 4;
+    constexpr int NW = NT / 64;
+    __shared__ float sh_m1[2][NW], sh_m2[2][NW], sh_cv[2][NW];
+    __shared__ int sh_k1[2][NW], sh_ck[2][NW];
+    __shared__ unsigned int hist[kBins];
+    __shared__ double xs[64 * 32];
+    __shared__ int sh[4];
+    __shared__ double shd[NW];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int L = g.levels;
+    for (;;) {
+        if (tid == 0) sh[3] = atomicAdd(g.queue, 1);
+        __syncthreads();
+        const int q = sh[3];
+        __syncthreads();
+        if (q >= g.count) break;
+        const int b = g.order[q];
+        const BatchDesc D = g.desc[b];
+        const int n = D.n, ld = D.ld;
+        float *S = g.wsf + D.w_off;
+        float *RA = S + (int64_t)n * ld;                       // per level: R then A
+        float *vec = RA + (int64_t)2 * L * n * ld;             // per level: pref, Q, phi, tau, C, B
+        int32_t *E = g.wsi + D.i_off;
+        DevState *ds = (DevState *)(E + (int64_t)L * ld);
+        auto R = [&](int l) { return RA + (int64_t)(2 * l) * n * ld; };
+        auto A = [&](int l) { return RA + (int64_t)(2 * l + 1) * n * ld; };
+        auto vp = [&](int l, int k) { return vec + (int64_t)(6 * l + k) * ld; };
+
+        // 1. similarity and preference
+        build_instance<NT>(g.X + D.x_off * g.d, g.d, n, ld, S, xs);
+        const float p = median_instance<NT>(S, n, ld, hist, sh);
+        // 2. Algorithm 1 initial state (alpha = rho = 0, phi = c = 0; tau^1 is never read and
+        //    tau^l is written before it is read); padding columns of alpha hold -inf
+        for (int l = 0; l < L; ++l) {
+            float *Rl = R(l), *Al = A(l);
+            for (int64_t e = tid; e < (int64_t)n * ld; e += NT) {
+                Rl[e] = 0.f;
+                Al[e] = ((int)(e % ld) < n) ? 0.f : neg_inf<float>();
+            }
+            for (int j = tid; j < ld; j += NT) {
+                vp(l, 0)[j] = (j < n) ? p : 0.f;
+                for (int k = 1; k < 6; ++k) vp(l, k)[j] = 0.f;
+                E[(int64_t)l * ld + j] = 0;
+            }
+        }
+        if (tid == 0) {
+            ds->t = ds->stable = ds->done = ds->stop_iter = ds->changed = ds->final_changed = 0;
+        }
+        __syncthreads();
+        // 3. sweeps
+        int t = 0, stable = 0, stop_iter = -1;
+        for (int it = 0; it < g.max_iters; ++it) {
+            t += 1;
+            for (int l = 0; l < L; ++l) {
+                SweepArgs<float> a;
+                a.S = S;
+                a.lds = ld;
+                a.R = R(l);
+                a.A = A(l);
+                a.ldw = ld;
+                a.pref = vp(l, 0);
+                a.C = vp(l, 4);
+                a.phi_down = l > 0 ? vp(l - 1, 2) : nullptr;
+                a.B = vp(l, 5);
+                a.tau = l > 0 ? vp(l, 3) : nullptr;
+                a.E = E + (int64_t)l * ld;
+                a.Qpart = nullptr;
+                a.n = n;
+                a.rb = n;
+                a.lam = g.lam;
+                a.oml = g.oml;
+                a.ds = ds;
+                V Bv[CH], qv[CH];
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    const int j0 = c * NT * VW + tid * VW;
+                    Bv[c] = (t > 1 && j0 < n) ? *(const V *)(a.B + j0) : (V)(0.f);
+                    qv[c] = (V)(0.f);
+                }
+                if (t == 1)
+                    sweep_rows<float, NT, CH, true, true>(a, t, 0, n, Bv, qv, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
+                else
+                    sweep_rows<float, NT, CH, false, true>(a, t, 0, n, Bv, qv, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
+                __syncthreads();   // c^l, phi^{l-1}, labels of every row are written
+                // column sums (complete, in row order), tau^{l+1}, B^{l-1} and B^l at the top
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    const int j0 = c * NT * VW + tid * VW;
+                    if (j0 >= n) continue;
+                    *(V *)(vp(l, 1) + j0) = qv[c];
+                    if (l + 1 < L) *(V *)(vp(l + 1, 3) + j0) = *(const V *)(vp(l, 4) + j0) + qv[c];
+                    if (l == L - 1) *(V *)(vp(l, 5) + j0) = qv[c];
+                    if (l > 0)
+                        *(V *)(vp(l - 1, 5) + j0) =
+                            (*(const V *)(vp(l - 1, 4) + j0) + *(const V *)(vp(l - 1, 2) + j0)) +
+                            *(const V *)(vp(l - 1, 1) + j0);
+                }
+                __syncthreads();
+            }
+            // stop rule: the row pass of iteration t compared the labels of iteration t-1
+            if (t >= 2) {
+                const int lit = t - 1;
+                stable = (lit >= 2 && !ds->changed) ? stable + 1 : 0;
+            }
+            __syncthreads();
+            if (tid == 0) ds->changed = 0;
+            if (g.stable_iters > 0 && stable >= g.stable_iters) {
+                stop_iter = t - 1;
+                break;
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+        // 4. labels: those recorded by the last row pass after an early stop, otherwise the
+        //    labels of iteration t from alpha^t finished on the fly (nothing written)
+        int32_t *out = g.labels + D.out_off;
+        for (int l = 0; l < L; ++l) {
+            if (stop_iter >= 0) {
+                for (int i = tid; i < n; i += NT) out[(int64_t)l * n + i] = E[(int64_t)l * ld + i];
+                continue;
+            }
+            const float *Rl = R(l), *Al = A(l), *Bl = vp(l, 5);
+            for (int i = 0; i < n; ++i) {
+                float cv = neg_inf<float>();
+                int ck = INT_MAX;
+                for (int j = tid; j < n; j += NT) {
+                    const float rj = Rl[(int64_t)i * ld + j];
+                    float al = Al[(int64_t)i * ld + j];
+                    if (t >= 1) {
+                        const float ah = (j == i) ? Bl[j] - rj : fminf(0.f, Bl[j] - fmaxf(0.f, rj));
+                        al = g.lam * al + g.oml * ah;
+                    }
+                    const float x = al + rj;
+                    if (x > cv) {
+                        cv = x;
+                        ck = j;
+                    }
+                }
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) {
+                    const float ocv = __shfl_xor(cv, off, 64);
+                    const int ock = __shfl_xor(ck, off, 64);
+                    argmax_merge(cv, ck, ocv, ock);
+                }
+                if (lane == 0) {
+                    sh_cv[0][wid] = cv;
+                    sh_ck[0][wid] = ck;
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    cv = sh_cv[0][0];
+                    ck = sh_ck[0][0];
+                    for (int w = 1; w < NW; ++w) argmax_merge(cv, ck, sh_cv[0][w], sh_ck[0][w]);
+                    out[(int64_t)l * n + i] = ck;
+                }
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+        // 5. net similarity per level and total, FP64, fixed-order reduction
+        double total = 0.0;
+        for (int l = 0; l < L; ++l) {
+            double acc = 0.0;
+            for (int i = tid; i < n; i += NT) {
+                const int e = out[(int64_t)l * n + i];
+                if (e < 0 || e >= n)
+                    acc += __builtin_nan("");   // no valid exemplar (non-finite messages)
+                else
+                    acc += (e == i) ? (double)p : (double)S[(int64_t)i * ld + e];
+            }
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            if (lane == 0) shd[wid] = acc;
+            __syncthreads();
+            if (tid == 0) {
+                double s = 0.0;
+                for (int w = 0; w < NW; ++w) s += shd[w];
+                g.ns[(int64_t)b * (L + 1) + l] = s;
+                total += s;
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            g.ns[(int64_t)b * (L + 1) + L] = total;
+            g.iters[b] = stop_iter >= 0 ? stop_iter : t;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void batch_reset(int32_t *queue) { queue[0] = 0; }
+
+}  // namespace
+
+hipError_t launch_batch(const float *X, int64_t d, const BatchDesc *desc, const int *order, int count, int levels,
+                        double lam, int max_iters, int stable_iters, float *wsf, int32_t *wsi, int32_t *queue,
+                        int32_t *labels, double *ns, int32_t *iters, int threads, int workgroups, hipStream_t st) {
+    BatchArgs g;
+    g.X = X;
+    g.d = d;
+    g.desc = desc;
+    g.order = order;
+    g.count = count;
+    g.levels = levels;
+    g.lam = (float)lam;
+    g.oml = (float)(1.0 - lam);
+    g.max_iters = max_iters;
+    g.stable_iters = stable_iters;
+    g.wsf = wsf;
+    g.wsi = wsi;
+    g.queue = queue;
+    g.labels = labels;
+    g.ns = ns;
+    g.iters = iters;
+    hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, st, queue);
+    switch (threads) {
+        case 256: hipLaunchKernelGGL((batch_kernel<256, 2>), dim3(workgroups), dim3(256), 0, st, g); break;
+        case 512: hipLaunchKernelGGL((batch_kernel<512, 1>), dim3(workgroups), dim3(512), 0, st, g); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace hap

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -714,6 +715,172 @@ hap_status hap_destroy(hap_ctx *c) {
         if (e != hipSuccess && s == HAP_OK) s = fail_hip(e, "hap_destroy: hipFree");
     }
     delete c;
+    return s;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched form
+// ---------------------------------------------------------------------------
+struct hap_batch {
+    int count = 0, levels = 0;
+    int64_t d = 0;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool own_ws = false;
+    hap::BatchDesc *desc = nullptr;  // device
+    int *order = nullptr;            // device
+    int32_t *queue = nullptr;        // device
+    float *wsf = nullptr;
+    int32_t *wsi = nullptr;
+    int threads = 512, workgroups = 512;
+};
+
+namespace {
+
+struct BatchPlan {
+    std::vector<hap::BatchDesc> desc;
+    std::vector<int> order;
+    size_t off_desc, off_order, off_queue, off_f, off_i, total;
+};
+
+bool plan_batch(int32_t count, const int32_t *n, int64_t d, int32_t levels, BatchPlan &pl, std::string &err) {
+    if (count < 1 || !n || d < 1 || d > 32 || levels < 1 || levels > 64) {
+        err = "hap_batch: need count >= 1, 1 <= d <= 32, 1 <= levels <= 64";
+        return false;
+    }
+    pl.desc.resize(count);
+    int64_t xo = 0, fo = 0, io = 0, oo = 0;
+    for (int b = 0; b < count; ++b) {
+        if (n[b] < 2 || n[b] > 2048) {
+            err = "hap_batch: every problem needs 2 <= n <= 2048 points";
+            return false;
+        }
+        const int ld = (n[b] + 63) / 64 * 64;
+        hap::BatchDesc &D = pl.desc[b];
+        D.n = n[b];
+        D.ld = ld;
+        D.x_off = xo;
+        D.w_off = fo;
+        D.i_off = io;
+        D.out_off = oo;
+        xo += n[b];
+        fo += (hap::batch_floats(n[b], ld, levels) + 63) / 64 * 64;
+        io += (hap::batch_ints(ld, levels) + 63) / 64 * 64;
+        oo += (int64_t)levels * n[b];
+    }
+    pl.order.resize(count);
+    for (int b = 0; b < count; ++b) pl.order[b] = b;
+    // largest problems first (ties by index, so the order is deterministic)
+    std::sort(pl.order.begin(), pl.order.end(), [&](int a, int b) { return n[a] != n[b] ? n[a] > n[b] : a < b; });
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    pl.off_desc = take(sizeof(hap::BatchDesc) * count);
+    pl.off_order = take(sizeof(int) * count);
+    pl.off_queue = take(64);
+    pl.off_f = take((size_t)fo * 4);
+    pl.off_i = take((size_t)io * 4);
+    pl.total = off;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+hap_status hap_batch_workspace_size(int32_t count, const int32_t *n, int64_t d, int32_t levels, size_t *bytes) {
+    if (!bytes) return fail_arg("hap_batch_workspace_size: null pointer");
+    BatchPlan pl;
+    std::string err;
+    if (!plan_batch(count, n, d, levels, pl, err)) return fail_arg(err.c_str());
+    *bytes = pl.total;
+    return HAP_OK;
+}
+
+hap_status hap_batch_create(hap_batch **out, int32_t count, const int32_t *n, int64_t d, int32_t levels,
+                            void *workspace, size_t workspace_bytes, void *stream) {
+    if (!out) return fail_arg("hap_batch_create: null pointer");
+    *out = nullptr;
+    BatchPlan pl;
+    std::string err;
+    if (!plan_batch(count, n, d, levels, pl, err)) return fail_arg(err.c_str());
+    if (workspace && (workspace_bytes < pl.total || ((uintptr_t)workspace & (kAlign - 1)) != 0))
+        return fail_arg("hap_batch_create: workspace too small or not 256-byte aligned");
+    hap_batch *b = new (std::nothrow) hap_batch();
+    if (!b) return fail_arg("hap_batch_create: host allocation failed", HAP_E_OOM);
+    b->count = count;
+    b->levels = levels;
+    b->d = d;
+    if (workspace) {
+        b->ws = workspace;
+        b->ws_bytes = workspace_bytes;
+    } else {
+        if (hipMalloc(&b->ws, pl.total) != hipSuccess) {
+            (void)hipGetLastError();
+            delete b;
+            return fail_arg("hap_batch_create: hipMalloc of the workspace failed", HAP_E_OOM);
+        }
+        b->ws_bytes = pl.total;
+        b->own_ws = true;
+    }
+    char *base = (char *)b->ws;
+    b->desc = (hap::BatchDesc *)(base + pl.off_desc);
+    b->order = (int *)(base + pl.off_order);
+    b->queue = (int32_t *)(base + pl.off_queue);
+    b->wsf = (float *)(base + pl.off_f);
+    b->wsi = (int32_t *)(base + pl.off_i);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(b->desc, pl.desc.data(), sizeof(hap::BatchDesc) * count, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->order, pl.order.data(), sizeof(int) * count, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        hap_status s = fail_hip(e, "hap_batch_create");
+        if (b->own_ws) (void)hipFree(b->ws);
+        delete b;
+        return s;
+    }
+    *out = b;
+    return HAP_OK;
+}
+
+hap_status hap_batch_run(hap_batch *b, const void *X, double damping, int32_t max_iters, int32_t stable_iters,
+                         int32_t *labels, double *net_similarity, int32_t *iters, void *stream) {
+    if (!b || !X || !labels || !net_similarity || !iters) return fail_arg("hap_batch_run: null pointer");
+    if (!(damping >= 0.0 && damping < 1.0)) return fail_arg("hap_batch_run: damping must be in [0, 1)");
+    if (max_iters < 0 || stable_iters < 0) return fail_arg("hap_batch_run: negative count");
+    hipError_t e = hap::launch_batch((const float *)X, b->d, b->desc, b->order, b->count, b->levels, damping, max_iters,
+                                     stable_iters, b->wsf, b->wsi, b->queue, labels, net_similarity, iters, b->threads,
+                                     b->workgroups, (hipStream_t)stream);
+    if (e != hipSuccess) return fail_hip(e, "hap_batch_run");
+    return HAP_OK;
+}
+
+hap_status hap_batch_set_launch(hap_batch *b, int32_t threads, int32_t workgroups) {
+    if (!b) return fail_arg("hap_batch_set_launch: null pointer");
+    if (threads && threads != 256 && threads != 512) return fail_arg("hap_batch_set_launch: threads must be 256 or 512");
+    if (workgroups < 0) return fail_arg("hap_batch_set_launch: workgroups must be >= 1");
+    if (threads) b->threads = threads;
+    if (workgroups) b->workgroups = workgroups;
+    return HAP_OK;
+}
+
+hap_status hap_batch_get_launch(hap_batch *b, int32_t *threads, int32_t *workgroups) {
+    if (!b) return fail_arg("hap_batch_get_launch: null pointer");
+    if (threads) *threads = b->threads;
+    if (workgroups) *workgroups = b->workgroups;
+    return HAP_OK;
+}
+
+hap_status hap_batch_destroy(hap_batch *b) {
+    if (!b) return HAP_OK;
+    hap_status s = HAP_OK;
+    if (b->own_ws && hipFree(b->ws) != hipSuccess) s = fail_hip(hipGetLastError(), "hap_batch_destroy");
+    delete b;
     return s;
 }
 

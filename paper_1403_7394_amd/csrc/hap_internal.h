@@ -96,6 +96,29 @@ hipError_t launch_build(const void *X, int64_t n, int64_t d, int64_t ldx, int x_
                         int64_t lds, int s_dtype, int mode, double noise_rel, uint64_t seed,
                         hipStream_t st);
 
+// Batched form (batch.hip): one descriptor per instance.
+struct BatchDesc {
+    int64_t x_off;   // first row of the instance in the packed points
+    int64_t w_off;   // first float of the instance's workspace
+    int64_t i_off;   // first int of the instance's integer workspace
+    int64_t out_off; // first label of the instance in the output (levels x n, level-major)
+    int n;
+    int ld;          // padded row length (multiple of 64) of S, R, A
+};
+
+// Per-instance workspace (floats): S, then per level R, A, then per level the vectors
+// pref, Q, phi, tau, C, B.  Ints: per level E, then a DevState.
+__host__ __device__ inline int64_t batch_floats(int n, int ld, int levels) {
+    return (int64_t)n * ld * (1 + 2 * levels) + (int64_t)6 * levels * ld;
+}
+__host__ __device__ inline int64_t batch_ints(int ld, int levels) {
+    return (int64_t)levels * ld + (int64_t)(sizeof(DevState) / sizeof(int32_t));
+}
+
+hipError_t launch_batch(const float *X, int64_t d, const BatchDesc *desc, const int *order, int count, int levels,
+                        double lam, int max_iters, int stable_iters, float *wsf, int32_t *wsi, int32_t *queue,
+                        int32_t *labels, double *ns, int32_t *iters, int threads, int workgroups, hipStream_t st);
+
 void set_error(const std::string &msg);
 
 }  // namespace hap

@@ -1,0 +1,213 @@
+// Device code of the fused per-level row pass, shared by the sweep launches and the
+// batched persistent kernel.  See sweep.hip for the scheme (Eq. 2.1-2.6, Algorithm 1).
+#pragma once
+
+#include <climits>
+
+#include "hap_internal.h"
+
+namespace hap {
+
+template <typename T>
+struct SweepArgs {
+    const T *__restrict__ S;
+    int64_t lds;
+    T *__restrict__ R;
+    T *__restrict__ A;
+    int64_t ldw;
+    const T *__restrict__ pref;
+    T *C;                 // [ldw] c^l, written by the row pass
+    T *phi_down;          // phi^{l-1}, nullptr at l = 0
+    const T *__restrict__ B;    // B^{l,t-1}_j = c_j + phi_j + Q_j (Q_j at the top level), formed by the column sums
+    const T *__restrict__ tau;  // nullptr at l = 0 (tau^1 = +inf)
+    int32_t *E;
+    T *__restrict__ Qpart;
+    int n;
+    int rb;
+    T lam, oml;
+    DevState *ds;
+};
+
+// Merge two (max, argmax, second max) triples; the lower index wins a tie.
+template <typename T>
+__device__ __forceinline__ void top2_merge(T &m1, int &k1, T &m2, T om1, int ok1, T om2) {
+    const bool take = om1 > m1 || (om1 == m1 && ok1 < k1);
+    const T lo = take ? m1 : om1;     // the losing maximum competes for second place
+    m2 = fmax(take ? om2 : m2, lo);
+    m1 = take ? om1 : m1;
+    k1 = take ? ok1 : k1;
+}
+
+template <typename T>
+__device__ __forceinline__ void argmax_merge(T &v, int &k, T ov, int ok) {
+    const bool take = ov > v || (ov == v && ok < k);
+    v = take ? ov : v;
+    k = take ? ok : k;
+}
+
+template <typename T, bool WITH_C>
+__device__ __forceinline__ void wave_reduce(T &m1, int &k1, T &m2, T &cv, int &ck) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const T om1 = __shfl_xor(m1, off, 64);
+        const int ok1 = __shfl_xor(k1, off, 64);
+        const T om2 = __shfl_xor(m2, off, 64);
+        top2_merge(m1, k1, m2, om1, ok1, om2);
+        if constexpr (WITH_C) {
+            const T ocv = __shfl_xor(cv, off, 64);
+            const int ock = __shfl_xor(ck, off, 64);
+            argmax_merge(cv, ck, ocv, ock);
+        }
+    }
+}
+
+template <typename T, int NT, int NCH>
+struct RowRegs {
+    typename Vec<T>::type s[NCH], r[NCH], a[NCH];
+};
+
+// Columns j >= n: whole 16-byte vectors past n are not loaded (alpha reads as -inf so they
+// never win a maximum); inside the last partial vector the padding columns of A hold -inf
+// from initialisation and stay -inf or NaN, which '>' and fmax ignore.  Padding columns of
+// R, A and the column partials are never read back as results.
+template <typename T, int NT, int NCH, bool TAIL>
+__device__ __forceinline__ void load_row(const SweepArgs<T> &a, int i, RowRegs<T, NT, NCH> &x) {
+    using V = typename Vec<T>::type;
+    constexpr int VW = Vec<T>::N;
+    const T *Srow = a.S + (int64_t)i * a.lds;
+    const T *Rrow = a.R + (int64_t)i * a.ldw;
+    const T *Arow = a.A + (int64_t)i * a.ldw;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const int j0 = c * NT * VW + threadIdx.x * VW;
+        if (!TAIL || j0 < a.n) {
+            // S streams through once per level: non-temporal, so it does not displace R/A lines
+            x.s[c] = __builtin_nontemporal_load((const V *)(Srow + j0));
+            x.r[c] = *(const V *)(Rrow + j0);
+            x.a[c] = *(const V *)(Arow + j0);
+        } else {
+            x.s[c] = (V)(T(0));
+            x.r[c] = (V)(T(0));
+            x.a[c] = (V)(neg_inf<T>());
+        }
+    }
+}
+
+// The rows of one workgroup.  FIRST: iteration 1, alpha is the initial value (nothing to
+// finish, c and phi keep their initial 0).  TAIL: n is not exactly threads*chunks*VW, so
+// accesses past n are guarded (an exact fit needs no guard at all).
+template <typename T, int NT, int NCH, bool FIRST, bool TAIL>
+__device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, const int row0, const int row1,
+                                           const typename Vec<T>::type (&Bv)[NCH], typename Vec<T>::type (&qv)[NCH],
+                                           T (*sh_m1)[NT / 64], int (*sh_k1)[NT / 64], T (*sh_m2)[NT / 64],
+                                           T (*sh_cv)[NT / 64], int (*sh_ck)[NT / 64]) {
+#pragma clang fp contract(off)
+    using V = typename Vec<T>::type;
+    constexpr int VW = Vec<T>::N;
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int n = a.n;
+    const int64_t ldw = a.ldw;
+    const T lam = a.lam, oml = a.oml;
+    const T zero = T(0), ninf = neg_inf<T>();
+    const bool has_tau = a.tau != nullptr;
+
+    RowRegs<T, NT, NCH> x;
+    int buf = 0;
+    for (int i = row0; i < row1; ++i, buf ^= 1) {
+        load_row<T, NT, NCH, TAIL>(a, i, x);
+        T *Rrow = a.R + (int64_t)i * ldw;
+        T *Arow = a.A + (int64_t)i * ldw;
+        const T p_i = a.pref[i];
+        // Column indices are handled relative to this thread's base tid*VW: element (c, v) is
+        // column base + c*NT*VW + v, so compares and selects use compile-time offsets.
+        const int base = tid * VW;
+        int dcol = i - base;  // the diagonal sits at offset dcol
+        T m1 = ninf, m2 = ninf, cv = ninf;
+        int k1 = INT_MAX, ck = INT_MAX;   // offsets until the reduction
+        // phase 1: finish alpha^{t-1}, reduce c/e over alpha + rho and the top two of alpha + s
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int j0 = c * NT * VW + base;
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                const int j = c * NT * VW + v;
+                const bool diag = dcol == j;
+                const T sj = diag ? p_i : x.s[c][v];
+                x.s[c][v] = sj;
+                const T rj = x.r[c][v];
+                T al = x.a[c][v];
+                if constexpr (!FIRST) {
+                    const T Bj = Bv[c][v];
+                    const T ah = diag ? Bj - rj : fmin(zero, Bj - fmax(zero, rj));
+                    al = lam * al + oml * ah;
+                    x.a[c][v] = al;
+                    const T cx = al + rj;
+                    const bool g = cx > cv;
+                    cv = g ? cx : cv;
+                    ck = g ? j : ck;
+                }
+                const T y = al + sj;
+                const bool g1 = y > m1;
+                m2 = g1 ? m1 : fmax(m2, y);
+                k1 = g1 ? j : k1;
+                m1 = g1 ? y : m1;
+            }
+            if constexpr (!FIRST) {
+                if (!TAIL || j0 < n) __builtin_nontemporal_store(x.a[c], (V *)(Arow + j0));
+            }
+        }
+        k1 = (k1 == INT_MAX) ? INT_MAX : k1 + base;
+        ck = (ck == INT_MAX) ? INT_MAX : ck + base;
+        wave_reduce<T, !FIRST>(m1, k1, m2, cv, ck);
+        if (lane == 0) {
+            sh_m1[buf][wid] = m1;
+            sh_k1[buf][wid] = k1;
+            sh_m2[buf][wid] = m2;
+            if constexpr (!FIRST) {
+                sh_cv[buf][wid] = cv;
+                sh_ck[buf][wid] = ck;
+            }
+        }
+        __syncthreads();
+        m1 = sh_m1[buf][0];
+        k1 = sh_k1[buf][0];
+        m2 = sh_m2[buf][0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) top2_merge(m1, k1, m2, sh_m1[buf][w], sh_k1[buf][w], sh_m2[buf][w]);
+        if constexpr (!FIRST) {
+            if (tid == 0) {
+                cv = sh_cv[buf][0];
+                ck = sh_ck[buf][0];
+                for (int w = 1; w < NW; ++w) argmax_merge(cv, ck, sh_cv[buf][w], sh_ck[buf][w]);
+                a.C[i] = cv;
+                if (a.phi_down) a.phi_down[i] = m1;
+                const int old = a.E[i];
+                a.E[i] = ck;
+                if (t >= 3 && old != ck) atomicOr(&a.ds->changed, 1);
+            }
+        }
+        // phase 2: rho^t, column partials.  dcol is made opaque so the diagonal masks are
+        // recomputed here instead of being kept alive across the barrier.
+        asm volatile("" : "+v"(dcol));
+        const int k1r = k1 - base;
+        const T tau_i = has_tau ? a.tau[i] : zero;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int j0 = c * NT * VW + base;
+            V out;
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                const int j = c * NT * VW + v;
+                const T m = (j == k1r) ? m2 : m1;
+                const T rh = has_tau ? x.s[c][v] + fmin(tau_i, -m) : x.s[c][v] - m;
+                const T rn = lam * x.r[c][v] + oml * rh;
+                out[v] = rn;
+                qv[c][v] += (dcol == j) ? rn : fmax(zero, rn);
+            }
+            if (!TAIL || j0 < n) __builtin_nontemporal_store(out, (V *)(Rrow + j0));
+        }
+    }
+}
+
+}  // namespace hap

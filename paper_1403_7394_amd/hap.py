@@ -26,6 +26,8 @@ EXPORTS = (
     "hap_median_offdiag", "hap_workspace_size", "hap_init", "hap_iterate", "hap_exemplars",
     "hap_net_similarity", "hap_preference", "hap_read_messages", "hap_set_launch",
     "hap_get_launch", "hap_profile", "hap_profile_read", "hap_destroy",
+    "hap_batch_workspace_size", "hap_batch_create", "hap_batch_run", "hap_batch_set_launch",
+    "hap_batch_get_launch", "hap_batch_destroy",
 )
 
 
@@ -73,6 +75,12 @@ def _declare(lib):
         "hap_profile": (I32, [V, I32]),
         "hap_profile_read": (I32, [V, _c_dblp, ctypes.POINTER(I64), _c_dblp, ctypes.POINTER(I64)]),
         "hap_destroy": (I32, [V]),
+        "hap_batch_workspace_size": (I32, [I32, _c_i32p, I64, I32, ctypes.POINTER(SZ)]),
+        "hap_batch_create": (I32, [ctypes.POINTER(V), I32, _c_i32p, I64, I32, V, SZ, V]),
+        "hap_batch_run": (I32, [V, V, D, I32, I32, V, V, V, V]),
+        "hap_batch_set_launch": (I32, [V, I32, I32]),
+        "hap_batch_get_launch": (I32, [V, _c_i32p, _c_i32p]),
+        "hap_batch_destroy": (I32, [V]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -283,3 +291,82 @@ class Hap:
         _check("hap_get_launch", self._lib.hap_get_launch(self._ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
                                                           ctypes.byref(f)))
         return a.value, b.value, c.value, bool(f.value & LAUNCH_STREAM)
+
+
+class HapBatch:
+    """Many independent FP32 problems (2..2048 points each) run by one persistent launch.
+
+    sizes: list of point counts; X (run()): device FP32 tensor (sum(sizes), d), the problems'
+    points stacked in order.
+    """
+
+    def __init__(self, sizes, d: int, levels: int, workspace=None, stream=None):
+        import torch
+        lib = load()
+        self._lib = lib
+        self.sizes = [int(v) for v in sizes]
+        self.count = len(self.sizes)
+        self.d = int(d)
+        self.levels = int(levels)
+        self.offsets = [0]
+        for v in self.sizes:
+            self.offsets.append(self.offsets[-1] + v)
+        arr = (ctypes.c_int32 * self.count)(*self.sizes)
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        ws_ptr, ws_bytes = None, 0
+        if workspace is not None:
+            ws_ptr, ws_bytes = ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()
+            self._ws_keep = workspace
+        h = ctypes.c_void_p()
+        _check("hap_batch_create", lib.hap_batch_create(ctypes.byref(h), self.count, arr, self.d, self.levels,
+                                                        ws_ptr, ws_bytes, ctypes.c_void_p(self._stream.cuda_stream)))
+        self._h = h
+
+    @staticmethod
+    def workspace_size(sizes, d, levels) -> int:
+        lib = load()
+        arr = (ctypes.c_int32 * len(sizes))(*[int(v) for v in sizes])
+        b = ctypes.c_size_t()
+        _check("hap_batch_workspace_size", lib.hap_batch_workspace_size(len(sizes), arr, d, levels, ctypes.byref(b)))
+        return b.value
+
+    def outputs(self, device):
+        """Fresh output tensors: labels, net similarity, iterations."""
+        import torch
+        labels = torch.empty(self.levels * self.offsets[-1], dtype=torch.int32, device=device)
+        ns = torch.empty((self.count, self.levels + 1), dtype=torch.float64, device=device)
+        iters = torch.empty(self.count, dtype=torch.int32, device=device)
+        return labels, ns, iters
+
+    def run(self, X, damping, max_iters, stable_iters=0, out=None, stream=None):
+        import torch
+        labels, ns, iters = out if out is not None else self.outputs(X.device)
+        st = stream if stream is not None else torch.cuda.current_stream()
+        P = lambda t: ctypes.c_void_p(t.data_ptr())
+        _check("hap_batch_run", self._lib.hap_batch_run(self._h, P(X), float(damping), int(max_iters), int(stable_iters),
+                                                        P(labels), P(ns), P(iters), ctypes.c_void_p(st.cuda_stream)))
+        return labels, ns, iters
+
+    def labels_of(self, labels, b):
+        """(levels, n_b) view of problem b's labels."""
+        o, n = self.offsets[b], self.sizes[b]
+        return labels[self.levels * o: self.levels * (o + n)].view(self.levels, n)
+
+    def set_launch(self, threads=0, workgroups=0):
+        _check("hap_batch_set_launch", self._lib.hap_batch_set_launch(self._h, threads, workgroups))
+
+    def get_launch(self):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check("hap_batch_get_launch", self._lib.hap_batch_get_launch(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check("hap_batch_destroy", self._lib.hap_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

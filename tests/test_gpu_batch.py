@@ -1,0 +1,114 @@
+"""Batched form: many independent problems in one persistent launch, against the oracle.
+
+Inside the batch one workgroup owns a whole problem, so its column sums run in row order
+and every problem's FP32 trajectory is the oracle's evaluated in FP32, rounding for
+rounding: labels and net similarities are compared exactly (net similarity to 1e-12, the
+FP64 summation order differing).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import hap_ref
+from oracle import similarity as sim
+from paper_1403_7394_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _problems(sizes, d=16, seed=300):
+    out = []
+    for k, n in enumerate(sizes):
+        b = synth.gaussian_blobs(seed + k, n, d, 3 + k % 7, centre="uniform", centre_scale=10.0, sigma_lo=1.0,
+                                 sigma_hi=1.0, sizes="multinomial", dtype=np.float32)
+        out.append(b.X)
+    return out
+
+
+def _oracle(X, L, lam, T, K=0):
+    S32 = sim.similarity(X).astype(np.float32)
+    p = sim.median_offdiag(S32, np.float32)
+    r = hap_ref.hap(S32, p, L, lam, T, stable_iters=K, dtype=np.float32)
+    ns = [sim.net_similarity(S32, p, r.labels[l]) for l in range(L)]
+    return r, ns
+
+
+def _run_batch(hap, Xs, L, lam, T, K=0, launch=None):
+    sizes = [x.shape[0] for x in Xs]
+    X = torch.from_numpy(np.concatenate(Xs)).to(DEV)
+    bt = hap.HapBatch(sizes, Xs[0].shape[1], L)
+    if launch:
+        bt.set_launch(*launch)
+    labels, ns, iters = bt.run(X, lam, T, K)
+    torch.cuda.synchronize()
+    out = [bt.labels_of(labels, b).cpu().numpy() for b in range(len(sizes))], ns.cpu().numpy(), iters.cpu().numpy()
+    bt.close()
+    return out
+
+
+def test_batch_matches_fp32_oracle_exactly(hap_gpu):
+    sizes = [257, 64, 700, 2, 130, 1031, 96]
+    Xs = _problems(sizes)
+    L, lam, T = 3, 0.8, 30
+    labels, ns, iters = _run_batch(hap_gpu, Xs, L, lam, T)
+    for b, X in enumerate(Xs):
+        r, ns_ref = _oracle(X, L, lam, T)
+        assert np.array_equal(labels[b], r.labels), b
+        assert iters[b] == T
+        for l in range(L):
+            assert abs(ns[b, l] - ns_ref[l]) <= 1e-12 * abs(ns_ref[l]) + 1e-300, (b, l)
+        assert abs(ns[b, L] - sum(ns[b, :L])) <= 1e-12 * abs(ns[b, L])
+
+
+def test_batch_stop_rule_matches_oracle(hap_gpu):
+    Xs = _problems([60, 90, 200], d=4, seed=400)
+    L, lam, K = 1, 0.9, 20
+    labels, ns, iters = _run_batch(hap_gpu, Xs, L, lam, 800, K)
+    for b, X in enumerate(Xs):
+        r, _ = _oracle(X, L, lam, 800, K)
+        assert r.converged
+        assert iters[b] == r.iters, b
+        assert np.array_equal(labels[b], r.labels), b
+
+
+@pytest.mark.parametrize("launch", [(256, 1), (512, 3), (256, 1000)])
+def test_batch_launch_shapes_agree(hap_gpu, launch):
+    Xs = _problems([300, 33, 1500, 64, 512], seed=500)
+    base = _run_batch(hap_gpu, Xs, 3, 0.8, 12)
+    got = _run_batch(hap_gpu, Xs, 3, 0.8, 12, launch=launch)
+    for b in range(len(Xs)):
+        assert np.array_equal(base[0][b], got[0][b])
+    assert np.array_equal(base[1], got[1]) and np.array_equal(base[2], got[2])
+
+
+def test_batch_graph_capture_replays(hap_gpu):
+    """hap_batch_run launches kernels only, so it can be captured; every replay (with other
+    GPU work and synchronisations between replays) reproduces the eager result."""
+    Xs = _problems([400, 77, 1200], seed=600)
+    sizes = [x.shape[0] for x in Xs]
+    X = torch.from_numpy(np.concatenate(Xs)).to(DEV)
+    bt = hap_gpu.HapBatch(sizes, 16, 3)
+    eager = [t.clone() for t in bt.run(X, 0.8, 15)]
+    torch.cuda.synchronize()
+    out = bt.outputs(DEV)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        bt.run(X, 0.8, 15, out=out, stream=s)     # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        bt.run(X, 0.8, 15, out=out, stream=s)
+    for _ in range(3):
+        for t in out:
+            t.fill_(-7) if t.dtype != torch.float64 else t.fill_(-7.0)
+        junk = torch.randn(1 << 20, device=DEV).sum()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b_ in zip(out, eager):
+            assert torch.equal(a, b_)
+        assert torch.isfinite(junk)
+    bt.close()

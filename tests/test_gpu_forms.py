@@ -7,9 +7,11 @@ Error bounds are derived from each build's arithmetic (u = 2^-24, FP32 unit roun
               of the rounded points: S is the FP32 distance of the rounded points, so
               |dS| <= 2 |x_i - x_j| |d_i - d_j| + |d_i - d_j|^2 + (d + 4) u (n_i + n_j),
               with |d_i| <= 2^-8 |x_i|.
-  BF16x3      x = hi + lo + r, |x - hi| <= 2^-8 |x|, |r| <= 2^-8 |x - hi| <= 2^-16 |x|; r and the
-              dropped lo.lo term change g by at most 4 * 2^-16 |x_i| |x_j|; three passes of d
-              FP32 accumulations: |dS| <= 8 * 2^-16 |x_i| |x_j| + (3d + 4) u (n_i + n_j).
+  BF16x3      x = hi + lo + r, |x - hi| <= 2^-8 |x|, |r| <= 2^-8 |x - hi| <= 2^-16 |x|.  With the
+              norms n^_i = sum(hi^2 + 2 hi lo) the build gives exactly
+              -|x^_i - x^_j|^2 + |lo_i - lo_j|^2 (x^ = hi + lo) before FP32 rounding, so
+              |dS| <= 2 dist 2^-16 (|x_i| + |x_j|) + 2^-16 (|x_i| + |x_j|)^2 (1 + 2^-15)
+                      + (3d + 4) u (n_i + n_j).
   GEMM FP64   (d + 4) 2^-53 (n_i + n_j).
 """
 import numpy as np
@@ -53,7 +55,9 @@ def test_gram_builds_within_derived_bounds(hap_gpu, n, d, seed):
     assert np.all(np.abs(got - ref) <= 2 * dist * dlt + dlt ** 2 + (d + 4) * U32 * norm_sum)
 
     got3 = _build(hap_gpu, X, hap_gpu.BUILD_BF16X3)
-    assert np.all(np.abs(got3 - ref) <= 8 * 2.0 ** -16 * np.outer(xn, xn) + (3 * d + 4) * U32 * norm_sum)
+    xs = xn[:, None] + xn[None, :]
+    bound3 = 2 * dist * 2.0 ** -16 * xs + 2.0 ** -16 * xs ** 2 * (1 + 2.0 ** -15) + (3 * d + 4) * U32 * norm_sum
+    assert np.all(np.abs(got3 - ref) <= bound3)
     # the split-precision build is much closer than a single BF16 pass
     assert np.max(np.abs(got3 - ref)) < np.max(np.abs(got - ref)) / 16
 
