@@ -34,24 +34,31 @@ METRIC = "HAP N²·L message updates/s and time-to-converge vs plain, same GPU"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "row_pass_traffic_plain8192.json")
 SWEEP_SRC = os.path.join(ROOT, "paper_1403_7394_amd", "csrc", "sweep.hip")
+ROWPASS_SRC = os.path.join(ROOT, "paper_1403_7394_amd", "csrc", "rowpass.h")
 
 
-def sweep_source_hash() -> str:
-    with open(SWEEP_SRC, "rb") as f:
+def _hash16(path: str) -> str:
+    with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(bytes_per_launch_alg):
-    """HBM bytes per row-pass launch from the committed counter summary, if it was taken
-    on the current kernel source; otherwise None."""
+def measured_traffic(first_launches: int, steady_launches: int):
+    """HBM bytes per row-pass launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE scaled by a 1 GiB device copy), weighted over this run's first-sweep and
+    later launches; None unless the counters were taken on the current kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("sweep_source_sha256_16") != sweep_source_hash():
+    if (t.get("sweep_source_sha256_16") != _hash16(SWEEP_SRC)
+            or t.get("rowpass_source_sha256_16") != _hash16(ROWPASS_SRC)):
         return None
-    return t.get("hbm_bytes_per_launch")
+    total = first_launches + steady_launches
+    if total == 0:
+        return None
+    return (first_launches * t["hbm_bytes_per_launch_first"]
+            + steady_launches * t["hbm_bytes_per_launch_steady"]) / total
 
 
 def cpu_baseline(X, rp, sweeps: int = 2):
@@ -295,7 +302,7 @@ def main() -> int:
     bytes_per_launch = alg_bytes_total / max(row_n, 1)
     avg_launch_s = row_ms / max(row_n, 1) * 1e-3
     achieved = bytes_per_launch / avg_launch_s / 1e9
-    traffic = measured_traffic(bytes_per_launch)
+    traffic = measured_traffic(first_sweeps * L, row_n - first_sweeps * L)
     ms_per_step = elapsed / args.steps * 1e3
     value = n * n * L * sweeps / elapsed
 
