@@ -12,4 +12,6 @@ Contents
   ap_ref      plain Affinity Propagation (Frey and Dueck, 2007), written separately
   brute       exhaustive exemplar-set search for tiny inputs
   similarity  FP64 similarity, tie-break noise, median preference, net similarity
+  warm        learned warm start: per-point features, FP64 perceptron with backpropagation
+              and Adam, warm initial availabilities, warm run with cold fallback
 """

@@ -1,4 +1,5 @@
-"""Seeded synthetic inputs for HAP (Gaussian point blobs and small integer matrices).
+"""Seeded synthetic inputs for HAP (Gaussian point blobs, small integer matrices, initial
+perceptron parameters and minibatch orders for the warm start).
 
 This module only draws random numbers; it holds none of the method's arithmetic
 (no similarity, no preference, no message update).  The oracle side and the HIP
@@ -164,3 +165,25 @@ def integer_matrix(seed: int, n: int, lo: int = -20, hi: int = -1) -> np.ndarray
 def integer_vector(seed: int, n: int, lo: int = -20, hi: int = -1) -> np.ndarray:
     rng = _rng(seed + 7919)
     return rng.integers(lo, hi + 1, size=n).astype(np.float64)
+
+
+def mlp_init(seed: int, n_in: int, hidden: int, n_out: int) -> np.ndarray:
+    """Initial perceptron parameters as one flat FP32 vector (W1, b1, W2, b2, W3, b3; weights
+    row-major): weights N(0, 2/fan_in), biases 0."""
+    rng = _rng(seed)
+    parts = []
+    for fan_in, fan_out in ((n_in, hidden), (hidden, hidden), (hidden, n_out)):
+        parts.append(rng.standard_normal(fan_in * fan_out) * np.sqrt(2.0 / fan_in))
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def minibatch_order(seed: int, rows: int, batch: int, steps: int) -> np.ndarray:
+    """Row indices for `steps` minibatches of `batch` rows (int32): concatenated random
+    permutations of range(rows), one per pass over the data."""
+    rng = _rng(seed)
+    need = batch * steps
+    out = []
+    while sum(len(o) for o in out) < need:
+        out.append(rng.permutation(rows))
+    return np.concatenate(out)[:need].astype(np.int32)
