@@ -197,7 +197,8 @@ def run_batched_form(args, torch, hap, synth) -> dict:
         lab = h.labels()
         ns = h.net_similarity(-1)
         h.close()
-        agree.append((lab == bt.labels_of(labels_b, bidx)).float().mean().item())
+        mism = int((lab != bt.labels_of(labels_b, bidx)).sum().item())
+        agree.append(1.0 - mism / lab.numel())
         ns_rel.append(abs(ns - ns_b[bidx, L].item()) / abs(ns))
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
@@ -209,8 +210,126 @@ def run_batched_form(args, torch, hap, synth) -> dict:
             "batched_s": t_batch, "plain_s": t_plain, "speedup_vs_plain": t_plain / t_batch,
             "batched_updates_per_s": upd / t_batch, "plain_updates_per_s": upd / t_plain,
             "label_agreement_min": min(agree), "label_agreement_mean": float(np.mean(agree)),
-            "problems_identical_labels": int(sum(a == 1.0 for a in agree)),
+            "problems_identical_labels": int(sum(a == 1.0 for a in agree)), "problems": len(sizes),
             "net_similarity_rel_diff_max": max(ns_rel)}
+
+
+def _ari(a, b) -> float:
+    """Adjusted Rand index of two labelings (pair-counting form, Hubert and Arabie 1985)."""
+    import numpy as np
+    _, ia = np.unique(a, return_inverse=True)
+    _, ib = np.unique(b, return_inverse=True)
+    cont = np.zeros((ia.max() + 1, ib.max() + 1), dtype=np.int64)
+    np.add.at(cont, (ia, ib), 1)
+    comb = lambda x: x * (x - 1) / 2.0
+    s_ij = comb(cont).sum()
+    s_a = comb(cont.sum(axis=1)).sum()
+    s_b = comb(cont.sum(axis=0)).sum()
+    tot = comb(float(len(a)))
+    exp = s_a * s_b / tot
+    mx = 0.5 * (s_a + s_b)
+    return float((s_ij - exp) / (mx - exp)) if mx != exp else 1.0
+
+
+def run_warm_form(args, torch, hap, synth) -> dict:
+    """Warm-start form: a perceptron trained on HAP runs of 2-D blob problems (8192 points,
+    k in {3, 8, 16, 32, 64}, 5 seeds each) predicts the warm initial availabilities of the
+    65536-point, 32-dimensional, 1024-blob workload; the warm run (with the cold start as
+    fallback) is compared with the cold run on the same GPU, at L = 3 (the workload's levels)
+    and at L = 1."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    blobs, rp = synth.workload_warm_eval()
+    n_eval = blobs.X.shape[0]
+    iters = args.form_iters if args.form_iters else rp.max_iters
+    K = rp.stable_iters
+    out = {"form": "warm", "workload": f"{n_eval} points, d=32, 1024 blobs, FP32, damping {rp.damping}, "
+           f"up to {iters} iterations or {K} stable; network trained on 25 runs of 8192 2-D points",
+           "levels": {}}
+    n_tr = 8192
+    S_tr = torch.empty((n_tr, n_tr), dtype=torch.float32, device=dev)
+    for L in (3, 1):
+        t0 = time.perf_counter()
+        ws = torch.empty(hap.workspace_size(n_tr, L, hap.HAP_F32), dtype=torch.uint8, device=dev)
+        Fs, Ts, conv_tr = [], [], 0
+        for k in (3, 8, 16, 32, 64):
+            for rep in range(5):
+                b = synth.workload_warm_train(k, rep, n=n_tr)
+                hap.build_similarity(torch.from_numpy(b.X).to(dev), S_tr)
+                h = hap.Hap(S_tr, L, rp.damping, workspace=ws)
+                res = h.iterate(iters, K)
+                conv_tr += int(res.converged)
+                Fs.append(h.warm_features())
+                Ts.append(h.warm_targets())
+                h.close()
+        del ws
+        F = torch.cat(Fs)
+        T = torch.cat(Ts)
+        torch.cuda.synchronize()
+        t_data = time.perf_counter() - t0
+        batch, steps = 4096, 3000
+        m = hap.Mlp(torch.from_numpy(synth.mlp_init(3000 + L, hap.WARM_FEATURES, 128, L)).to(dev),
+                    hap.WARM_FEATURES, 128, L, precision=hap.HAP_BF16)
+        idx = torch.from_numpy(synth.minibatch_order(4000 + L, F.shape[0], batch, steps)).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hist = m.train(F, T, idx, batch, steps, 1e-3)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        hist = hist.cpu().numpy()
+        del F, T, idx
+        print(json.dumps({"form": "warm", "levels": L, "train_runs_converged": conv_tr, "data_s": t_data,
+                          "train_s": t_train, "loss_first": float(hist[:50].mean()),
+                          "loss_last": float(hist[-50:].mean())}), file=sys.stderr, flush=True)
+
+        X = torch.from_numpy(blobs.X).to(dev)
+        S = torch.empty((n_eval, n_eval), dtype=torch.float32, device=dev)
+        hap.build_similarity(X, S)
+        ws = torch.empty(hap.workspace_size(n_eval, L, hap.HAP_F32), dtype=torch.uint8, device=dev)
+
+        def run(warm: bool):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h = hap.Hap(S, L, rp.damping, workspace=ws)
+            fell, t_pred = False, 0.0
+            if warm:
+                Y = m.forward(h.warm_features())
+                torch.cuda.synchronize()
+                t_pred = time.perf_counter() - t0
+                res, fell = h.iterate_warm(Y, iters, K)
+            else:
+                res = h.iterate(iters, K)
+            labels = h.labels().cpu().numpy()
+            counts = [h.exemplars(l)[1] for l in range(L)]
+            ns = [h.net_similarity(l) for l in range(L)]
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            h.close()
+            return dict(iters=res.iters, converged=res.converged, fell_back=fell, wall_s=wall,
+                        predict_s=t_pred, exemplars_per_level=counts, net_similarity=ns), labels
+
+        cold, lab_c = run(False)
+        print(json.dumps({"form": "warm", "levels": L, "cold": cold}), file=sys.stderr, flush=True)
+        warm_r, lab_w = run(True)
+        print(json.dumps({"form": "warm", "levels": L, "warm": warm_r}), file=sys.stderr, flush=True)
+        # sweeps performed: a converged run stops one sweep after its stop iteration
+        sw = lambda r: (r["iters"] + 1) if (r["converged"] and r["iters"] < iters) else r["iters"]
+        warm_sweeps = sw(warm_r) + (iters if warm_r["fell_back"] else 0)
+        out["levels"][str(L)] = {
+            "train": {"runs": 25, "runs_converged": conv_tr, "samples": 25 * n_tr, "batch": batch,
+                      "steps": steps, "lr": 1e-3, "precision": "bf16", "data_s": t_data, "train_s": t_train,
+                      "loss_first50": float(hist[:50].mean()), "loss_last50": float(hist[-50:].mean())},
+            "cold": cold, "warm": warm_r,
+            "sweeps_cold": sw(cold), "sweeps_warm_total": warm_sweeps,
+            "wall_ratio_warm_over_cold": warm_r["wall_s"] / cold["wall_s"],
+            "exemplar_agreement": [float(np.mean(lab_c[l] == lab_w[l])) for l in range(L)],
+            "adjusted_rand_index": [_ari(lab_c[l], lab_w[l]) for l in range(L)],
+            "net_similarity_rel_diff": [(a - b) / abs(b) for a, b in zip(warm_r["net_similarity"],
+                                                                       cold["net_similarity"])],
+        }
+        del S, ws, X, m
+        torch.cuda.empty_cache()
+    return out
 
 
 def main() -> int:
@@ -222,9 +341,9 @@ def main() -> int:
     ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration under rocprofv3)")
-    ap.add_argument("--form", choices=["plain", "precision", "batched"], default="plain",
+    ap.add_argument("--form", choices=["plain", "precision", "batched", "warm"], default="plain",
                     help="plain: the headline line; precision: the similarity build forms; "
-                         "batched: many problems in one launch")
+                         "batched: many problems in one launch; warm: the learned warm start")
     ap.add_argument("--form-iters", type=int, default=0, help="iterations for a form run (0 = the workload's)")
     args = ap.parse_args()
 
@@ -247,6 +366,9 @@ def main() -> int:
         return 0
     if args.form == "batched":
         print(json.dumps(run_batched_form(args, torch, hap, synth)), flush=True)
+        return 0
+    if args.form == "warm":
+        print(json.dumps(run_warm_form(args, torch, hap, synth)), flush=True)
         return 0
     dev = torch.device("cuda:0")
     blobs, rp = synth.workload_plain_f32()

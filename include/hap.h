@@ -245,6 +245,96 @@ HAP_API hap_status hap_batch_set_launch(hap_batch *batch, int32_t threads, int32
 HAP_API hap_status hap_batch_get_launch(hap_batch *batch, int32_t *threads, int32_t *workgroups);
 HAP_API hap_status hap_batch_destroy(hap_batch *batch);
 
+/*
+ * Learned warm start.  The paper starts every run from alpha = rho = 0 (Algorithm 1); the
+ * warm start replaces only the initial availabilities.  A network predicts, per point and
+ * level, y = g(v) with v = (alpha^l_jj + rho^l_jj) / |p_j| of a finished run and
+ * g(v) = sign(v) (sqrt(1 + |v|) - 1).  With rho = 0, Eq. 2.2-2.3 turn a column base
+ * B_j = g^-1(y) |p_j| (g^-1(y) = sign(y) |y| (|y| + 2), p the level's preference) into
+ * alpha_jj = B_j and alpha_ij = min(0, B_j); every other initial value stays as in
+ * Algorithm 1.
+ */
+#define HAP_WARM_FEATURES 32
+/*
+ * Per-point features of the context's S and level-1 preferences p (a = |p_i|), into F
+ * (device FP32, n rows of HAP_WARM_FEATURES, row stride ldf >= HAP_WARM_FEATURES):
+ *   [0,16)  the 16 largest off-diagonal s_ij of row i, descending (ties: lower j first), / a;
+ *           a row with fewer than 16 off-diagonal entries repeats its smallest one
+ *   16      p_i / a
+ *   17      #{j != i : s_ij > p_i} / (n - 1)
+ *   18      mean of the off-diagonal s_ij, / a
+ *   19      log(1 + #{j != i : s_ij > p_i}) / 10
+ *   20+m    log(1 + D_m) / 10, D_m = sum_{j != i} max(0, s_ij - 2^-m p_i) / a, m = 0..5
+ *   26+m    (D_m(i) - M_m(i)) / max(D_m(i), M_m(i)) (0 when both are 0), M_m(i) the largest
+ *           D_m(j) over the j of entries [0,16) (all j != i when n - 1 < 16)
+ * Needs n >= 2 and p_i != 0.  Uses the context's column-partial buffer as scratch (no
+ * iteration state is touched).  Synchronises the stream.
+ */
+HAP_API hap_status hap_warm_features(hap_ctx *ctx, float *F, int64_t ldf);
+/*
+ * Training targets of the current state: T[j*ldt + l] = g((alpha^l_jj + rho^l_jj) / |p^l_j|)
+ * with alpha^l the availabilities of the last completed iteration (device FP32, n rows,
+ * ldt >= levels).  Synchronises the stream.
+ */
+HAP_API hap_status hap_warm_targets(hap_ctx *ctx, float *T, int64_t ldt);
+/*
+ * Restart the context from the Algorithm 1 initial state (the preferences stay), with the
+ * warm initial availabilities of the network outputs Y (device FP32, n rows, Y[j*ldy + l]
+ * for level l, ldy >= levels), or the cold start when Y is NULL.  Synchronises the stream.
+ */
+HAP_API hap_status hap_set_warm_start(hap_ctx *ctx, const float *Y, int64_t ldy);
+/*
+ * Warm run with the cold start as fallback: hap_set_warm_start(Y), hap_iterate(max_iters,
+ * stable_iters); if that run does not converge (and Y is not NULL), restart cold and iterate
+ * again.  *fell_back (host, may be NULL) is 1 when the cold run's result is the one
+ * returned.  stable_iters >= 1.
+ */
+HAP_API hap_status hap_iterate_warm(hap_ctx *ctx, const float *Y, int64_t ldy, int32_t max_iters,
+                                    int32_t stable_iters, int32_t *iters_done, int32_t *converged,
+                                    int32_t *fell_back);
+
+/*
+ * The warm start's perceptron: n_in -> hidden -> hidden -> n_out, ReLU after both hidden
+ * layers: h1 = relu(X W1 + b1), h2 = relu(h1 W2 + b2), y = h2 W3 + b3.  Parameters are one
+ * flat FP32 device vector of hap_mlp_param_count floats: W1 (n_in x hidden, row-major), b1,
+ * W2 (hidden x hidden), b2, W3 (hidden x n_out), b3.  precision HAP_F32 multiplies FP32
+ * operands, HAP_BF16 rounds both operands of every product to BF16 (nearest even); both
+ * accumulate in FP32 on the matrix cores.  X, Y, T are device FP32 row-major with the given
+ * row strides.  The workspace (device, 256-byte aligned, caller-owned) holds the activations
+ * of `rows` rows: hap_mlp_workspace_size bytes.  Nothing synchronises the stream.
+ */
+HAP_API int64_t hap_mlp_param_count(int32_t n_in, int32_t hidden, int32_t n_out); /* -1 for bad sizes */
+HAP_API hap_status hap_mlp_workspace_size(int32_t n_in, int32_t hidden, int32_t n_out, int64_t rows, size_t *bytes);
+HAP_API hap_status hap_mlp_forward(const float *params, int32_t n_in, int32_t hidden, int32_t n_out,
+                                   int32_t precision, const float *X, int64_t ldx, int64_t rows, float *Y,
+                                   int64_t ldy, void *workspace, size_t workspace_bytes, void *stream);
+/*
+ * Loss = mean over rows and outputs of (y - t)^2 (written to *loss, device double) and its
+ * gradient with respect to every parameter (grad: device FP32, same layout as params).
+ */
+HAP_API hap_status hap_mlp_loss_grad(const float *params, int32_t n_in, int32_t hidden, int32_t n_out,
+                                     int32_t precision, const float *X, int64_t ldx, const float *T, int64_t ldt,
+                                     int64_t rows, float *grad, double *loss, void *workspace,
+                                     size_t workspace_bytes, void *stream);
+/*
+ * One Adam step (Kingma and Ba, 2015) on count parameters: opt_state (device FP32, 2*count:
+ * first moments, then second moments; zero before step 1), step >= 1 (bias corrections
+ * 1 - beta^step).
+ */
+HAP_API hap_status hap_mlp_adam(float *params, const float *grad, float *opt_state, int64_t count, int64_t step,
+                                double lr, double beta1, double beta2, double eps, void *stream);
+/*
+ * Minibatch training: step s = 0..steps-1 gathers the rows idx[s*batch .. (s+1)*batch) of
+ * X and T (device int32; an index outside [0, rows) reads as NaN), computes loss and
+ * gradient (loss_hist[s], device double, may be NULL) and takes Adam step step0 + s + 1
+ * (beta1 0.9, beta2 0.999, eps 1e-8).  Workspace for `batch` rows.
+ */
+HAP_API hap_status hap_mlp_train(float *params, float *opt_state, int32_t n_in, int32_t hidden, int32_t n_out,
+                                 int32_t precision, int64_t step0, const float *X, int64_t ldx, const float *T,
+                                 int64_t ldt, int64_t rows, const int32_t *idx, int64_t batch, int64_t steps,
+                                 double lr, double *loss_hist, void *workspace, size_t workspace_bytes,
+                                 void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2,6 +2,7 @@
 // workspace, and the host side of the iteration.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -882,6 +883,198 @@ hap_status hap_batch_destroy(hap_batch *b) {
     if (b->own_ws && hipFree(b->ws) != hipSuccess) s = fail_hip(hipGetLastError(), "hap_batch_destroy");
     delete b;
     return s;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Learned warm start and its perceptron
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// Back to the Algorithm 1 initial state (the preferences stay), then, when Y is given, the
+// warm initial availabilities of every level from the network outputs Y (n x L, row stride ldy).
+template <typename T>
+hap_status restart_state(hap_ctx *c, const float *Y, int64_t ldy) {
+    const Layout lo = make_layout(c->n, c->L, c->esz);
+    char *base = (char *)c->ws;
+    hipStream_t st = c->stream;
+    HIP_TRY(hipMemsetAsync(base + lo.R, 0, lo.pref - lo.R, st), c);
+    HIP_TRY(hipMemsetAsync(base + lo.Q, 0, lo.Qpart - lo.Q, st), c);
+    HIP_TRY(hipMemsetAsync(c->ds, 0, sizeof(DevState), st), c);
+    HIP_TRY(hap::launch_alpha_pad<T>((T *)c->A, (int64_t)c->L * c->n, (int)c->n, c->ldw, st), c);
+    if (Y) {
+        for (int l = 0; l < c->L; ++l) {
+            LevelPtrs<T> lv = level_ptrs<T>(c, l);
+            HIP_TRY(hap::launch_warm_alpha<T>(lv, (int)c->n, c->ldw, Y, ldy, l, (T *)c->Qpart, st), c);
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(st), c);
+    c->t_host = 0;
+    c->labels_ready = false;
+    return HAP_OK;
+}
+
+bool mlp_dims_ok(int32_t n_in, int32_t hidden, int32_t n_out) {
+    return n_in >= 1 && hidden >= 1 && n_out >= 1 && n_in <= 4096 && hidden <= 4096 && n_out <= 4096;
+}
+
+}  // namespace
+
+extern "C" {
+
+hap_status hap_warm_features(hap_ctx *c, float *F, int64_t ldf) {
+    if (!c || !F) return fail_arg("hap_warm_features: null pointer");
+    if (c->failed) return fail_arg("hap_warm_features: context failed earlier", HAP_E_STATE);
+    if (c->n < 2) return fail_arg("hap_warm_features: needs at least two points");
+    if (ldf < HAP_WARM_FEATURES) return fail_arg("hap_warm_features: ldf < HAP_WARM_FEATURES");
+    hipError_t e;
+    if (c->dtype == HAP_F32)
+        e = hap::launch_warm_features<float>((const float *)c->S, c->lds, (const float *)c->pref, (int)c->n, F, ldf,
+                                             c->Qpart, c->stream);
+    else
+        e = hap::launch_warm_features<double>((const double *)c->S, c->lds, (const double *)c->pref, (int)c->n, F, ldf,
+                                              c->Qpart, c->stream);
+    if (e != hipSuccess) return fail_hip(e, "hap_warm_features", c);
+    HIP_TRY(hipStreamSynchronize(c->stream), c);
+    return HAP_OK;
+}
+
+hap_status hap_warm_targets(hap_ctx *c, float *T, int64_t ldt) {
+    if (!c || !T) return fail_arg("hap_warm_targets: null pointer");
+    if (c->failed) return fail_arg("hap_warm_targets: context failed earlier", HAP_E_STATE);
+    if (ldt < c->L) return fail_arg("hap_warm_targets: ldt < levels");
+    for (int l = 0; l < c->L; ++l) {
+        hipError_t e;
+        if (c->dtype == HAP_F32)
+            e = hap::launch_warm_targets<float>(level_ptrs<float>(c, l), (int)c->n, c->ldw, c->lam, c->t_host, T + l,
+                                                ldt, c->stream);
+        else
+            e = hap::launch_warm_targets<double>(level_ptrs<double>(c, l), (int)c->n, c->ldw, c->lam, c->t_host, T + l,
+                                                 ldt, c->stream);
+        if (e != hipSuccess) return fail_hip(e, "hap_warm_targets", c);
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream), c);
+    return HAP_OK;
+}
+
+hap_status hap_set_warm_start(hap_ctx *c, const float *Y, int64_t ldy) {
+    if (!c) return fail_arg("hap_set_warm_start: null context");
+    if (c->failed) return fail_arg("hap_set_warm_start: context failed earlier", HAP_E_STATE);
+    if (Y && ldy < c->L) return fail_arg("hap_set_warm_start: ldy < levels");
+    return c->dtype == HAP_F32 ? restart_state<float>(c, Y, ldy) : restart_state<double>(c, Y, ldy);
+}
+
+hap_status hap_iterate_warm(hap_ctx *c, const float *Y, int64_t ldy, int32_t max_iters, int32_t stable_iters,
+                            int32_t *iters_done, int32_t *converged, int32_t *fell_back) {
+    if (!c) return fail_arg("hap_iterate_warm: null context");
+    if (stable_iters < 1) return fail_arg("hap_iterate_warm: the fallback needs a stop rule (stable_iters >= 1)");
+    hap_status s = hap_set_warm_start(c, Y, ldy);
+    if (s != HAP_OK) return s;
+    int32_t it = 0, conv = 0, fell = 0;
+    s = hap_iterate(c, max_iters, stable_iters, &it, &conv);
+    if (s != HAP_OK) return s;
+    if (!conv && Y) {
+        s = hap_set_warm_start(c, nullptr, 0);
+        if (s != HAP_OK) return s;
+        s = hap_iterate(c, max_iters, stable_iters, &it, &conv);
+        if (s != HAP_OK) return s;
+        fell = 1;
+    }
+    if (iters_done) *iters_done = it;
+    if (converged) *converged = conv;
+    if (fell_back) *fell_back = fell;
+    return HAP_OK;
+}
+
+int64_t hap_mlp_param_count(int32_t n_in, int32_t hidden, int32_t n_out) {
+    if (!mlp_dims_ok(n_in, hidden, n_out)) return -1;
+    return hap::mlp_layout(n_in, hidden, n_out, 0).count;
+}
+
+hap_status hap_mlp_workspace_size(int32_t n_in, int32_t hidden, int32_t n_out, int64_t rows, size_t *bytes) {
+    if (!bytes) return fail_arg("hap_mlp_workspace_size: null pointer");
+    if (!mlp_dims_ok(n_in, hidden, n_out) || rows < 0 || rows > INT32_MAX)
+        return fail_arg("hap_mlp_workspace_size: bad sizes");
+    *bytes = hap::mlp_layout(n_in, hidden, n_out, rows).bytes;
+    return HAP_OK;
+}
+
+hap_status hap_mlp_forward(const float *params, int32_t n_in, int32_t hidden, int32_t n_out, int32_t precision,
+                           const float *X, int64_t ldx, int64_t rows, float *Y, int64_t ldy, void *workspace,
+                           size_t workspace_bytes, void *stream) {
+    if (!params || !X || !Y || !workspace) return fail_arg("hap_mlp_forward: null pointer");
+    if (!mlp_dims_ok(n_in, hidden, n_out) || rows < 0 || rows > INT32_MAX || ldx < n_in || ldy < n_out)
+        return fail_arg("hap_mlp_forward: bad sizes");
+    if (precision != HAP_F32 && precision != HAP_BF16)
+        return fail_arg("hap_mlp_forward: precision must be HAP_F32 or HAP_BF16", HAP_E_DTYPE);
+    const hap::MlpLayout lo = hap::mlp_layout(n_in, hidden, n_out, rows);
+    if (workspace_bytes < lo.bytes) return fail_arg("hap_mlp_forward: workspace too small");
+    hipError_t e = hap::mlp_forward(lo, n_in, hidden, n_out, precision == HAP_BF16, params, X, ldx, (int)rows, Y, ldy,
+                                    (char *)workspace, (hipStream_t)stream);
+    if (e != hipSuccess) return fail_hip(e, "hap_mlp_forward");
+    return HAP_OK;
+}
+
+hap_status hap_mlp_loss_grad(const float *params, int32_t n_in, int32_t hidden, int32_t n_out, int32_t precision,
+                             const float *X, int64_t ldx, const float *T, int64_t ldt, int64_t rows, float *grad,
+                             double *loss, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!params || !X || !T || !grad || !loss || !workspace) return fail_arg("hap_mlp_loss_grad: null pointer");
+    if (!mlp_dims_ok(n_in, hidden, n_out) || rows < 1 || rows > INT32_MAX || ldx < n_in || ldt < n_out)
+        return fail_arg("hap_mlp_loss_grad: bad sizes");
+    if (precision != HAP_F32 && precision != HAP_BF16)
+        return fail_arg("hap_mlp_loss_grad: precision must be HAP_F32 or HAP_BF16", HAP_E_DTYPE);
+    const hap::MlpLayout lo = hap::mlp_layout(n_in, hidden, n_out, rows);
+    if (workspace_bytes < lo.bytes) return fail_arg("hap_mlp_loss_grad: workspace too small");
+    hipError_t e = hap::mlp_loss_grad(lo, n_in, hidden, n_out, precision == HAP_BF16, params, X, ldx, T, ldt,
+                                      (int)rows, grad, loss, (char *)workspace, (hipStream_t)stream);
+    if (e != hipSuccess) return fail_hip(e, "hap_mlp_loss_grad");
+    return HAP_OK;
+}
+
+hap_status hap_mlp_adam(float *params, const float *grad, float *opt_state, int64_t count, int64_t step, double lr,
+                        double beta1, double beta2, double eps, void *stream) {
+    if (!params || !grad || !opt_state) return fail_arg("hap_mlp_adam: null pointer");
+    if (count < 0 || step < 1) return fail_arg("hap_mlp_adam: count < 0 or step < 1");
+    if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps > 0.0 && lr > 0.0))
+        return fail_arg("hap_mlp_adam: bad hyper-parameters");
+    hipError_t e = hap::mlp_adam(params, grad, opt_state, opt_state + count, count, step, lr, beta1, beta2, eps,
+                                 (hipStream_t)stream);
+    if (e != hipSuccess) return fail_hip(e, "hap_mlp_adam");
+    return HAP_OK;
+}
+
+hap_status hap_mlp_train(float *params, float *opt_state, int32_t n_in, int32_t hidden, int32_t n_out,
+                         int32_t precision, int64_t step0, const float *X, int64_t ldx, const float *T, int64_t ldt,
+                         int64_t rows, const int32_t *idx, int64_t batch, int64_t steps, double lr, double *loss_hist,
+                         void *workspace, size_t workspace_bytes, void *stream) {
+    if (!params || !opt_state || !X || !T || !idx || !workspace) return fail_arg("hap_mlp_train: null pointer");
+    if (!mlp_dims_ok(n_in, hidden, n_out) || rows < 1 || rows > INT32_MAX || batch < 1 || batch > INT32_MAX ||
+        steps < 0 || step0 < 0 || ldx < n_in || ldt < n_out)
+        return fail_arg("hap_mlp_train: bad sizes");
+    if (precision != HAP_F32 && precision != HAP_BF16)
+        return fail_arg("hap_mlp_train: precision must be HAP_F32 or HAP_BF16", HAP_E_DTYPE);
+    if (!(lr > 0.0)) return fail_arg("hap_mlp_train: lr must be positive");
+    const hap::MlpLayout lo = hap::mlp_layout(n_in, hidden, n_out, batch);
+    if (workspace_bytes < lo.bytes) return fail_arg("hap_mlp_train: workspace too small");
+    char *ws = (char *)workspace;
+    hipStream_t st = (hipStream_t)stream;
+    float *Xb = (float *)(ws + lo.Xb), *Tb = (float *)(ws + lo.Tb), *G = (float *)(ws + lo.G);
+    double *loss = (double *)(ws + lo.loss);
+    for (int64_t s = 0; s < steps; ++s) {
+        const int32_t *ix = idx + s * batch;
+        hipError_t e = hap::mlp_gather(X, ldx, n_in, ix, (int)batch, (int)rows, Xb, st);
+        if (e == hipSuccess) e = hap::mlp_gather(T, ldt, n_out, ix, (int)batch, (int)rows, Tb, st);
+        if (e == hipSuccess)
+            e = hap::mlp_loss_grad(lo, n_in, hidden, n_out, precision == HAP_BF16, params, Xb, n_in, Tb, n_out,
+                                   (int)batch, G, loss_hist ? loss_hist + s : loss, ws, st);
+        if (e == hipSuccess)
+            e = hap::mlp_adam(params, G, opt_state, opt_state + lo.count, lo.count, step0 + s + 1, lr, 0.9, 0.999,
+                              1e-8, st);
+        if (e != hipSuccess) return fail_hip(e, "hap_mlp_train");
+    }
+    return HAP_OK;
 }
 
 }  // extern "C"

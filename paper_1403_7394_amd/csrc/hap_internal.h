@@ -119,6 +119,37 @@ hipError_t launch_batch(const float *X, int64_t d, const BatchDesc *desc, const 
                         double lam, int max_iters, int stable_iters, float *wsf, int32_t *wsi, int32_t *queue,
                         int32_t *labels, double *ns, int32_t *iters, int threads, int workgroups, hipStream_t st);
 
+// Warm-start perceptron (mlp.hip).  Offsets of the flat parameter vector (floats) and of the
+// workspace regions (bytes) for `rows` rows.
+struct MlpLayout {
+    int64_t oW1, ob1, oW2, ob2, oW3, ob3, count;
+    size_t Xb, Tb, H1, H2, Y, dY, dH2, dH1, G, loss, bytes;
+};
+MlpLayout mlp_layout(int n_in, int hidden, int n_out, int64_t rows);
+hipError_t mlp_forward(const MlpLayout &lo, int n_in, int hidden, int n_out, bool bf16, const float *P,
+                       const float *X, int64_t ldx, int rows, float *Y, int64_t ldy, char *ws, hipStream_t st);
+hipError_t mlp_loss_grad(const MlpLayout &lo, int n_in, int hidden, int n_out, bool bf16, const float *P,
+                         const float *X, int64_t ldx, const float *T, int64_t ldt, int rows, float *G, double *loss,
+                         char *ws, hipStream_t st);
+hipError_t mlp_adam(float *P, const float *G, float *M, float *V, int64_t count, int64_t step, double lr, double b1,
+                    double b2, double eps, hipStream_t st);
+hipError_t mlp_gather(const float *X, int64_t ldx, int w, const int32_t *idx, int rows, int x_rows, float *out,
+                      hipStream_t st);
+
+// Warm start (warm.hip).  Features of every row of S (n x HAP_WARM_FEATURES floats) with
+// scratch of warm_feature_scratch_bytes(n); training targets of the current state; warm
+// initial availabilities from network outputs.
+size_t warm_feature_scratch_bytes(int64_t n);
+template <typename T>
+hipError_t launch_warm_features(const T *S, int64_t lds, const T *pref, int n, float *F, int64_t ldf, void *scratch,
+                                hipStream_t st);
+template <typename T>
+hipError_t launch_warm_targets(const LevelPtrs<T> &lv, int n, int64_t ldw, double lam, int t, float *out, int64_t ldo,
+                               hipStream_t st);
+template <typename T>
+hipError_t launch_warm_alpha(const LevelPtrs<T> &lv, int n, int64_t ldw, const float *Y, int64_t ldy, int col,
+                             T *bases_scratch, hipStream_t st);
+
 void set_error(const std::string &msg);
 
 }  // namespace hap

@@ -28,7 +28,12 @@ EXPORTS = (
     "hap_get_launch", "hap_profile", "hap_profile_read", "hap_destroy",
     "hap_batch_workspace_size", "hap_batch_create", "hap_batch_run", "hap_batch_set_launch",
     "hap_batch_get_launch", "hap_batch_destroy",
+    "hap_warm_features", "hap_warm_targets", "hap_set_warm_start", "hap_iterate_warm",
+    "hap_mlp_param_count", "hap_mlp_workspace_size", "hap_mlp_forward", "hap_mlp_loss_grad", "hap_mlp_adam",
+    "hap_mlp_train",
 )
+WARM_FEATURES = 32
+HAP_BF16 = 2
 
 
 class HapError(RuntimeError):
@@ -81,6 +86,16 @@ def _declare(lib):
         "hap_batch_set_launch": (I32, [V, I32, I32]),
         "hap_batch_get_launch": (I32, [V, _c_i32p, _c_i32p]),
         "hap_batch_destroy": (I32, [V]),
+        "hap_warm_features": (I32, [V, V, I64]),
+        "hap_warm_targets": (I32, [V, V, I64]),
+        "hap_set_warm_start": (I32, [V, V, I64]),
+        "hap_iterate_warm": (I32, [V, V, I64, I32, I32, _c_i32p, _c_i32p, _c_i32p]),
+        "hap_mlp_param_count": (I64, [I32, I32, I32]),
+        "hap_mlp_workspace_size": (I32, [I32, I32, I32, I64, ctypes.POINTER(SZ)]),
+        "hap_mlp_forward": (I32, [V, I32, I32, I32, I32, V, I64, I64, V, I64, V, SZ, V]),
+        "hap_mlp_loss_grad": (I32, [V, I32, I32, I32, I32, V, I64, V, I64, I64, V, V, V, SZ, V]),
+        "hap_mlp_adam": (I32, [V, V, V, I64, I64, D, D, D, D, V]),
+        "hap_mlp_train": (I32, [V, V, I32, I32, I32, I32, I64, V, I64, V, I64, I64, V, I64, I64, D, V, V, SZ, V]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -285,6 +300,37 @@ class Hap:
                                                               ctypes.byref(c), ctypes.byref(d)))
         return a.value, b.value, c.value, d.value
 
+    # ---------------------------------------------------------------- warm start
+    def warm_features(self, out=None):
+        """(n, WARM_FEATURES) FP32 features of every point (hap_warm_features)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n, WARM_FEATURES, dtype=torch.float32, device=self.S.device)
+        _check("hap_warm_features", self._lib.hap_warm_features(self._ctx, ctypes.c_void_p(out.data_ptr()), _ld(out)))
+        return out
+
+    def warm_targets(self, out=None):
+        """(n, levels) FP32 training targets of the current state (hap_warm_targets)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n, self.levels, dtype=torch.float32, device=self.S.device)
+        _check("hap_warm_targets", self._lib.hap_warm_targets(self._ctx, ctypes.c_void_p(out.data_ptr()), _ld(out)))
+        return out
+
+    def set_warm_start(self, Y=None):
+        """Restart from the warm availabilities of network outputs Y (n, levels), or cold."""
+        ptr, ld = (None, 0) if Y is None else (ctypes.c_void_p(Y.data_ptr()), _ld(Y))
+        self._warm_keep = Y
+        _check("hap_set_warm_start", self._lib.hap_set_warm_start(self._ctx, ptr, ld))
+
+    def iterate_warm(self, Y, max_iters: int, stable_iters: int):
+        """Warm run with the cold start as fallback: (IterResult, fell_back)."""
+        ptr, ld = (None, 0) if Y is None else (ctypes.c_void_p(Y.data_ptr()), _ld(Y))
+        it, cv, fb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check("hap_iterate_warm", self._lib.hap_iterate_warm(self._ctx, ptr, ld, max_iters, stable_iters,
+                                                              ctypes.byref(it), ctypes.byref(cv), ctypes.byref(fb)))
+        return IterResult(it.value, bool(cv.value)), bool(fb.value)
+
     def get_launch(self):
         """(threads, chunks, rows_per_block, streaming)."""
         a, b, c, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
@@ -370,3 +416,81 @@ class HapBatch:
             self.close()
         except Exception:
             pass
+
+
+class Mlp:
+    """The warm start's perceptron (n_in -> hidden -> hidden -> n_out, ReLU) on the GPU.
+
+    params: flat FP32 device tensor (hap_mlp_param_count values); precision HAP_F32 or
+    HAP_BF16 (operands of every product rounded to BF16, FP32 accumulation)."""
+
+    def __init__(self, params, n_in: int, hidden: int, n_out: int, precision: int = HAP_BF16, stream=None):
+        import torch
+        self._lib = load()
+        self.n_in, self.hidden, self.n_out, self.precision = n_in, hidden, n_out, precision
+        cnt = self._lib.hap_mlp_param_count(n_in, hidden, n_out)
+        if cnt < 0 or params.numel() != cnt or params.dtype != torch.float32 or not params.is_contiguous():
+            raise ValueError("params must be a contiguous FP32 tensor of hap_mlp_param_count values")
+        self.params = params
+        self.count = cnt
+        self.opt_state = torch.zeros(2 * cnt, dtype=torch.float32, device=params.device)
+        self.step = 0
+        self._stream_obj = stream
+        self._ws = None
+
+    def _workspace(self, rows: int):
+        import torch
+        b = ctypes.c_size_t()
+        _check("hap_mlp_workspace_size", self._lib.hap_mlp_workspace_size(self.n_in, self.hidden, self.n_out, rows,
+                                                                            ctypes.byref(b)))
+        if self._ws is None or self._ws.numel() < b.value:
+            self._ws = torch.empty(b.value, dtype=torch.uint8, device=self.params.device)
+        return ctypes.c_void_p(self._ws.data_ptr()), self._ws.numel()
+
+    def forward(self, X, out=None):
+        import torch
+        rows = X.shape[0]
+        if out is None:
+            out = torch.empty(rows, self.n_out, dtype=torch.float32, device=X.device)
+        ws, nb = self._workspace(rows)
+        P = lambda t: ctypes.c_void_p(t.data_ptr())
+        _check("hap_mlp_forward", self._lib.hap_mlp_forward(P(self.params), self.n_in, self.hidden, self.n_out,
+                                                            self.precision, P(X), _ld(X), rows, P(out), _ld(out), ws,
+                                                            nb, _stream(self._stream_obj)))
+        return out
+
+    def loss_grad(self, X, T):
+        """(loss tensor (device double, shape []), gradient (flat FP32, like params))."""
+        import torch
+        rows = X.shape[0]
+        grad = torch.empty_like(self.params)
+        loss = torch.empty((), dtype=torch.float64, device=X.device)
+        ws, nb = self._workspace(rows)
+        P = lambda t: ctypes.c_void_p(t.data_ptr())
+        _check("hap_mlp_loss_grad", self._lib.hap_mlp_loss_grad(P(self.params), self.n_in, self.hidden, self.n_out,
+                                                                self.precision, P(X), _ld(X), P(T), _ld(T), rows,
+                                                                P(grad), P(loss), ws, nb, _stream(self._stream_obj)))
+        return loss, grad
+
+    def adam(self, grad, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        self.step += 1
+        P = lambda t: ctypes.c_void_p(t.data_ptr())
+        _check("hap_mlp_adam", self._lib.hap_mlp_adam(P(self.params), P(grad), P(self.opt_state), self.count, self.step,
+                                                      lr, beta1, beta2, eps, _stream(self._stream_obj)))
+
+    def train(self, X, T, idx, batch: int, steps: int, lr: float, loss_hist=None):
+        """Minibatch Adam over rows idx (device int32, batch*steps entries); returns the
+        per-step losses (device double tensor)."""
+        import torch
+        if idx.dtype != torch.int32 or idx.numel() < batch * steps:
+            raise ValueError("idx must be int32 with batch*steps entries")
+        if loss_hist is None:
+            loss_hist = torch.empty(steps, dtype=torch.float64, device=X.device)
+        ws, nb = self._workspace(batch)
+        P = lambda t: ctypes.c_void_p(t.data_ptr())
+        _check("hap_mlp_train", self._lib.hap_mlp_train(P(self.params), P(self.opt_state), self.n_in, self.hidden,
+                                                        self.n_out, self.precision, self.step, P(X), _ld(X), P(T),
+                                                        _ld(T), X.shape[0], P(idx), batch, steps, lr, P(loss_hist),
+                                                        ws, nb, _stream(self._stream_obj)))
+        self.step += steps
+        return loss_hist

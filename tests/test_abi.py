@@ -100,3 +100,31 @@ def test_build_and_median_check_arguments(lib):
     d = ctypes.c_double()
     assert lib.hap_median_offdiag(fake, 1, 4, 0, ctypes.byref(d), None) == hap.HAP_E_ARG
     assert lib.hap_median_offdiag(fake, 10, 10, 0, ctypes.byref(d), None) == hap.HAP_E_ARG
+
+
+def test_mlp_sizes_and_argument_checks(lib):
+    # W1 32x128, b1, W2 128x128, b2, W3 128x3, b3
+    assert lib.hap_mlp_param_count(32, 128, 3) == 32 * 128 + 128 + 128 * 128 + 128 + 128 * 3 + 3
+    assert lib.hap_mlp_param_count(0, 128, 3) == -1
+    b = ctypes.c_size_t()
+    assert lib.hap_mlp_workspace_size(32, 128, 3, 4096, ctypes.byref(b)) == hap.HAP_OK
+    assert b.value >= 4 * 4096 * 128 * 4           # two activations and two deltas of 4096 x 128
+    assert lib.hap_mlp_workspace_size(32, 128, 3, -1, ctypes.byref(b)) == hap.HAP_E_ARG
+    fake = ctypes.c_void_p(4096)  # never dereferenced: every call below fails its checks first
+    big = 1 << 40
+    assert lib.hap_mlp_forward(None, 32, 128, 3, hap.HAP_F32, fake, 32, 10, fake, 3, fake, big, None) == hap.HAP_E_ARG
+    assert lib.hap_mlp_forward(fake, 32, 128, 3, hap.HAP_F64, fake, 32, 10, fake, 3, fake, big, None) == hap.HAP_E_DTYPE
+    assert lib.hap_mlp_forward(fake, 32, 128, 3, hap.HAP_F32, fake, 31, 10, fake, 3, fake, big, None) == hap.HAP_E_ARG
+    assert lib.hap_mlp_forward(fake, 32, 128, 3, hap.HAP_F32, fake, 32, 10, fake, 3, fake, 16, None) == hap.HAP_E_ARG
+    assert lib.hap_mlp_adam(fake, fake, fake, 10, 0, 1e-3, 0.9, 0.999, 1e-8, None) == hap.HAP_E_ARG
+    assert lib.hap_mlp_adam(fake, fake, fake, 10, 1, 1e-3, 1.0, 0.999, 1e-8, None) == hap.HAP_E_ARG
+    assert lib.hap_mlp_train(fake, fake, 32, 128, 3, hap.HAP_BF16, 0, fake, 32, fake, 3, 100, fake, 0, 5, 1e-3,
+                             None, fake, big, None) == hap.HAP_E_ARG
+
+
+def test_warm_calls_reject_a_null_context(lib):
+    fake = ctypes.c_void_p(4096)
+    assert lib.hap_warm_features(None, fake, 32) == hap.HAP_E_ARG
+    assert lib.hap_warm_targets(None, fake, 3) == hap.HAP_E_ARG
+    assert lib.hap_set_warm_start(None, None, 0) == hap.HAP_E_ARG
+    assert lib.hap_iterate_warm(None, None, 0, 10, 5, None, None, None) == hap.HAP_E_ARG
