@@ -9,13 +9,15 @@ Synthetic data from paper_1403_7394_amd.synth (seed 1002).
 One step is one pass of the whole hot path with the points already on the GPU:
 similarity build, median preference and initial state, the sweeps until the
 stop rule, exemplars of every level and the FP64 net similarity.  `value` is
-N^2*L*(sweeps performed) / (wall time of the timed steps).
+N^2*L*(sweeps performed) / (wall time of the timed steps).  The row pass runs in
+points mode (s_ij recomputed from the 2-D points, bit-identical to reading S;
+--read-s reads S instead).
 
 The roofline entry is for the dominant kernel, the fused row pass: its
-algorithmic traffic (read S, R, A and write R, A: 5 N^2 words per level per
-sweep; 4 N^2 in the first sweep, which has no alpha to finish) divided by its
-average launch duration, measured with HIP events recorded on its own stream
-during the timed steps.
+algorithmic traffic (read R, A and write R, A: 4 N^2 words per level per sweep,
+3 N^2 in the first sweep, which has no alpha to finish; 5 N^2 and 4 N^2 when S is
+read) divided by its average launch duration, measured with HIP events recorded
+on its own stream during the timed steps.
 """
 from __future__ import annotations
 
@@ -32,7 +34,8 @@ if ROOT not in sys.path:
 
 METRIC = "HAP N²·L message updates/s and time-to-converge vs plain, same GPU"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "row_pass_traffic_plain8192.json")
+TRAFFIC_FILES = {True: os.path.join(ROOT, "profiles", "row_pass_traffic_plain8192_points.json"),
+                 False: os.path.join(ROOT, "profiles", "row_pass_traffic_plain8192.json")}
 SWEEP_SRC = os.path.join(ROOT, "paper_1403_7394_amd", "csrc", "sweep.hip")
 ROWPASS_SRC = os.path.join(ROOT, "paper_1403_7394_amd", "csrc", "rowpass.h")
 
@@ -42,12 +45,12 @@ def _hash16(path: str) -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(first_launches: int, steady_launches: int):
+def measured_traffic(points: bool, first_launches: int, steady_launches: int):
     """HBM bytes per row-pass launch from the committed counter summary (FETCH_SIZE and
     WRITE_SIZE scaled by a 1 GiB device copy), weighted over this run's first-sweep and
     later launches; None unless the counters were taken on the current kernel source."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILES[points]) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -345,6 +348,7 @@ def main() -> int:
                     help="plain: the headline line; precision: the similarity build forms; "
                          "batched: many problems in one launch; warm: the learned warm start")
     ap.add_argument("--form-iters", type=int, default=0, help="iterations for a form run (0 = the workload's)")
+    ap.add_argument("--read-s", action="store_true", help="plain form: the row pass reads S (no points mode)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -385,9 +389,13 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
 
+    points = not args.read_s
+
     def step(profile: bool):
         hap.build_similarity(X, S)
         h = hap.Hap(S, L, rp.damping, workspace=ws)
+        if points:
+            h.set_points(X)
         if profile:
             h.profile(True)
         res = h.iterate(rp.max_iters, rp.stable_iters)
@@ -420,11 +428,13 @@ def main() -> int:
 
     w = 4
     # algorithmic bytes of all row-pass launches: 4 N^2 w in the first sweep, 5 N^2 w after
-    alg_bytes_total = (first_sweeps * L * 4 + (row_n - first_sweeps * L) * 5) * n * n * w
+    # (one word less per element in points mode, where S is not read)
+    first_w, steady_w = (3, 4) if points else (4, 5)
+    alg_bytes_total = (first_sweeps * L * first_w + (row_n - first_sweeps * L) * steady_w) * n * n * w
     bytes_per_launch = alg_bytes_total / max(row_n, 1)
     avg_launch_s = row_ms / max(row_n, 1) * 1e-3
     achieved = bytes_per_launch / avg_launch_s / 1e9
-    traffic = measured_traffic(first_sweeps * L, row_n - first_sweeps * L)
+    traffic = measured_traffic(points, first_sweeps * L, row_n - first_sweeps * L)
     ms_per_step = elapsed / args.steps * 1e3
     value = n * n * L * sweeps / elapsed
 
@@ -444,6 +454,7 @@ def main() -> int:
         "config": {
             "workload": "plain HAP, 8192 points in 2-D, 64 Gaussian blobs, FP32, L=3, damping 0.9, "
                         "median preference, 500 iterations or 50 stable",
+            "row_pass": "points mode (s_ij recomputed from the points)" if points else "reads S",
             "n": n, "levels": L, "damping": rp.damping, "max_iters": rp.max_iters,
             "stable_iters": rp.stable_iters, "seed": blobs.seed,
         },
@@ -454,7 +465,7 @@ def main() -> int:
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "row pass (sweep_kernel)",
+            "kernel": "row pass (sweep_kernel, points mode)" if points else "row pass (sweep_kernel)",
             "avg_launch_us": avg_launch_s * 1e6,
             "alg_bytes_per_launch": bytes_per_launch,
             "launches": row_n,

@@ -196,6 +196,18 @@ HAP_API hap_status hap_get_launch(hap_ctx *ctx, int32_t *threads, int32_t *chunk
                                   int32_t *flags);
 
 /*
+ * Points mode of the register-resident row pass.  The caller states that the context's S
+ * was built from X (device FP32, n x d row-major, row stride ldx) by hap_build_similarity
+ * with HAP_BUILD_DIRECT and no noise; the row pass then recomputes s_ij = -||x_i - x_j||^2
+ * with the build's arithmetic (FP64 accumulation in coordinate order, rounded once), which
+ * gives the same values as reading S and saves one N^2 read per level and iteration (about
+ * a fifth of the sweep's traffic).  The one-off passes (median, labels, net similarity) and
+ * the streaming row pass still read S.  FP32 contexts, d = 2 or 3.  X must stay valid
+ * while the context iterates.  X = NULL switches the mode off.
+ */
+HAP_API hap_status hap_set_points(hap_ctx *ctx, const void *X, int64_t d, int64_t ldx, int32_t x_dtype);
+
+/*
  * Per-launch timing of the sweep kernels with HIP events recorded on the
  * context's stream around every launch.  enable = 1 starts collecting (and
  * clears the totals), 0 stops.  hap_profile_read returns the summed elapsed time

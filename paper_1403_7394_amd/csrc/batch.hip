@@ -206,6 +206,8 @@ __global__ __launch_bounds__(NT) void batch_kernel(BatchArgs g) {
                 a.tau = l > 0 ? vp(l, 3) : nullptr;
                 a.E = E + (int64_t)l * ld;
                 a.Qpart = nullptr;
+                a.X = nullptr;
+                a.ldx = 0;
                 a.n = n;
                 a.rb = n;
                 a.lam = g.lam;

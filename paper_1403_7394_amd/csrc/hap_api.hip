@@ -34,6 +34,10 @@ struct hap_ctx {
     size_t esz = 4;
     double lam = 0.0;
     const void *S = nullptr;
+    // points mode (hap_set_points): the row pass recomputes s_ij from X
+    const void *X = nullptr;
+    int64_t ldx = 0;
+    int d = 0;
 
     void *ws = nullptr;
     size_t ws_bytes = 0;
@@ -245,7 +249,7 @@ hap_status run_sweeps(hap_ctx *c, int count, int K) {
             const T *tau_l = l > 0 ? lv.tau : nullptr;
             HIP_TRY(prof_mark(c, 0, false), c);
             HIP_TRY(hap::launch_sweep_level<T>((const T *)c->S, c->lds, lv, phi_down, tau_l, (int)c->n, c->ldw, c->lam,
-                                               Qpart, c->lc, c->ds, c->stream),
+                                               Qpart, c->lc, c->ds, c->stream, (const T *)c->X, c->ldx, c->d),
                     c);
             HIP_TRY(prof_mark(c, 0, true), c);
             T *tau_next = (l + 1 < L) ? level_ptrs<T>(c, l + 1).tau : nullptr;
@@ -666,6 +670,24 @@ hap_status hap_set_launch(hap_ctx *c, int32_t threads, int32_t chunks, int32_t r
     lc.ordered = (lc.rows_per_block == 1);
     if (!launch_fits(lc, c->n, c->esz, c->nb_cap)) return fail_arg("hap_set_launch: shape does not fit this problem");
     c->lc = lc;
+    return HAP_OK;
+}
+
+hap_status hap_set_points(hap_ctx *c, const void *X, int64_t d, int64_t ldx, int32_t x_dtype) {
+    if (!c) return fail_arg("hap_set_points: null context");
+    if (!X) {
+        c->X = nullptr;
+        c->ldx = 0;
+        c->d = 0;
+        return HAP_OK;
+    }
+    if (c->dtype != HAP_F32 || x_dtype != HAP_F32)
+        return fail_arg("hap_set_points: points mode needs FP32 similarities and FP32 points", HAP_E_DTYPE);
+    if (d != 2 && d != 3) return fail_arg("hap_set_points: points mode supports d = 2 or 3", HAP_E_UNSUPPORTED);
+    if (ldx < d) return fail_arg("hap_set_points: ldx < d");
+    c->X = X;
+    c->ldx = ldx;
+    c->d = (int)d;
     return HAP_OK;
 }
 

@@ -26,6 +26,14 @@ struct SweepArgs {
     int rb;
     T lam, oml;
     DevState *ds;
+    const T *X;           // points mode: s_ij recomputed from X (row stride ldx) instead of read
+    int64_t ldx;
+};
+
+// Coordinates of the columns a thread owns (points mode, D coordinates per point).
+template <typename T, int NCH, int D>
+struct ColPoints {
+    T x[NCH][Vec<T>::N][D > 0 ? D : 1];
 };
 
 // Merge two (max, argmax, second max) triples; the lower index wins a tie.
@@ -70,19 +78,49 @@ struct RowRegs {
 // never win a maximum); inside the last partial vector the padding columns of A hold -inf
 // from initialisation and stay -inf or NaN, which '>' and fmax ignore.  Padding columns of
 // R, A and the column partials are never read back as results.
-template <typename T, int NT, int NCH, bool TAIL>
-__device__ __forceinline__ void load_row(const SweepArgs<T> &a, int i, RowRegs<T, NT, NCH> &x) {
+//
+// D > 0 (points mode): instead of reading S, s_ij is recomputed from the D coordinates of
+// points i and j exactly as the direct similarity build computes it (squared differences
+// summed in FP64 in coordinate order, no contraction, negated, rounded once), so the values
+// equal those of an S built that way and one N^2 read per level and sweep is saved.
+template <typename T, int NT, int NCH, bool TAIL, int D>
+__device__ __forceinline__ void load_row(const SweepArgs<T> &a, int i, RowRegs<T, NT, NCH> &x,
+                                         const ColPoints<T, NCH, D> &cp) {
+#pragma clang fp contract(off)
     using V = typename Vec<T>::type;
     constexpr int VW = Vec<T>::N;
     const T *Srow = a.S + (int64_t)i * a.lds;
     const T *Rrow = a.R + (int64_t)i * a.ldw;
     const T *Arow = a.A + (int64_t)i * a.ldw;
+    double xi[D > 0 ? D : 1];
+    if constexpr (D > 0) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) xi[k] = (double)a.X[(int64_t)i * a.ldx + k];
+    }
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         const int j0 = c * NT * VW + threadIdx.x * VW;
         if (!TAIL || j0 < a.n) {
-            // S streams through once per level: non-temporal, so it does not displace R/A lines
-            x.s[c] = __builtin_nontemporal_load((const V *)(Srow + j0));
+            if constexpr (D == 0) {
+                // S streams through once per level: non-temporal, so it does not displace R/A lines
+                x.s[c] = __builtin_nontemporal_load((const V *)(Srow + j0));
+            } else {
+#pragma unroll
+                for (int v = 0; v < VW; ++v) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        // opaque per row, so the FP64 conversions are not hoisted out of the row
+                        // loop (that would double the registers holding the column points)
+                        T xj = cp.x[c][v][k];
+                        asm volatile("" : "+v"(xj));
+                        const double df = xi[k] - (double)xj;
+                        const double sq = df * df;
+                        acc = acc + sq;
+                    }
+                    x.s[c][v] = (T)(-acc);
+                }
+            }
             x.r[c] = *(const V *)(Rrow + j0);
             x.a[c] = *(const V *)(Arow + j0);
         } else {
@@ -96,11 +134,12 @@ __device__ __forceinline__ void load_row(const SweepArgs<T> &a, int i, RowRegs<T
 // The rows of one workgroup.  FIRST: iteration 1, alpha is the initial value (nothing to
 // finish, c and phi keep their initial 0).  TAIL: n is not exactly threads*chunks*VW, so
 // accesses past n are guarded (an exact fit needs no guard at all).
-template <typename T, int NT, int NCH, bool FIRST, bool TAIL>
+template <typename T, int NT, int NCH, bool FIRST, bool TAIL, int D = 0>
 __device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, const int row0, const int row1,
                                            const typename Vec<T>::type (&Bv)[NCH], typename Vec<T>::type (&qv)[NCH],
                                            T (*sh_m1)[NT / 64], int (*sh_k1)[NT / 64], T (*sh_m2)[NT / 64],
-                                           T (*sh_cv)[NT / 64], int (*sh_ck)[NT / 64]) {
+                                           T (*sh_cv)[NT / 64], int (*sh_ck)[NT / 64],
+                                           const ColPoints<T, NCH, D> &cp = ColPoints<T, NCH, D>{}) {
 #pragma clang fp contract(off)
     using V = typename Vec<T>::type;
     constexpr int VW = Vec<T>::N;
@@ -115,7 +154,7 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, c
     RowRegs<T, NT, NCH> x;
     int buf = 0;
     for (int i = row0; i < row1; ++i, buf ^= 1) {
-        load_row<T, NT, NCH, TAIL>(a, i, x);
+        load_row<T, NT, NCH, TAIL, D>(a, i, x, cp);
         T *Rrow = a.R + (int64_t)i * ldw;
         T *Arow = a.A + (int64_t)i * ldw;
         const T p_i = a.pref[i];

@@ -30,8 +30,14 @@
 
 namespace hap {
 
-template <typename T, int NT, int NCH, bool TAIL>
-__global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
+// Waves per SIMD the register allocation must allow: the FP32 512-thread row pass reading S
+// fits in 128 registers without spilling, which lets two workgroups share a CU (two rows in
+// flight per CU instead of one).
+template <typename T, int NT, int D>
+constexpr int sweep_min_waves() { return (sizeof(T) == 4 && NT == 512 && D == 0) ? 4 : 1; }
+
+template <typename T, int NT, int NCH, bool TAIL, int D>
+__global__ __launch_bounds__(NT, (sweep_min_waves<T, NT, D>())) void sweep_kernel(SweepArgs<T> a) {
 #pragma clang fp contract(off)
     using V = typename Vec<T>::type;
     constexpr int VW = Vec<T>::N;
@@ -55,12 +61,24 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
         Bv[c] = (!first && (!TAIL || j0 < n)) ? *(const V *)(a.B + j0) : (V)(T(0));
         qv[c] = (V)(T(0));
     }
+    // points mode: the coordinates of this thread's columns, kept for every row
+    ColPoints<T, NCH, D> cp;
+    if constexpr (D > 0) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c)
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                const int j = c * NT * VW + tid * VW + v;
+#pragma unroll
+                for (int k = 0; k < D; ++k) cp.x[c][v][k] = (j < n) ? a.X[(int64_t)j * a.ldx + k] : T(0);
+            }
+    }
     const int row0 = blockIdx.x * a.rb;
     const int row1 = min(n, row0 + a.rb);
     if (first)
-        sweep_rows<T, NT, NCH, true, TAIL>(a, t, row0, row1, Bv, qv, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
+        sweep_rows<T, NT, NCH, true, TAIL, D>(a, t, row0, row1, Bv, qv, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck, cp);
     else
-        sweep_rows<T, NT, NCH, false, TAIL>(a, t, row0, row1, Bv, qv, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
+        sweep_rows<T, NT, NCH, false, TAIL, D>(a, t, row0, row1, Bv, qv, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck, cp);
 
     T *qrow = a.Qpart + (int64_t)blockIdx.x * ldw;
 #pragma unroll
@@ -478,10 +496,24 @@ bool launch_supported(int threads, int chunks, int elem_size) {
         else return hipErrorInvalidValue;                                                      \
     } while (0)
 
+template <typename T, int D>
+hipError_t launch_resident(const SweepArgs<T> &a, const Launch &lc, int nb, bool tail, hipStream_t st) {
+#define HAP_LAUNCH_SWEEP(NTC, NCHC)                                                                     \
+    do {                                                                                                \
+        if (tail)                                                                                       \
+            hipLaunchKernelGGL((sweep_kernel<T, NTC, NCHC, true, D>), dim3(nb), dim3(NTC), 0, st, a);   \
+        else                                                                                            \
+            hipLaunchKernelGGL((sweep_kernel<T, NTC, NCHC, false, D>), dim3(nb), dim3(NTC), 0, st, a);  \
+    } while (0)
+    HAP_DISPATCH_NT_NCH(lc.threads, lc.chunks, HAP_LAUNCH_SWEEP);
+#undef HAP_LAUNCH_SWEEP
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_sweep_level(const T *S, int64_t lds, const LevelPtrs<T> &lv, T *phi_down,
                               const T *tau_l, int n, int64_t ldw, double lam, T *Qpart, const Launch &lc,
-                              DevState *ds, hipStream_t st) {
+                              DevState *ds, hipStream_t st, const T *X, int64_t ldx, int d) {
     SweepArgs<T> a;
     a.S = S;
     a.lds = lds;
@@ -500,6 +532,8 @@ hipError_t launch_sweep_level(const T *S, int64_t lds, const LevelPtrs<T> &lv, T
     a.lam = (T)lam;
     a.oml = (T)(1.0 - lam);
     a.ds = ds;
+    a.X = X;
+    a.ldx = ldx;
     const int nb = (n + lc.rows_per_block - 1) / lc.rows_per_block;
     const bool tail = (int64_t)lc.threads * lc.chunks * Vec<T>::N != n;
     if (lc.streaming) {
@@ -510,16 +544,12 @@ hipError_t launch_sweep_level(const T *S, int64_t lds, const LevelPtrs<T> &lv, T
             hipLaunchKernelGGL((sweep_stream_kernel<T, 1024, false>), dim3(nb), dim3(1024), 0, st, a, lc.chunks);
         return hipGetLastError();
     }
-#define HAP_LAUNCH_SWEEP(NTC, NCHC)                                                                    \
-    do {                                                                                               \
-        if (tail)                                                                                      \
-            hipLaunchKernelGGL((sweep_kernel<T, NTC, NCHC, true>), dim3(nb), dim3(NTC), 0, st, a);     \
-        else                                                                                           \
-            hipLaunchKernelGGL((sweep_kernel<T, NTC, NCHC, false>), dim3(nb), dim3(NTC), 0, st, a);    \
-    } while (0)
-    HAP_DISPATCH_NT_NCH(lc.threads, lc.chunks, HAP_LAUNCH_SWEEP);
-#undef HAP_LAUNCH_SWEEP
-    return hipGetLastError();
+    if (X == nullptr) return launch_resident<T, 0>(a, lc, nb, tail, st);
+    if constexpr (sizeof(T) == 4) {
+        if (d == 2) return launch_resident<T, 2>(a, lc, nb, tail, st);
+        if (d == 3) return launch_resident<T, 3>(a, lc, nb, tail, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename T>
@@ -590,7 +620,8 @@ hipError_t launch_alpha_pad(T *A, int64_t rows, int n, int64_t ldw, hipStream_t 
 #define HAP_INSTANTIATE(T)                                                                                        \
     template hipError_t launch_alpha_pad<T>(T *, int64_t, int, int64_t, hipStream_t);                             \
     template hipError_t launch_sweep_level<T>(const T *, int64_t, const LevelPtrs<T> &, T *, const T *, int,      \
-                                              int64_t, double, T *, const Launch &, DevState *, hipStream_t);     \
+                                              int64_t, double, T *, const Launch &, DevState *, hipStream_t,      \
+                                              const T *, int64_t, int);                                           \
     template hipError_t launch_colsum<T>(const T *, int64_t, int, int, const LevelPtrs<T> &, const LevelPtrs<T> *, \
                                          T *, bool, bool, int, bool, DevState *, hipStream_t);                    \
     template hipError_t launch_finalize<T>(const T *, int64_t, const LevelPtrs<T> &, int, int64_t, double, int,   \

@@ -24,7 +24,7 @@ LAUNCH_STREAM = 2
 EXPORTS = (
     "hap_version", "hap_status_string", "hap_last_error", "hap_build_similarity",
     "hap_median_offdiag", "hap_workspace_size", "hap_init", "hap_iterate", "hap_exemplars",
-    "hap_net_similarity", "hap_preference", "hap_read_messages", "hap_set_launch",
+    "hap_net_similarity", "hap_preference", "hap_read_messages", "hap_set_launch", "hap_set_points",
     "hap_get_launch", "hap_profile", "hap_profile_read", "hap_destroy",
     "hap_batch_workspace_size", "hap_batch_create", "hap_batch_run", "hap_batch_set_launch",
     "hap_batch_get_launch", "hap_batch_destroy",
@@ -76,6 +76,7 @@ def _declare(lib):
         "hap_preference": (I32, [V, _c_dblp]),
         "hap_read_messages": (I32, [V, I32, V, V, I64, V, V, V]),
         "hap_set_launch": (I32, [V, I32, I32, I32, I32]),
+        "hap_set_points": (I32, [V, V, I64, I64, I32]),
         "hap_get_launch": (I32, [V, _c_i32p, _c_i32p, _c_i32p, _c_i32p]),
         "hap_profile": (I32, [V, I32]),
         "hap_profile_read": (I32, [V, _c_dblp, ctypes.POINTER(I64), _c_dblp, ctypes.POINTER(I64)]),
@@ -289,6 +290,17 @@ class Hap:
     def set_launch(self, threads=0, chunks=0, rows_per_block=0, streaming=None):
         flags = -1 if streaming is None else (LAUNCH_STREAM if streaming else 0)
         _check("hap_set_launch", self._lib.hap_set_launch(self._ctx, threads, chunks, rows_per_block, flags))
+
+    def set_points(self, X=None):
+        """Points mode: the row pass recomputes s_ij from X (the FP32 points S was built from
+        with BUILD_DIRECT, no noise) instead of reading S.  None switches it off."""
+        if X is None:
+            _check("hap_set_points", self._lib.hap_set_points(self._ctx, None, 0, 0, 0))
+            self._points_keep = None
+            return
+        _check("hap_set_points", self._lib.hap_set_points(self._ctx, ctypes.c_void_p(X.data_ptr()), X.shape[1],
+                                                          _ld(X), _dtype_code(X)))
+        self._points_keep = X
 
     def profile(self, enable: bool):
         _check("hap_profile", self._lib.hap_profile(self._ctx, 1 if enable else 0))

@@ -3,7 +3,8 @@
     python paper_1403_7394_amd/profile_run.py [--sweeps K] [--copy-gib G] [--n N]
 
 Builds the FP32 similarity of the 8192-point, 64-blob 2-D workload on the GPU, runs K full
-sweeps (all three levels, damping 0.9, no stop rule) and, before that, one device copy of
+sweeps (all three levels, damping 0.9, no stop rule; the row pass in points mode unless
+--read-s) and, before that, one device copy of
 G GiB (read G GiB, write G GiB) whose counter readings calibrate the HBM byte counters.
 Every kernel runs on torch's current stream; a line is printed after each step.
 """
@@ -23,6 +24,7 @@ def main() -> int:
     ap.add_argument("--sweeps", type=int, default=4)
     ap.add_argument("--copy-gib", type=float, default=1.0)
     ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--read-s", action="store_true", help="row pass reads S (default: points mode)")
     args = ap.parse_args()
 
     import torch
@@ -48,6 +50,8 @@ def main() -> int:
     S = torch.empty((n, n), dtype=torch.float32, device=dev)
     hap.build_similarity(X, S)
     h = hap.Hap(S, rp.levels, rp.damping)
+    if not args.read_s:
+        h.set_points(X)
     torch.cuda.synchronize()
     print(f"similarity and state ready: n={n} levels={rp.levels}", flush=True)
     res = h.iterate(args.sweeps)

@@ -1,0 +1,74 @@
+"""Points mode of the row pass (s_ij recomputed from the points instead of read from S)
+against the same run reading S, and against the FP32 oracle: bit-identical."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import hap_ref
+from oracle import similarity as sim
+from paper_1403_7394_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _run(hap, X, L, lam, T, points, launch=None):
+    n = X.shape[0]
+    Xt = torch.from_numpy(X).to(DEV)
+    S = torch.empty((n, n + (-n) % 4), dtype=torch.float32, device=DEV)[:, :n]
+    hap.build_similarity(Xt, S)
+    h = hap.Hap(S, L, lam)
+    if launch:
+        h.set_launch(*launch)
+    if points:
+        h.set_points(Xt)
+    res = h.iterate(T)
+    out = dict(labels=h.labels().cpu().numpy(), iters=res.iters,
+               msgs=[{k: v.cpu().numpy() for k, v in h.messages(l).items()} for l in range(L)])
+    h.close()
+    return out
+
+
+def _same(a, b, L):
+    assert np.array_equal(a["labels"], b["labels"])
+    for l in range(L):
+        for k in ("rho", "alpha", "c", "phi"):
+            assert np.array_equal(a["msgs"][l][k], b["msgs"][l][k]), (l, k)
+
+
+@pytest.mark.parametrize("n,d,launch", [(1000, 2, None), (1000, 2, (256, 1, 1)), (8192, 2, None),
+                                        (8192, 2, (1024, 2, 16)), (700, 3, None), (4096, 3, (512, 2, 8))])
+def test_points_mode_equals_reading_S(hap_gpu, n, d, launch):
+    b = synth.small_blobs(1200 + n + d, n, d=d, k=6, dtype=np.float32)
+    L, lam, T = 3, 0.9, 12
+    _same(_run(hap_gpu, b.X, L, lam, T, True, launch), _run(hap_gpu, b.X, L, lam, T, False, launch), L)
+
+
+def test_points_mode_matches_fp32_oracle(hap_gpu):
+    b = synth.small_blobs(1300, 600, d=2, k=5, dtype=np.float32)
+    L, lam, T = 2, 0.9, 15
+    g = _run(hap_gpu, b.X, L, lam, T, True, (256, 1, 1))
+    S32 = sim.similarity(b.X).astype(np.float32)
+    r = hap_ref.hap(S32, sim.median_offdiag(S32, np.float32), L, lam, T, dtype=np.float32)
+    assert np.array_equal(g["labels"], r.labels)
+    for l in range(L):
+        assert np.array_equal(g["msgs"][l]["rho"], r.state.rho[l])
+        assert np.array_equal(g["msgs"][l]["alpha"], r.state.alpha[l])
+
+
+def test_points_mode_rejects_unsupported_inputs(hap_gpu):
+    b = synth.small_blobs(1301, 100, d=4, k=3, dtype=np.float32)
+    Xt = torch.from_numpy(b.X).to(DEV)
+    S = torch.empty((100, 100), dtype=torch.float32, device=DEV)
+    hap_gpu.build_similarity(Xt, S)
+    h = hap_gpu.Hap(S, 1, 0.9)
+    with pytest.raises(hap_gpu.HapError):
+        h.set_points(Xt)                        # d = 4
+    with pytest.raises(hap_gpu.HapError):
+        h.set_points(Xt[:, :2].double())        # FP64 points
+    h.close()
+    S64 = S.double()
+    h = hap_gpu.Hap(S64, 1, 0.9)
+    with pytest.raises(hap_gpu.HapError):
+        h.set_points(Xt[:, :2].contiguous())    # FP64 context
+    h.close()
