@@ -96,11 +96,9 @@ __global__ __launch_bounds__(256) void build_direct_kernel(const TX *__restrict_
 // bf16(x) for BF16, hi + lo for BF16x3), summed in FP64, so that the diagonal cancels.
 // The clamp keeps S <= 0 where cancellation leaves a tiny positive value.
 //
-// One 256-thread workgroup owns a 128 x 128 tile of S; each wavefront a 64 x 64 quarter
-// as 4 x 4 blocks of 16 x 16 MFMA outputs (lane l, register r holds row 4*(l/16) + r,
-// column l%16 of a block).  Both operands are rows of X: the A fragment of a lane is
-// row (l%16) of the row block, the B fragment row (l%16) of the column block, with the
-// same k slots, so the k order inside a fragment does not matter.
+// Both operands are rows of X: the A fragment of a lane is row (l%16) of the row block, the
+// B fragment row (l%16) of the column block, with the same k slots, so the k order inside a
+// fragment does not matter.
 // ---------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -153,100 +151,130 @@ __global__ __launch_bounds__(256) void norms_kernel_f64(const double *__restrict
     out[i] = acc;
 }
 
+// Each workgroup owns a 128 x 128 tile of S; its four waves own 64 x 64 quarters as 4 x 4 MFMA
+// blocks.  The two 128-point slabs of X are staged through LDS in chunks of kKc coordinates
+// with 16-byte loads issued all at once (so a chunk costs one memory latency, not one per
+// k step), zero-filled past n and d; fragments are then read from LDS.  The same LDS holds
+// the output tile for the epilogue.
+constexpr int kKc = 64;               // coordinates per staged chunk
+constexpr int kXs = kKc + 4;          // padded LDS row of a staged slab
+constexpr int kTs = 128 + 4;          // padded LDS row of the output tile
+constexpr int kSmemFloats = (2 * 128 * kXs > 128 * kTs) ? 2 * 128 * kXs : 128 * kTs;
+
 template <int MODE>
 __global__ __launch_bounds__(256) void build_mfma_f32_kernel(const float *__restrict__ X, int n, int d, int64_t ldx,
                                                              const float *__restrict__ norms, float *__restrict__ S,
                                                              int64_t lds) {
 #pragma clang fp contract(off)
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __shared__ float smem[kSmemFloats];
+    float(*xs)[128][kXs] = reinterpret_cast<float(*)[128][kXs]>(smem);   // [0]: rows i, [1]: rows j
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lg = lane >> 4;
-    const int i0 = blockIdx.y * 128 + (wave >> 1) * 64;
-    const int j0 = blockIdx.x * 128 + (wave & 1) * 64;
+    const int bi = blockIdx.y * 128, bj = blockIdx.x * 128;
+    const int wi = (wave >> 1) * 64, wj = (wave & 1) * 64;
+    const bool vec_x = ((ldx & 3) == 0) && ((((uintptr_t)X) & 15) == 0);
     f32x4 acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = (f32x4)(0.f);
-    // rows this lane feeds into the A and B fragments (clamped; results past n are not stored)
-    const float *ra[4], *rb[4];
+
+    for (int k0 = 0; k0 < d; k0 += kKc) {
+        // stage both slabs: 2 x 128 rows x kKc coordinates, 16 bytes per access
+        for (int e = tid; e < 2 * 128 * (kKc / 4); e += 256) {
+            const int m = e / (128 * (kKc / 4));
+            const int rem = e % (128 * (kKc / 4));
+            const int r = rem / (kKc / 4), c4 = rem % (kKc / 4);
+            const int g = (m == 0 ? bi : bj) + r;
+            const int k = k0 + 4 * c4;
+            f32x4 v = (f32x4)(0.f);
+            if (g < n) {
+                const float *src = X + (int64_t)g * ldx + k;
+                if (vec_x && k + 3 < d) {
+                    v = *(const f32x4 *)src;
+                } else {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        ra[q] = X + (int64_t)min(i0 + 16 * q + lr, n - 1) * ldx;
-        rb[q] = X + (int64_t)min(j0 + 16 * q + lr, n - 1) * ldx;
-    }
-    if (MODE == kModeF32) {
-        for (int k0 = 0; k0 < d; k0 += 4) {
-            const int k = k0 + lg;
-            float fa[4], fb[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                fa[q] = k < d ? ra[q][k] : 0.f;
-                fb[q] = k < d ? rb[q][k] : 0.f;
-            }
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a], fb[b], acc[a][b], 0, 0, 0);
-        }
-    } else {
-        for (int k0 = 0; k0 < d; k0 += 32) {
-            const int kb = k0 + 8 * lg;
-            bf16x8 ha[4], hb[4], la[4], lb[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int k = kb + e;
-                    const float xa = k < d ? ra[q][k] : 0.f;
-                    const float xb = k < d ? rb[q][k] : 0.f;
-                    const __bf16 ya = to_bf16(xa), yb = to_bf16(xb);
-                    ha[q][e] = ya;
-                    hb[q][e] = yb;
-                    if (MODE == kModeBF16x3) {
-                        la[q][e] = to_bf16(xa - from_bf16(ya));
-                        lb[q][e] = to_bf16(xb - from_bf16(yb));
-                    }
+                    for (int q = 0; q < 4; ++q) v[q] = (k + q < d) ? src[q] : 0.f;
                 }
             }
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    if (MODE == kModeBF16x3) {
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(la[a], hb[b], acc[a][b], 0, 0, 0);
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[a], lb[b], acc[a][b], 0, 0, 0);
-                    }
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[a], hb[b], acc[a][b], 0, 0, 0);
-                }
+            *(f32x4 *)&xs[m][r][4 * c4] = v;   // rows of kXs floats keep 16-byte alignment
         }
+        __syncthreads();
+        const int kc = (d - k0) < kKc ? (d - k0) : kKc;
+        if (MODE == kModeF32) {
+            for (int kk = 0; kk < kc; kk += 4) {
+                float fa[4], fb[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    fa[q] = xs[0][wi + 16 * q + lr][kk + lg];
+                    fb[q] = xs[1][wj + 16 * q + lr][kk + lg];
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a], fb[b], acc[a][b], 0, 0, 0);
+            }
+        } else {
+            for (int kk = 0; kk < kc; kk += 32) {
+                bf16x8 ha[4], hb[4], la[4], lb[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float *pa = &xs[0][wi + 16 * q + lr][kk + 8 * lg];
+                    const float *pb = &xs[1][wj + 16 * q + lr][kk + 8 * lg];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const float xa = pa[e], xb = pb[e];
+                        const __bf16 ya = to_bf16(xa), yb = to_bf16(xb);
+                        ha[q][e] = ya;
+                        hb[q][e] = yb;
+                        if (MODE == kModeBF16x3) {
+                            la[q][e] = to_bf16(xa - from_bf16(ya));
+                            lb[q][e] = to_bf16(xb - from_bf16(yb));
+                        }
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        if (MODE == kModeBF16x3) {
+                            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(la[a], hb[b], acc[a][b], 0, 0, 0);
+                            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[a], lb[b], acc[a][b], 0, 0, 0);
+                        }
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha[a], hb[b], acc[a][b], 0, 0, 0);
+                    }
+            }
+        }
+        __syncthreads();
     }
-    // Epilogue: form S in the MFMA layout into an LDS tile, then write the 128 x 128 tile
-    // row by row with 16-byte stores (each row segment is 512 contiguous bytes).
-    __shared__ float tile[128][128 + 4];
-    const int ti = (wave >> 1) * 64, tj = (wave & 1) * 64;
+    // Epilogue: form S in the MFMA layout (lane l, register r of a block holds row
+    // 4*(l/16) + r, column l%16) into the LDS tile, then write the 128 x 128 tile row by row
+    // with 16-byte stores (each row segment is 512 contiguous bytes).
+    float(*tile)[kTs] = reinterpret_cast<float(*)[kTs]>(smem);
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int il = ti + 16 * a + 4 * lg + r;
-            const int i = blockIdx.y * 128 + il;
+            const int il = wi + 16 * a + 4 * lg + r;
+            const int i = bi + il;
             const float ni = norms[min(i, n - 1)];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const int jl = tj + 16 * b + lr;
-                const int j = blockIdx.x * 128 + jl;
+                const int jl = wj + 16 * b + lr;
+                const int j = bj + jl;
                 const float v = -((ni + norms[min(j, n - 1)]) - 2.f * acc[a][b][r]);
                 tile[il][jl] = (i == j) ? 0.f : fminf(0.f, v);
             }
         }
     }
     __syncthreads();
-    const int col4 = (threadIdx.x & 31) * 4;
-    const int jg = blockIdx.x * 128 + col4;
+    const int col4 = (tid & 31) * 4;
+    const int jg = bj + col4;
     const bool vec_ok = ((lds & 3) == 0) && ((((uintptr_t)S) & 15) == 0);
-    for (int rr = threadIdx.x >> 5; rr < 128; rr += 8) {
-        const int i = blockIdx.y * 128 + rr;
+    for (int rr = tid >> 5; rr < 128; rr += 8) {
+        const int i = bi + rr;
         if (i >= n) break;
         float *dst = S + (int64_t)i * lds + jg;
         if (vec_ok && jg + 3 < n) {
