@@ -122,9 +122,39 @@ def labels_of(state: HapState) -> np.ndarray:
     return np.argmax(state.alpha + state.rho, axis=2)
 
 
+def _iteration_mrhap(st: HapState, s, L: int, lam, oml, Q, record, c_zero: bool) -> None:
+    """One iteration of the MapReduce schedule (Section 3): every level is updated from the
+    state the previous iteration left.  The first job updates tau and c (both skipped in the
+    first iteration) and then rho at every level; the second updates phi (from the level
+    above's availabilities as they were before this job) and then alpha at every level."""
+    # job 1: tau and c from the previous state (not in the first iteration), then rho
+    if st.t >= 2:
+        c_new = st.c.copy()
+        for l in range(L - 1):
+            if not c_zero:
+                c_new[l] = np.max(st.alpha[l] + st.rho[l], axis=1)          # Eq. 2.6
+        for l in range(1, L):
+            st.tau[l] = c_new[l - 1] + column_sums(st.rho[l - 1])          # Eq. 2.4
+        st.c = c_new
+    for l in range(L):
+        rhat = responsibility(s[l], st.alpha[l], None if l == 0 else st.tau[l])   # Eq. 2.1
+        st.rho[l] = lam * st.rho[l] + oml * rhat
+    # job 2: phi from the level above's previous availabilities, then alpha
+    phi_new = st.phi.copy()
+    for l in range(L - 1):
+        phi_new[l] = np.max(st.alpha[l + 1] + s[l + 1], axis=1)            # Eq. 2.5
+    st.phi = phi_new
+    for l in range(L):
+        Q[l] = column_sums(st.rho[l])
+        B = (st.c[l] + st.phi[l]) + Q[l] if l < L - 1 else Q[l].copy()
+        st.alpha[l] = lam * st.alpha[l] + oml * availability(st.rho[l], B)  # Eq. 2.2 / 2.3
+        if record is not None:
+            record(st.t, l, st)
+
+
 def hap(S, pref, levels: int, damping: float, max_iters: int, stable_iters: int = 0,
         alpha0=None, state: HapState | None = None, record=None, c_zero: bool = False,
-        dtype=np.float64) -> HapResult:
+        dtype=np.float64, schedule: str = "sequential") -> HapResult:
     """Run HAP (Algorithm 1), in FP64 unless `dtype` says otherwise.
 
     The paper fixes no precision.  dtype=np.float32 evaluates the same steps with every
@@ -139,7 +169,12 @@ def hap(S, pref, levels: int, damping: float, max_iters: int, stable_iters: int 
     state  optional state to continue from (checkpoint / resume).
     record optional callable(t, l, state) called after every level update.
     c_zero diagnosis switch: keep c = 0 (a constant cluster preference) instead of Eq. 2.6.
+    schedule "sequential": the levels one after another inside an iteration (Algorithm 1);
+           "mrhap": the MapReduce schedule of Section 3 (every level from the previous
+           iteration's state; tau and c not updated in the first iteration).
     """
+    if schedule not in ("sequential", "mrhap"):
+        raise ValueError(schedule)
     dt = np.dtype(dtype).type
     S = np.asarray(S, dtype=dt)
     N = S.shape[0]
@@ -158,7 +193,9 @@ def hap(S, pref, levels: int, damping: float, max_iters: int, stable_iters: int 
     converged = False
     for _ in range(max_iters):
         st.t += 1
-        for l in range(L):
+        if schedule == "mrhap":
+            _iteration_mrhap(st, s, L, lam, oml, Q, record, c_zero)
+        for l in (range(L) if schedule == "sequential" else ()):
             # Eq. 2.1, then damp
             rhat = responsibility(s[l], st.alpha[l], None if l == 0 else st.tau[l])
             st.rho[l] = lam * st.rho[l] + oml * rhat

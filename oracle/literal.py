@@ -11,8 +11,10 @@ loops and no algebraic shortcut:
   Eq. 2.5  phi^{l-1}_i = max_k(alpha^l_ik + s^l_ik)
   Eq. 2.6  c^l_i = max_j(alpha^l_ij + rho^l_ij)
   Eq. 2.8  e^l_i = argmax_j(alpha^l_ij + rho^l_ij), lowest index on ties
-The schedule and readings are the same as in ``hap_ref``.  The cost is O(L N^3)
-per iteration, so this is for N <= 8 only.
+The schedule and readings are the same as in ``hap_ref`` (schedule="mrhap" gives the
+MapReduce schedule of Section 3: every level from the previous iteration's state, tau and
+c not updated in the first iteration).  The cost is O(L N^3) per iteration, so this is for
+N <= 8 only.
 
 The number type is a parameter.  With ``fractions.Fraction`` inputs (integer
 similarities, a rational damping such as 1/2 or 9/10) every operation (+, *,
@@ -28,7 +30,16 @@ def _min_tau(tau, x):
     return x if tau is None else (tau if tau < x else x)
 
 
-def hap_literal(S, pref, levels, damping, iters, num=Fraction):
+def _colsum_plus(rho_l, j, N, zero, c_j):
+    """c_j + rho_jj + sum_{k != j} max(0, rho_kj) (the right-hand side of Eq. 2.4)."""
+    acc = c_j + rho_l[j][j]
+    for k in range(N):
+        if k != j:
+            acc = acc + max(zero, rho_l[k][j])
+    return acc
+
+
+def hap_literal(S, pref, levels, damping, iters, num=Fraction, schedule="sequential"):
     """S: N x N nested lists/array (diagonal ignored); pref: L x N; damping: number.
 
     Returns (labels, rho, alpha, c, phi, tau) as nested lists of `num`.
@@ -46,56 +57,76 @@ def hap_literal(S, pref, levels, damping, iters, num=Fraction):
     phi = [[zero] * N for _ in range(L)]
     tau = [[None] * N for _ in range(L)]
 
-    for _t in range(iters):
-        for l in range(L):
-            # Eq. 2.1 with damping
-            new_rho = [[None] * N for _ in range(N)]
-            for i in range(N):
-                for j in range(N):
-                    mx = None
-                    for k in range(N):
-                        if k == j:
-                            continue
-                        v = alpha[l][i][k] + s[l][i][k]
-                        if mx is None or v > mx:
-                            mx = v
-                    r = s[l][i][j] - mx if l == 0 else s[l][i][j] + _min_tau(tau[l][i], -mx)
-                    new_rho[i][j] = lam * rho[l][i][j] + (one - lam) * r
-            rho[l] = new_rho
-            # Eq. 2.2 / 2.3 with damping
-            top = (l == L - 1)
-            new_alpha = [[None] * N for _ in range(N)]
+    def rho_update(l):
+        # Eq. 2.1 with damping
+        new_rho = [[None] * N for _ in range(N)]
+        for i in range(N):
             for j in range(N):
-                base = zero if top else c[l][j] + phi[l][j]
-                for i in range(N):
-                    if i == j:
-                        acc = base
-                        for k in range(N):
-                            if k != j:
-                                acc = acc + max(zero, rho[l][k][j])
-                        a = acc
-                    else:
-                        acc = base + rho[l][j][j]
-                        for k in range(N):
-                            if k != i and k != j:
-                                acc = acc + max(zero, rho[l][k][j])
-                        a = min(zero, acc)
-                    new_alpha[i][j] = lam * alpha[l][i][j] + (one - lam) * a
-            alpha[l] = new_alpha
-            # Eq. 2.4 (c^l from before its update), 2.5, 2.6
-            if l < L - 1:
-                nt = []
-                for j in range(N):
-                    acc = c[l][j] + rho[l][j][j]
+                mx = None
+                for k in range(N):
+                    if k == j:
+                        continue
+                    v = alpha[l][i][k] + s[l][i][k]
+                    if mx is None or v > mx:
+                        mx = v
+                r = s[l][i][j] - mx if l == 0 else s[l][i][j] + _min_tau(tau[l][i], -mx)
+                new_rho[i][j] = lam * rho[l][i][j] + (one - lam) * r
+        rho[l] = new_rho
+
+    def alpha_update(l):
+        # Eq. 2.2 / 2.3 with damping
+        top = (l == L - 1)
+        new_alpha = [[None] * N for _ in range(N)]
+        for j in range(N):
+            base = zero if top else c[l][j] + phi[l][j]
+            for i in range(N):
+                if i == j:
+                    acc = base
                     for k in range(N):
                         if k != j:
                             acc = acc + max(zero, rho[l][k][j])
-                    nt.append(acc)
-                tau[l + 1] = nt
+                    a = acc
+                else:
+                    acc = base + rho[l][j][j]
+                    for k in range(N):
+                        if k != i and k != j:
+                            acc = acc + max(zero, rho[l][k][j])
+                    a = min(zero, acc)
+                new_alpha[i][j] = lam * alpha[l][i][j] + (one - lam) * a
+        alpha[l] = new_alpha
+
+    def c_of(l):
+        return [max(alpha[l][i][j] + rho[l][i][j] for j in range(N)) for i in range(N)]
+
+    for t in range(1, iters + 1):
+        if schedule == "mrhap":
+            # first job: tau and c from the previous state (not at t = 1), then rho
+            if t >= 2:
+                new_c = [c_of(l) if l < L - 1 else c[l] for l in range(L)]
+                for l in range(1, L):
+                    tau[l] = [_colsum_plus(rho[l - 1], j, N, zero, new_c[l - 1][j]) for j in range(N)]
+                for l in range(L):
+                    c[l] = new_c[l]
+            for l in range(L):
+                rho_update(l)
+            # second job: phi from the level above's previous alpha, then alpha
+            new_phi = [[max(alpha[l + 1][i][k] + s[l + 1][i][k] for k in range(N)) for i in range(N)]
+                       if l < L - 1 else phi[l] for l in range(L)]
+            for l in range(L):
+                phi[l] = new_phi[l]
+            for l in range(L):
+                alpha_update(l)
+            continue
+        for l in range(L):
+            rho_update(l)
+            alpha_update(l)
+            # Eq. 2.4 (c^l from before its update), 2.5, 2.6
+            if l < L - 1:
+                tau[l + 1] = [_colsum_plus(rho[l], j, N, zero, c[l][j]) for j in range(N)]
             if l > 0:
                 phi[l - 1] = [max(alpha[l][i][k] + s[l][i][k] for k in range(N)) for i in range(N)]
             if l < L - 1:
-                c[l] = [max(alpha[l][i][j] + rho[l][i][j] for j in range(N)) for i in range(N)]
+                c[l] = c_of(l)
 
     labels = []
     for l in range(L):
