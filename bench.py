@@ -17,7 +17,7 @@ The roofline entry is for the dominant kernel, the fused row pass: its
 algorithmic traffic (read R, A and write R, A: 4 N^2 words per level per sweep,
 3 N^2 in the first sweep, which has no alpha to finish; 5 N^2 and 4 N^2 when S is
 read) divided by its average launch duration, measured with HIP events recorded
-on its own stream during the timed steps.
+on its own stream around the launches of every 8th sweep of the timed steps.
 """
 from __future__ import annotations
 
@@ -38,6 +38,7 @@ TRAFFIC_FILES = {True: os.path.join(ROOT, "profiles", "row_pass_traffic_plain819
                  False: os.path.join(ROOT, "profiles", "row_pass_traffic_plain8192.json")}
 SWEEP_SRC = os.path.join(ROOT, "paper_1403_7394_amd", "csrc", "sweep.hip")
 ROWPASS_SRC = os.path.join(ROOT, "paper_1403_7394_amd", "csrc", "rowpass.h")
+PROF_EVERY = 8
 
 
 def _hash16(path: str) -> str:
@@ -330,7 +331,36 @@ def run_warm_form(args, torch, hap, synth) -> dict:
             "net_similarity_rel_diff": [(a - b) / abs(b) for a, b in zip(warm_r["net_similarity"],
                                                                        cold["net_similarity"])],
         }
-        del S, ws, X, m
+        del S, ws, X
+        # held-out problems from the training distribution (2-D, 8192 points, new k and seeds)
+        held = []
+        ws_h = torch.empty(hap.workspace_size(n_tr, L, hap.HAP_F32), dtype=torch.uint8, device=dev)
+        for k in (5, 12, 24, 48, 96):
+            b = synth.gaussian_blobs(9001 + k, n_tr, 2, k, centre="uniform", centre_scale=10.0, sigma_lo=1.0,
+                                     sigma_hi=1.0, sizes="multinomial", dtype=np.float32)
+            hap.build_similarity(torch.from_numpy(b.X).to(dev), S_tr)
+            rows = {}
+            for warm in (False, True):
+                h = hap.Hap(S_tr, L, rp.damping, workspace=ws_h)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if warm:
+                    res, fell = h.iterate_warm(m.forward(h.warm_features()), iters, K)
+                else:
+                    res, fell = h.iterate(iters, K), False
+                lab = h.labels().cpu().numpy()
+                torch.cuda.synchronize()
+                rows[warm] = (res, fell, time.perf_counter() - t0, lab, h.net_similarity(-1))
+                h.close()
+            (rc_, _, tc, lc, nc), (rw_, fw, tw, lw, nw) = rows[False], rows[True]
+            held.append({"k": k, "cold_iters": rc_.iters, "cold_converged": rc_.converged, "warm_iters": rw_.iters,
+                         "warm_converged": rw_.converged, "fell_back": fw, "cold_s": tc, "warm_s": tw,
+                         "exemplar_agreement": float(np.mean(lc == lw)),
+                         "adjusted_rand_index": [_ari(lc[l], lw[l]) for l in range(L)],
+                         "net_similarity_rel_diff": (nw - nc) / abs(nc)})
+        out["levels"][str(L)]["held_out_2d_8192"] = held
+        print(json.dumps({"form": "warm", "levels": L, "held_out": held}), file=sys.stderr, flush=True)
+        del ws_h, m
         torch.cuda.empty_cache()
     return out
 
@@ -349,6 +379,8 @@ def main() -> int:
                          "batched: many problems in one launch; warm: the learned warm start")
     ap.add_argument("--form-iters", type=int, default=0, help="iterations for a form run (0 = the workload's)")
     ap.add_argument("--read-s", action="store_true", help="plain form: the row pass reads S (no points mode)")
+    ap.add_argument("--schedule", choices=["sequential", "mrhap"], default="sequential",
+                    help="plain form: Algorithm 1's level-sequential schedule or the MapReduce one (Section 3)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -390,14 +422,17 @@ def main() -> int:
         del src, dst
 
     points = not args.read_s
+    schedule = hap.SCHEDULE_MRHAP if args.schedule == "mrhap" else hap.SCHEDULE_SEQUENTIAL
 
     def step(profile: bool):
         hap.build_similarity(X, S)
-        h = hap.Hap(S, L, rp.damping, workspace=ws)
+        h = hap.Hap(S, L, rp.damping, workspace=ws, schedule=schedule)
         if points:
             h.set_points(X)
         if profile:
-            h.profile(True)
+            # event pairs around the launches of every PROF_EVERY-th sweep: enough launches for
+            # a stable average without the events' own overhead on every launch
+            h.profile(True, every=PROF_EVERY)
         res = h.iterate(rp.max_iters, rp.stable_iters)
         prof = h.profile_read() if profile else None
         counts = [h.exemplars(l)[1] for l in range(L)]
@@ -455,6 +490,7 @@ def main() -> int:
             "workload": "plain HAP, 8192 points in 2-D, 64 Gaussian blobs, FP32, L=3, damping 0.9, "
                         "median preference, 500 iterations or 50 stable",
             "row_pass": "points mode (s_ij recomputed from the points)" if points else "reads S",
+            "schedule": args.schedule,
             "n": n, "levels": L, "damping": rp.damping, "max_iters": rp.max_iters,
             "stable_iters": rp.stable_iters, "seed": blobs.seed,
         },
@@ -468,12 +504,15 @@ def main() -> int:
             "kernel": "row pass (sweep_kernel, points mode)" if points else "row pass (sweep_kernel)",
             "avg_launch_us": avg_launch_s * 1e6,
             "alg_bytes_per_launch": bytes_per_launch,
-            "launches": row_n,
+            "launches_timed": row_n,
+            "launches": int(sweeps * L),
+            "timed_every": PROF_EVERY,
         },
         "sweeps_per_step": sweeps / args.steps,
         "converged": bool(res.converged),
         "time_to_converge_ms": ms_per_step,
-        "sweep_updates_per_s": n * n * L * sweeps / ((row_ms + col_ms) * 1e-3) if row_ms > 0 else None,
+        # the timed sweeps' kernel time only (row passes and column sums, no host work)
+        "sweep_updates_per_s": n * n * row_n / ((row_ms + col_ms) * 1e-3) if row_ms > 0 else None,
         "colsum_avg_us": col_ms / max(col_n, 1) * 1e3,
         "exemplars_per_level": counts,
         "net_similarity": ns,

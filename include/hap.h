@@ -78,12 +78,21 @@ enum {
     HAP_PREF_VECTOR = 2     /* pref_vec[l*n + j], device, in the working type */
 };
 
+/* Iteration schedules. */
+enum {
+    HAP_SCHEDULE_SEQUENTIAL = 0, /* Algorithm 1: the levels one after another inside an iteration */
+    HAP_SCHEDULE_MRHAP = 1       /* Section 3 (MapReduce): every level from the previous iteration's
+                                    state; tau and c (Eq. 2.4, 2.6) are not updated in the first
+                                    iteration, phi (Eq. 2.5) uses the level above's availabilities
+                                    from before the iteration's availability update */
+};
+
 typedef struct {
     uint32_t struct_size;       /* sizeof(hap_params) */
     int32_t levels;             /* L >= 1 */
     double damping;             /* lambda in [0, 1) */
     int32_t pref_mode;          /* HAP_PREF_* */
-    int32_t reserved0;
+    int32_t schedule;           /* HAP_SCHEDULE_* */
     const double *pref_scalar;  /* host [levels], HAP_PREF_SCALAR only */
     const void *pref_vec;       /* device [levels*n] in the working type, HAP_PREF_VECTOR only */
 } hap_params;
@@ -182,14 +191,16 @@ HAP_API hap_status hap_read_messages(hap_ctx *ctx, int32_t level, void *rho, voi
  * 16-byte column chunks per thread (1, 2, 4 or 8; 4 needs <= 512 threads, 8 needs
  * <= 256) and rows per workgroup (>= 1; 1 sums the column partials in row
  * order).  threads * chunks * (16 / element size) must cover n.  0 keeps the
- * library's choice for that field.  flags: HAP_LAUNCH_STREAM selects the
- * streaming row pass for long rows (1024 threads, 1 to 16 chunks; the row is
- * read again from the caches in its second phase); 0 selects the
- * register-resident row pass; -1 keeps the current choice.
- * Returns HAP_E_ARG (and changes nothing) for a shape that does not fit.  For
- * the autotuner.
+ * library's choice for that field.  flags (a bit set; -1 keeps the current
+ * choices): HAP_LAUNCH_STREAM selects the streaming row pass for long rows (1024
+ * threads, 1 to 16 chunks; the row is read again from the caches in its second
+ * phase), otherwise the register-resident row pass; HAP_LAUNCH_EAGER issues every
+ * launch from the host instead of replaying captured graphs of sweep chunks (the
+ * default captures each chunk of up to 16 sweeps once on a private stream and
+ * replays it on the context's stream).  Returns HAP_E_ARG (and changes nothing)
+ * for a shape that does not fit.  For the autotuner and for comparisons.
  */
-enum { HAP_LAUNCH_STREAM = 2 };
+enum { HAP_LAUNCH_STREAM = 2, HAP_LAUNCH_EAGER = 4 };
 HAP_API hap_status hap_set_launch(hap_ctx *ctx, int32_t threads, int32_t chunks, int32_t rows_per_block,
                                   int32_t flags);
 HAP_API hap_status hap_get_launch(hap_ctx *ctx, int32_t *threads, int32_t *chunks, int32_t *rows_per_block,
@@ -209,11 +220,12 @@ HAP_API hap_status hap_set_points(hap_ctx *ctx, const void *X, int64_t d, int64_
 
 /*
  * Per-launch timing of the sweep kernels with HIP events recorded on the
- * context's stream around every launch.  enable = 1 starts collecting (and
- * clears the totals), 0 stops.  hap_profile_read returns the summed elapsed time
- * (ms) and the launch count of the row pass (Eq. 2.1-2.6 fused, one launch per
- * level and iteration) and of the column-sum epilogue (Eq. 2.4).  For the
- * benchmark's roofline figure.
+ * context's stream around the launches.  enable = k >= 1 starts collecting (and
+ * clears the totals) for the launches of every k-th sweep (1: every launch), 0 stops.
+ * hap_profile_read returns the summed elapsed time (ms) and the count of the timed
+ * launches of the row pass (Eq. 2.1-2.6 fused, one launch per level and iteration)
+ * and of the column-sum epilogue (Eq. 2.4).  Timed sweeps are launched one kernel at
+ * a time (never from a captured graph).  For the benchmark's roofline figure.
  */
 HAP_API hap_status hap_profile(hap_ctx *ctx, int32_t enable);
 HAP_API hap_status hap_profile_read(hap_ctx *ctx, double *row_pass_ms, int64_t *row_pass_launches,

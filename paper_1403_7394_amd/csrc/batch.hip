@@ -208,6 +208,10 @@ __global__ __launch_bounds__(NT) void batch_kernel(BatchArgs g) {
                 a.Qpart = nullptr;
                 a.X = nullptr;
                 a.ldx = 0;
+                a.tau_c = nullptr;
+                a.tau_q = nullptr;
+                a.tau_store = nullptr;
+                a.mrhap = 0;
                 a.n = n;
                 a.rb = n;
                 a.lam = g.lam;

@@ -30,6 +30,7 @@ struct hap_ctx {
     hipStream_t stream = nullptr;
     int64_t n = 0, lds = 0, ldw = 0;
     int L = 0;
+    int schedule = HAP_SCHEDULE_SEQUENTIAL;
     int dtype = HAP_F32;
     size_t esz = 4;
     double lam = 0.0;
@@ -56,11 +57,25 @@ struct hap_ctx {
     Launch lc{};
     // per-launch event timing (hap_profile)
     bool prof = false;
+    int prof_period = 1;          // time the launches of every prof_period-th sweep
+    long long prof_sweep = 0;     // sweeps issued since timing was switched on
+    bool prof_now = false;        // the current sweep's launches are timed
     std::vector<hipEvent_t> ev;      // pairs: [2k] before, [2k+1] after launch k of the current chunk
     std::vector<int> ev_kind;        // 0 = row pass, 1 = column sums
     int ev_used = 0;
     double prof_ms[2] = {0.0, 0.0};
     long long prof_n[2] = {0, 0};
+    // replayable graphs of sweep chunks (key: sweeps, stop-rule K)
+    struct GraphEntry {
+        int count, K;
+        bool prof;
+        hipGraphExec_t exec;
+        int ev_pairs;
+    };
+    std::vector<GraphEntry> graphs;
+    hipStream_t cap_stream = nullptr;
+    bool use_graphs = true;       // HAP_LAUNCH_EAGER switches them off
+    bool graphs_broken = false;   // capture is not available: launch eagerly
     int t_host = 0;               // completed iterations, mirrored on the host
     bool labels_ready = false;    // Efinal holds the labels of iteration t_host
     bool failed = false;
@@ -101,7 +116,7 @@ Layout make_layout(int64_t n, int L, size_t esz) {
     lo.Efinal = take((size_t)lo.ldw * 4 * L);
     lo.mark = take((size_t)lo.ldw * 4);
     lo.count = take(64);
-    lo.Qpart = take((size_t)lo.nb_cap * vec);
+    lo.Qpart = take((size_t)2 * lo.nb_cap * vec);   // two buffers (the MapReduce schedule alternates)
     lo.ds = take(sizeof(DevState));
     lo.dbl = take(sizeof(double) * (size_t)(L + 4));
     lo.sel = take(hap::select_scratch_bytes());
@@ -205,7 +220,7 @@ bool ld_ok(int64_t n, int64_t ld, int32_t dt) {
 
 // Event pair around the next launch when profiling (the pool grows on demand).
 hipError_t prof_mark(hap_ctx *c, int kind, bool after) {
-    if (!c->prof) return hipSuccess;
+    if (!c->prof || !c->prof_now) return hipSuccess;
     if (!after) {
         const size_t need = (size_t)(c->ev_used + 1) * 2;
         while (c->ev.size() < need) {
@@ -240,26 +255,119 @@ template <typename T>
 hap_status run_sweeps(hap_ctx *c, int count, int K) {
     const int L = c->L;
     const int nb = (int)((c->n + c->lc.rows_per_block - 1) / c->lc.rows_per_block);
-    T *Qpart = (T *)c->Qpart;
+    T *Qpart[2] = {(T *)c->Qpart, (T *)c->Qpart + (size_t)c->nb_cap * c->ldw};
+    hap::SweepExtra<T> ex;
+    ex.X = (const T *)c->X;
+    ex.ldx = c->ldx;
+    ex.d = c->d;
+    auto row = [&](int l, T *qp) -> hap_status {
+        LevelPtrs<T> lv = level_ptrs<T>(c, l);
+        LevelPtrs<T> down = level_ptrs<T>(c, l > 0 ? l - 1 : 0);
+        T *phi_down = l > 0 ? down.phi : nullptr;
+        hap::SweepExtra<T> e = ex;
+        const T *tau_l = nullptr;
+        if (c->schedule == HAP_SCHEDULE_MRHAP) {
+            e.mrhap = 1;
+            if (l > 0) {
+                e.tau_c = down.C;      // c^{l-1} of this iteration (its row pass ran just before)
+                e.tau_q = down.Q;      // column sums of the previous iteration
+                e.tau_store = lv.tau;
+            }
+        } else if (l > 0) {
+            tau_l = lv.tau;
+        }
+        HIP_TRY(prof_mark(c, 0, false), c);
+        HIP_TRY(hap::launch_sweep_level<T>((const T *)c->S, c->lds, lv, phi_down, tau_l, (int)c->n, c->ldw, c->lam,
+                                           qp, c->lc, c->ds, c->stream, e),
+                c);
+        HIP_TRY(prof_mark(c, 0, true), c);
+        return HAP_OK;
+    };
+    auto col = [&](int l, T *qp, bool with_tau) -> hap_status {
+        LevelPtrs<T> lv = level_ptrs<T>(c, l);
+        LevelPtrs<T> down = level_ptrs<T>(c, l > 0 ? l - 1 : 0);
+        T *tau_next = (with_tau && l + 1 < L) ? level_ptrs<T>(c, l + 1).tau : nullptr;
+        HIP_TRY(prof_mark(c, 1, false), c);
+        HIP_TRY(hap::launch_colsum<T>(qp, c->ldw, nb, (int)c->n, lv, l > 0 ? &down : nullptr, tau_next, l == L - 1,
+                                      l == L - 1, K, c->lc.ordered, c->ds, c->stream),
+                c);
+        HIP_TRY(prof_mark(c, 1, true), c);
+        return HAP_OK;
+    };
     for (int it = 0; it < count; ++it) {
-        for (int l = 0; l < L; ++l) {
-            LevelPtrs<T> lv = level_ptrs<T>(c, l);
-            LevelPtrs<T> down = level_ptrs<T>(c, l > 0 ? l - 1 : 0);
-            T *phi_down = l > 0 ? down.phi : nullptr;
-            const T *tau_l = l > 0 ? lv.tau : nullptr;
-            HIP_TRY(prof_mark(c, 0, false), c);
-            HIP_TRY(hap::launch_sweep_level<T>((const T *)c->S, c->lds, lv, phi_down, tau_l, (int)c->n, c->ldw, c->lam,
-                                               Qpart, c->lc, c->ds, c->stream, (const T *)c->X, c->ldx, c->d),
-                    c);
-            HIP_TRY(prof_mark(c, 0, true), c);
-            T *tau_next = (l + 1 < L) ? level_ptrs<T>(c, l + 1).tau : nullptr;
-            HIP_TRY(prof_mark(c, 1, false), c);
-            HIP_TRY(hap::launch_colsum<T>(Qpart, c->ldw, nb, (int)c->n, lv, l > 0 ? &down : nullptr, tau_next,
-                                          l == L - 1, l == L - 1, K, c->lc.ordered, c->ds, c->stream),
-                    c);
-            HIP_TRY(prof_mark(c, 1, true), c);
+        c->prof_now = c->prof && (c->prof_sweep++ % c->prof_period == 0);
+        if (c->schedule == HAP_SCHEDULE_MRHAP) {
+            // Every row pass reads the previous iteration's column sums, so the column sums of
+            // level l-1 run after the row pass of level l (two partial buffers alternate).
+            hap_status s = row(0, Qpart[0]);
+            for (int l = 1; l < L && s == HAP_OK; ++l) {
+                s = row(l, Qpart[l & 1]);
+                if (s == HAP_OK) s = col(l - 1, Qpart[(l - 1) & 1], false);
+            }
+            if (s == HAP_OK) s = col(L - 1, Qpart[(L - 1) & 1], false);
+            if (s != HAP_OK) return s;
+        } else {
+            for (int l = 0; l < L; ++l) {
+                hap_status s = row(l, Qpart[0]);
+                if (s == HAP_OK) s = col(l, Qpart[0], true);
+                if (s != HAP_OK) return s;
+            }
         }
     }
+    return HAP_OK;
+}
+
+void drop_graphs(hap_ctx *c) {
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+}
+
+// One chunk of sweeps.  The chunk's launches are captured once into a graph on a private
+// stream and replayed on the context's stream, which removes the per-launch host overhead
+// between the short kernels.  The kernels read the iteration counter from device memory, so
+// every replay continues the run.  Per-launch timing (hap_profile) needs events around each
+// launch that the host can read back, so timed chunks are launched one kernel at a time, as
+// they are when capture is not available.
+template <typename T>
+hap_status launch_chunk(hap_ctx *c, int count, int K) {
+    if (!c->use_graphs || c->graphs_broken || c->prof) return run_sweeps<T>(c, count, K);
+    hap_ctx::GraphEntry *ge = nullptr;
+    for (auto &g : c->graphs)
+        if (g.count == count && g.K == K && g.prof == c->prof) ge = &g;
+    if (!ge) {
+        auto give_up = [&]() {
+            (void)hipGetLastError();
+            c->graphs_broken = true;
+            c->failed = false;
+            return run_sweeps<T>(c, count, K);
+        };
+        if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+            c->cap_stream = nullptr;
+            return give_up();
+        }
+        const int ev0 = c->ev_used;
+        if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return give_up();
+        hipStream_t saved = c->stream;
+        c->stream = c->cap_stream;
+        const hap_status s = run_sweeps<T>(c, count, K);
+        c->stream = saved;
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+        const int pairs = c->ev_used - ev0;
+        c->ev_used = ev0;
+        if (s != HAP_OK || e != hipSuccess || graph == nullptr) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return give_up();
+        }
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return give_up();
+        c->graphs.push_back({count, K, c->prof, exec, pairs});
+        ge = &c->graphs.back();
+    }
+    HIP_TRY(hipGraphLaunch(ge->exec, c->stream), c);
+    c->ev_used += ge->ev_pairs;
     return HAP_OK;
 }
 
@@ -368,6 +476,8 @@ hap_status hap_init(hap_ctx **out, const void *S, int64_t n, int64_t lds, int32_
     } else if (p->pref_mode != HAP_PREF_MEDIAN) {
         return fail_arg("hap_init: pref_mode");
     }
+    if (p->schedule != HAP_SCHEDULE_SEQUENTIAL && p->schedule != HAP_SCHEDULE_MRHAP)
+        return fail_arg("hap_init: schedule");
     const size_t esz = dtype_size(dtype);
     Layout lo = make_layout(n, p->levels, esz);
     Launch lc = default_launch(n, esz);
@@ -390,6 +500,7 @@ hap_status hap_init(hap_ctx **out, const void *S, int64_t n, int64_t lds, int32_
     c->lds = lds;
     c->ldw = lo.ldw;
     c->L = p->levels;
+    c->schedule = p->schedule;
     c->dtype = dtype;
     c->esz = esz;
     c->lam = p->damping;
@@ -482,8 +593,8 @@ hap_status hap_iterate(hap_ctx *c, int32_t max_iters, int32_t stable_iters, int3
     bool stopped = false;
     while (left > 0) {
         const int now = left < chunk ? left : chunk;
-        hap_status s = (c->dtype == HAP_F32) ? run_sweeps<float>(c, now, stable_iters)
-                                             : run_sweeps<double>(c, now, stable_iters);
+        hap_status s = (c->dtype == HAP_F32) ? launch_chunk<float>(c, now, stable_iters)
+                                             : launch_chunk<double>(c, now, stable_iters);
         if (s != HAP_OK) return s;
         left -= now;
         if (c->prof) {
@@ -599,27 +710,38 @@ hap_status hap_read_messages(hap_ctx *c, int32_t level, void *rho, void *alpha, 
     // alpha^{l,t} and c^l = max_j(alpha + rho) of the top level are not part of the method's state
     // (c is unused there); c of the top level is reported as 0.
     const bool top = level == c->L - 1;
-    if (alpha || (cvec && !top)) {
+    // Under the MapReduce schedule c^l and phi^l of iteration t are the values the row passes
+    // of iteration t computed (from the state of iteration t-1) and stored; under the
+    // level-sequential schedule they are recomputed from alpha^t and rho^t.
+    const bool mr = c->schedule == HAP_SCHEDULE_MRHAP;
+    void *c_fin = (cvec && !top && !mr) ? cvec : nullptr;
+    if (alpha || c_fin) {
         if (c->dtype == HAP_F32) {
             LevelPtrs<float> lv = level_ptrs<float>(c, level);
             HIP_TRY(hap::launch_finalize<float>((const float *)c->S, c->lds, lv, (int)c->n, c->ldw, c->lam, c->t_host,
-                                                nullptr, (float *)alpha, ld, top ? nullptr : (float *)cvec, nullptr,
-                                                c->ds, st),
+                                                nullptr, (float *)alpha, ld, (float *)c_fin, nullptr, c->ds, st),
                     c);
         } else {
             LevelPtrs<double> lv = level_ptrs<double>(c, level);
             HIP_TRY(hap::launch_finalize<double>((const double *)c->S, c->lds, lv, (int)c->n, c->ldw, c->lam, c->t_host,
-                                                 nullptr, (double *)alpha, ld, top ? nullptr : (double *)cvec, nullptr,
-                                                 c->ds, st),
+                                                 nullptr, (double *)alpha, ld, (double *)c_fin, nullptr, c->ds, st),
                     c);
         }
+    }
+    if (cvec && mr && !top && c->t_host > 0) {
+        const char *src = c->C + (size_t)c->ldw * esz * level;
+        HIP_TRY(hipMemcpyAsync(cvec, src, (size_t)c->n * esz, hipMemcpyDeviceToDevice, st), c);
     }
     if (cvec && top) HIP_TRY(hipMemsetAsync(cvec, 0, (size_t)c->n * esz, st), c);
     if (cvec && c->t_host == 0) HIP_TRY(hipMemsetAsync(cvec, 0, (size_t)c->n * esz, st), c);
     if (phi) {
-        // phi^l after iteration t is max_k(alpha^{l+1,t}_ik + s_ik); 0 at the top level and before iteration 1
+        // phi^l after iteration t is max_k(alpha^{l+1,t}_ik + s_ik) (level-sequential) or the
+        // stored phi^l of iteration t (MapReduce); 0 at the top level and before iteration 1
         if (top || c->t_host == 0) {
             HIP_TRY(hipMemsetAsync(phi, 0, (size_t)c->n * esz, st), c);
+        } else if (mr) {
+            const char *src = c->phi + (size_t)c->ldw * esz * level;
+            HIP_TRY(hipMemcpyAsync(phi, src, (size_t)c->n * esz, hipMemcpyDeviceToDevice, st), c);
         } else if (c->dtype == HAP_F32) {
             LevelPtrs<float> up = level_ptrs<float>(c, level + 1);
             HIP_TRY(hap::launch_finalize<float>((const float *)c->S, c->lds, up, (int)c->n, c->ldw, c->lam, c->t_host,
@@ -670,6 +792,8 @@ hap_status hap_set_launch(hap_ctx *c, int32_t threads, int32_t chunks, int32_t r
     lc.ordered = (lc.rows_per_block == 1);
     if (!launch_fits(lc, c->n, c->esz, c->nb_cap)) return fail_arg("hap_set_launch: shape does not fit this problem");
     c->lc = lc;
+    if (flags >= 0) c->use_graphs = (flags & HAP_LAUNCH_EAGER) == 0;
+    drop_graphs(c);
     return HAP_OK;
 }
 
@@ -679,6 +803,7 @@ hap_status hap_set_points(hap_ctx *c, const void *X, int64_t d, int64_t ldx, int
         c->X = nullptr;
         c->ldx = 0;
         c->d = 0;
+        drop_graphs(c);
         return HAP_OK;
     }
     if (c->dtype != HAP_F32 || x_dtype != HAP_F32)
@@ -688,12 +813,13 @@ hap_status hap_set_points(hap_ctx *c, const void *X, int64_t d, int64_t ldx, int
     c->X = X;
     c->ldx = ldx;
     c->d = (int)d;
+    drop_graphs(c);
     return HAP_OK;
 }
 
 hap_status hap_get_launch(hap_ctx *c, int32_t *threads, int32_t *chunks, int32_t *rows_per_block, int32_t *flags) {
     if (!c) return fail_arg("hap_get_launch: null context");
-    if (flags) *flags = c->lc.streaming ? HAP_LAUNCH_STREAM : 0;
+    if (flags) *flags = (c->lc.streaming ? HAP_LAUNCH_STREAM : 0) | (c->use_graphs ? 0 : HAP_LAUNCH_EAGER);
     if (threads) *threads = c->lc.threads;
     if (chunks) *chunks = c->lc.chunks;
     if (rows_per_block) *rows_per_block = c->lc.rows_per_block;
@@ -706,9 +832,12 @@ hap_status hap_profile(hap_ctx *c, int32_t enable) {
         HIP_TRY(hipStreamSynchronize(c->stream), c);
         HIP_TRY(prof_collect(c), c);
     }
+    if (enable < 0) return fail_arg("hap_profile: enable must be >= 0");
     if (enable) {
         c->prof_ms[0] = c->prof_ms[1] = 0.0;
         c->prof_n[0] = c->prof_n[1] = 0;
+        c->prof_period = enable;
+        c->prof_sweep = 0;
     }
     c->prof = enable != 0;
     return HAP_OK;
@@ -732,6 +861,8 @@ hap_status hap_destroy(hap_ctx *c) {
     hap_status s = HAP_OK;
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) s = fail_hip(e, "hap_destroy: synchronize");
+    drop_graphs(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (hipEvent_t ev : c->ev) (void)hipEventDestroy(ev);
     if (c->own_ws) {
         e = hipFree(c->ws);

@@ -62,12 +62,22 @@ struct LevelPtrs {
 };
 
 // Host launchers (defined in the .hip files).
-// X != nullptr selects the points mode of the register-resident row pass (FP32, d = 2 or 3):
-// s_ij is recomputed from the coordinates instead of read from S.
+// Options of one row-pass launch.  X != nullptr selects the points mode of the
+// register-resident row pass (FP32, d = 2 or 3): s_ij is recomputed from the coordinates
+// instead of read from S.  tau_c/tau_q/tau_store/mrhap select the MapReduce schedule.
+template <typename T>
+struct SweepExtra {
+    const T *X = nullptr;
+    int64_t ldx = 0;
+    int d = 0;
+    const T *tau_c = nullptr, *tau_q = nullptr;
+    T *tau_store = nullptr;
+    int mrhap = 0;
+};
 template <typename T>
 hipError_t launch_sweep_level(const T *S, int64_t lds, const LevelPtrs<T> &lv, T *phi_down,
                               const T *tau_l, int n, int64_t ldw, double lam, T *Qpart, const Launch &lc,
-                              DevState *ds, hipStream_t st, const T *X = nullptr, int64_t ldx = 0, int d = 0);
+                              DevState *ds, hipStream_t st, const SweepExtra<T> &ex);
 template <typename T>
 hipError_t launch_colsum(const T *Qpart, int64_t ldw, int nb, int n, const LevelPtrs<T> &lv,
                          const LevelPtrs<T> *down, T *tau_next, bool top, bool last, int K, bool ordered,

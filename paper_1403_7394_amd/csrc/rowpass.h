@@ -28,7 +28,28 @@ struct SweepArgs {
     DevState *ds;
     const T *X;           // points mode: s_ij recomputed from X (row stride ldx) instead of read
     int64_t ldx;
+    // MapReduce schedule (Section 3): tau_i = tau_c[i] + tau_q[i] (c^{l-1} of this iteration,
+    // column sums Q^{l-1} of the previous one; no clip in the first iteration), stored in
+    // tau_store; phi^{l-1} is also written in the first iteration.
+    const T *tau_c, *tau_q;
+    T *tau_store;
+    int mrhap;
 };
+
+// The upward message this row pass clips with (Eq. 2.1 at l > 1), or false for no clip.
+template <typename T>
+__device__ __forceinline__ bool row_tau(const SweepArgs<T> &a, int i, int t, T &tau_i) {
+    if (a.tau_c != nullptr) {
+        if (t < 2) return false;
+        tau_i = a.tau_c[i] + a.tau_q[i];
+        return true;
+    }
+    if (a.tau != nullptr) {
+        tau_i = a.tau[i];
+        return true;
+    }
+    return false;
+}
 
 // Coordinates of the columns a thread owns (points mode, D coordinates per point).
 template <typename T, int NCH, int D>
@@ -149,7 +170,6 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, c
     const int64_t ldw = a.ldw;
     const T lam = a.lam, oml = a.oml;
     const T zero = T(0), ninf = neg_inf<T>();
-    const bool has_tau = a.tau != nullptr;
 
     RowRegs<T, NT, NCH> x;
     int buf = 0;
@@ -225,12 +245,16 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, c
                 a.E[i] = ck;
                 if (t >= 3 && old != ck) atomicOr(&a.ds->changed, 1);
             }
+        } else {
+            if (a.mrhap && tid == 0 && a.phi_down) a.phi_down[i] = m1;
         }
         // phase 2: rho^t, column partials.  dcol is made opaque so the diagonal masks are
         // recomputed here instead of being kept alive across the barrier.
         asm volatile("" : "+v"(dcol));
         const int k1r = k1 - base;
-        const T tau_i = has_tau ? a.tau[i] : zero;
+        T tau_i = zero;
+        const bool has_tau = row_tau(a, i, t, tau_i);
+        if (a.tau_store && tid == 0) a.tau_store[i] = has_tau ? tau_i : pos_inf<T>();
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             const int j0 = c * NT * VW + base;

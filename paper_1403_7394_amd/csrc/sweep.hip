@@ -129,7 +129,6 @@ __device__ __forceinline__ void stream_rows(const SweepArgs<T> &a, const int t, 
     const int64_t ldw = a.ldw;
     const T lam = a.lam, oml = a.oml;
     const T zero = T(0), ninf = neg_inf<T>();
-    const bool has_tau = a.tau != nullptr;
     const int base = tid * VW;
     const int voff = tid * 16;
     const __amdgpu_buffer_rsrc_t rB = row_rsrc(a.B, ldw * (int64_t)sizeof(T));
@@ -207,10 +206,14 @@ __device__ __forceinline__ void stream_rows(const SweepArgs<T> &a, const int t, 
                 a.E[i] = ck;
                 if (t >= 3 && old != ck) atomicOr(&a.ds->changed, 1);
             }
+        } else {
+            if (a.mrhap && tid == 0 && a.phi_down) a.phi_down[i] = m1;
         }
         // phase 2
         const int k1r = k1 - base;
-        const T tau_i = has_tau ? a.tau[i] : zero;
+        T tau_i = zero;
+        const bool has_tau = row_tau(a, i, t, tau_i);
+        if (a.tau_store && tid == 0) a.tau_store[i] = has_tau ? tau_i : pos_inf<T>();
         for (int c = 0; c < nch; ++c) {
             const int off0 = c * NT * VW;
             const V sv = buf_load<V, 0>(rS, voff, c * CB);
@@ -513,7 +516,10 @@ hipError_t launch_resident(const SweepArgs<T> &a, const Launch &lc, int nb, bool
 template <typename T>
 hipError_t launch_sweep_level(const T *S, int64_t lds, const LevelPtrs<T> &lv, T *phi_down,
                               const T *tau_l, int n, int64_t ldw, double lam, T *Qpart, const Launch &lc,
-                              DevState *ds, hipStream_t st, const T *X, int64_t ldx, int d) {
+                              DevState *ds, hipStream_t st, const SweepExtra<T> &ex) {
+    const T *X = ex.X;
+    const int64_t ldx = ex.ldx;
+    const int d = ex.d;
     SweepArgs<T> a;
     a.S = S;
     a.lds = lds;
@@ -534,6 +540,10 @@ hipError_t launch_sweep_level(const T *S, int64_t lds, const LevelPtrs<T> &lv, T
     a.ds = ds;
     a.X = X;
     a.ldx = ldx;
+    a.tau_c = ex.tau_c;
+    a.tau_q = ex.tau_q;
+    a.tau_store = ex.tau_store;
+    a.mrhap = ex.mrhap;
     const int nb = (n + lc.rows_per_block - 1) / lc.rows_per_block;
     const bool tail = (int64_t)lc.threads * lc.chunks * Vec<T>::N != n;
     if (lc.streaming) {
@@ -621,7 +631,7 @@ hipError_t launch_alpha_pad(T *A, int64_t rows, int n, int64_t ldw, hipStream_t 
     template hipError_t launch_alpha_pad<T>(T *, int64_t, int, int64_t, hipStream_t);                             \
     template hipError_t launch_sweep_level<T>(const T *, int64_t, const LevelPtrs<T> &, T *, const T *, int,      \
                                               int64_t, double, T *, const Launch &, DevState *, hipStream_t,      \
-                                              const T *, int64_t, int);                                           \
+                                              const SweepExtra<T> &);                                             \
     template hipError_t launch_colsum<T>(const T *, int64_t, int, int, const LevelPtrs<T> &, const LevelPtrs<T> *, \
                                          T *, bool, bool, int, bool, DevState *, hipStream_t);                    \
     template hipError_t launch_finalize<T>(const T *, int64_t, const LevelPtrs<T> &, int, int64_t, double, int,   \

@@ -19,6 +19,8 @@ HAP_F32, HAP_F64 = 0, 1
 BUILD_DIRECT, BUILD_GEMM, BUILD_BF16, BUILD_BF16X3 = 0, 1, 2, 3
 PREF_MEDIAN, PREF_SCALAR, PREF_VECTOR = 0, 1, 2
 LAUNCH_STREAM = 2
+LAUNCH_EAGER = 4
+SCHEDULE_SEQUENTIAL, SCHEDULE_MRHAP = 0, 1
 
 # every symbol include/hap.h declares
 EXPORTS = (
@@ -48,7 +50,7 @@ class hap_params(ctypes.Structure):
         ("levels", ctypes.c_int32),
         ("damping", ctypes.c_double),
         ("pref_mode", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("schedule", ctypes.c_int32),
         ("pref_scalar", ctypes.POINTER(ctypes.c_double)),
         ("pref_vec", ctypes.c_void_p),
     ]
@@ -185,7 +187,8 @@ class IterResult:
 class Hap:
     """One HAP problem on the GPU (wraps a hap_ctx).  S must outlive this object."""
 
-    def __init__(self, S, levels: int, damping: float, pref=None, workspace=None, stream=None):
+    def __init__(self, S, levels: int, damping: float, pref=None, workspace=None, stream=None,
+                 schedule: int = SCHEDULE_SEQUENTIAL):
         import torch
         lib = load()
         self._lib = lib
@@ -198,6 +201,9 @@ class Hap:
         p.struct_size = ctypes.sizeof(hap_params)
         p.levels = levels
         p.damping = float(damping)
+        p.schedule = int(schedule)
+        self.schedule = int(schedule)
+        self._eager = False
         self._pref_keep = None
         if pref is None:
             p.pref_mode = PREF_MEDIAN
@@ -287,8 +293,16 @@ class Hap:
         _check("hap_read_messages", self._lib.hap_read_messages(self._ctx, level, P(rho), P(alpha), self.n, P(c), P(phi), P(tau)))
         return dict(rho=rho, alpha=alpha, c=c, phi=phi, tau=tau)
 
-    def set_launch(self, threads=0, chunks=0, rows_per_block=0, streaming=None):
-        flags = -1 if streaming is None else (LAUNCH_STREAM if streaming else 0)
+    def set_launch(self, threads=0, chunks=0, rows_per_block=0, streaming=None, eager=None):
+        """Launch shape; streaming / eager None keep the current choice (both set together)."""
+        if streaming is None and eager is None:
+            flags = -1
+        else:
+            _, _, _, cur_stream = self.get_launch()
+            st = cur_stream if streaming is None else streaming
+            ea = self._eager if eager is None else eager
+            flags = (LAUNCH_STREAM if st else 0) | (LAUNCH_EAGER if ea else 0)
+            self._eager = bool(ea)
         _check("hap_set_launch", self._lib.hap_set_launch(self._ctx, threads, chunks, rows_per_block, flags))
 
     def set_points(self, X=None):
@@ -302,8 +316,9 @@ class Hap:
                                                           _ld(X), _dtype_code(X)))
         self._points_keep = X
 
-    def profile(self, enable: bool):
-        _check("hap_profile", self._lib.hap_profile(self._ctx, 1 if enable else 0))
+    def profile(self, enable, every: int = 1):
+        """Per-launch event timing of every `every`-th sweep (enable False stops)."""
+        _check("hap_profile", self._lib.hap_profile(self._ctx, int(every) if enable else 0))
 
     def profile_read(self):
         """(row pass ms, row pass launches, column-sum ms, column-sum launches)."""

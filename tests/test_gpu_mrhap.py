@@ -1,0 +1,97 @@
+"""The MapReduce schedule (Section 3) on the GPU against the oracle, through the C ABI.
+
+With one row per workgroup the column sums run in row order, so FP64 and FP32 runs are
+bit-identical to the oracle evaluated in the same precision (messages, c, phi, tau, labels,
+the stop iteration), for the register-resident and the streaming row pass and in points mode.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import hap_ref
+from oracle import similarity as sim
+from paper_1403_7394_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def to_device(S):
+    n = S.shape[0]
+    vw = 4 if S.dtype == np.float32 else 2
+    ld = n + (-n) % vw
+    buf = torch.zeros((n, ld), dtype=torch.float32 if S.dtype == np.float32 else torch.float64, device=DEV)
+    buf[:, :n] = torch.from_numpy(np.ascontiguousarray(S))
+    return buf[:, :n]
+
+
+def run(hap, S, L, lam, T, K=0, launch=(0, 0, 1), streaming=None, X=None, schedule=None):
+    h = hap.Hap(to_device(S), L, lam, schedule=hap.SCHEDULE_MRHAP if schedule is None else schedule)
+    h.set_launch(*launch, streaming=streaming)
+    if X is not None:
+        h.set_points(torch.from_numpy(X).to(DEV))
+    res = h.iterate(T, K)
+    out = dict(iters=res.iters, converged=res.converged, labels=h.labels().cpu().numpy(),
+               msgs=[{k: v.cpu().numpy() for k, v in h.messages(l).items()} for l in range(L)])
+    h.close()
+    return out
+
+
+def same_as_oracle(g, r, L):
+    st = r.state
+    for l in range(L):
+        m = g["msgs"][l]
+        assert np.array_equal(m["rho"], st.rho[l]), ("rho", l)
+        assert np.array_equal(m["alpha"], st.alpha[l]), ("alpha", l)
+        if l < L - 1:
+            assert np.array_equal(m["c"], st.c[l]), ("c", l)
+            assert np.array_equal(m["phi"], st.phi[l]), ("phi", l)
+        assert np.array_equal(m["tau"], st.tau[l]), ("tau", l)
+    assert np.array_equal(g["labels"], r.labels)
+
+
+def test_fp64_bit_identical(hap_gpu):
+    b, rp = synth.workload_small_f64()
+    S = sim.add_noise(sim.similarity(b.X), rp.noise_rel, rp.noise_seed)
+    p = sim.median_offdiag(S)
+    g = run(hap_gpu, S, 3, 0.5, 60)
+    same_as_oracle(g, hap_ref.hap(S, p, 3, 0.5, 60, schedule="mrhap"), 3)
+
+
+@pytest.mark.parametrize("n,T,streaming", [(1000, 40, None), (257, 80, None), (1000, 30, True)])
+def test_fp32_bit_identical(hap_gpu, n, T, streaming):
+    b = synth.small_blobs(1400 + n, n, d=2, k=6, dtype=np.float32)
+    S = sim.similarity(b.X).astype(np.float32)
+    p = sim.median_offdiag(S, np.float32)
+    launch = (1024, 1, 1) if streaming else (0, 0, 1)
+    g = run(hap_gpu, S, 3, 0.9, T, launch=launch, streaming=streaming)
+    same_as_oracle(g, hap_ref.hap(S, p, 3, 0.9, T, dtype=np.float32, schedule="mrhap"), 3)
+
+
+def test_points_mode_bit_identical(hap_gpu):
+    b = synth.small_blobs(1410, 700, d=2, k=5, dtype=np.float32)
+    S = sim.similarity(b.X).astype(np.float32)
+    p = sim.median_offdiag(S, np.float32)
+    g = run(hap_gpu, S, 2, 0.9, 30, X=b.X)
+    same_as_oracle(g, hap_ref.hap(S, p, 2, 0.9, 30, dtype=np.float32, schedule="mrhap"), 2)
+
+
+def test_stop_rule_matches_oracle(hap_gpu):
+    b = synth.gaussian_blobs(2004, 400, 2, 3, centre="uniform", centre_scale=10.0, sigma_lo=1.0, sigma_hi=1.0,
+                             sizes="multinomial", dtype=np.float32)
+    S = sim.similarity(b.X).astype(np.float32)
+    p = sim.median_offdiag(S, np.float32)
+    r = hap_ref.hap(S, p, 3, 0.9, 500, stable_iters=50, dtype=np.float32, schedule="mrhap")
+    g = run(hap_gpu, S, 3, 0.9, 500, K=50)
+    assert g["converged"] == r.converged and g["iters"] == r.iters
+    assert np.array_equal(g["labels"], r.labels)
+
+
+def test_one_level_equals_the_sequential_schedule(hap_gpu):
+    b = synth.small_blobs(1420, 900, d=2, k=5, dtype=np.float32)
+    S = sim.similarity(b.X).astype(np.float32)
+    a = run(hap_gpu, S, 1, 0.8, 50, launch=(0, 0, 0), schedule=hap_gpu.SCHEDULE_SEQUENTIAL)
+    m = run(hap_gpu, S, 1, 0.8, 50, launch=(0, 0, 0))
+    assert np.array_equal(a["labels"], m["labels"])
+    assert np.array_equal(a["msgs"][0]["rho"], m["msgs"][0]["rho"])
+    assert np.array_equal(a["msgs"][0]["alpha"], m["msgs"][0]["alpha"])
