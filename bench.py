@@ -218,24 +218,8 @@ def run_batched_form(args, torch, hap, synth) -> dict:
             "net_similarity_rel_diff_max": max(ns_rel)}
 
 
-def _ari(a, b) -> float:
-    """Adjusted Rand index of two labelings (pair-counting form, Hubert and Arabie 1985)."""
-    import numpy as np
-    _, ia = np.unique(a, return_inverse=True)
-    _, ib = np.unique(b, return_inverse=True)
-    cont = np.zeros((ia.max() + 1, ib.max() + 1), dtype=np.int64)
-    np.add.at(cont, (ia, ib), 1)
-    comb = lambda x: x * (x - 1) / 2.0
-    s_ij = comb(cont).sum()
-    s_a = comb(cont.sum(axis=1)).sum()
-    s_b = comb(cont.sum(axis=0)).sum()
-    tot = comb(float(len(a)))
-    exp = s_a * s_b / tot
-    mx = 0.5 * (s_a + s_b)
-    return float((s_ij - exp) / (mx - exp)) if mx != exp else 1.0
-
-
 def run_warm_form(args, torch, hap, synth) -> dict:
+    from paper_1403_7394_amd import metrics
     """Warm-start form: a perceptron trained on HAP runs of 2-D blob problems (8192 points,
     k in {3, 8, 16, 32, 64}, 5 seeds each) predicts the warm initial availabilities of the
     65536-point, 32-dimensional, 1024-blob workload; the warm run (with the cold start as
@@ -327,7 +311,9 @@ def run_warm_form(args, torch, hap, synth) -> dict:
             "sweeps_cold": sw(cold), "sweeps_warm_total": warm_sweeps,
             "wall_ratio_warm_over_cold": warm_r["wall_s"] / cold["wall_s"],
             "exemplar_agreement": [float(np.mean(lab_c[l] == lab_w[l])) for l in range(L)],
-            "adjusted_rand_index": [_ari(lab_c[l], lab_w[l]) for l in range(L)],
+            "purity_cold": [metrics.purity(lab_c[l], blobs.truth) for l in range(L)],
+            "purity_warm": [metrics.purity(lab_w[l], blobs.truth) for l in range(L)],
+            "adjusted_rand_index": [metrics.adjusted_rand_index(lab_c[l], lab_w[l]) for l in range(L)],
             "net_similarity_rel_diff": [(a - b) / abs(b) for a, b in zip(warm_r["net_similarity"],
                                                                        cold["net_similarity"])],
         }
@@ -356,7 +342,9 @@ def run_warm_form(args, torch, hap, synth) -> dict:
             held.append({"k": k, "cold_iters": rc_.iters, "cold_converged": rc_.converged, "warm_iters": rw_.iters,
                          "warm_converged": rw_.converged, "fell_back": fw, "cold_s": tc, "warm_s": tw,
                          "exemplar_agreement": float(np.mean(lc == lw)),
-                         "adjusted_rand_index": [_ari(lc[l], lw[l]) for l in range(L)],
+                         "purity_cold": [metrics.purity(lc[l], b.truth) for l in range(L)],
+                         "purity_warm": [metrics.purity(lw[l], b.truth) for l in range(L)],
+                         "adjusted_rand_index": [metrics.adjusted_rand_index(lc[l], lw[l]) for l in range(L)],
                          "net_similarity_rel_diff": (nw - nc) / abs(nc)})
         out["levels"][str(L)]["held_out_2d_8192"] = held
         print(json.dumps({"form": "warm", "levels": L, "held_out": held}), file=sys.stderr, flush=True)
@@ -391,7 +379,7 @@ def main() -> int:
 
     import torch
 
-    from paper_1403_7394_amd import hap, synth
+    from paper_1403_7394_amd import hap, metrics, synth
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -438,8 +426,9 @@ def main() -> int:
         counts = [h.exemplars(l)[1] for l in range(L)]
         ns = h.net_similarity(-1)
         launch = h.get_launch()
+        labels = h.labels()
         h.close()
-        return res, counts, ns, prof, launch
+        return res, counts, ns, prof, launch, labels
 
     for _ in range(args.warmup):
         step(False)
@@ -450,7 +439,7 @@ def main() -> int:
     row_n = col_n = 0
     first_sweeps = 0
     for _ in range(args.steps):
-        res, counts, ns, prof, launch = step(True)
+        res, counts, ns, prof, launch, labels = step(True)
         # an early stop is detected one sweep after the stop iteration; a stop at the cap is not
         sweeps += res.iters + 1 if (res.converged and res.iters < rp.max_iters) else res.iters
         first_sweeps += 1
@@ -516,6 +505,7 @@ def main() -> int:
         "colsum_avg_us": col_ms / max(col_n, 1) * 1e3,
         "exemplars_per_level": counts,
         "net_similarity": ns,
+        "purity_per_level": [metrics.purity(lab, blobs.truth) for lab in labels.cpu().numpy()],
         "launch": {"threads": launch[0], "chunks": launch[1], "rows_per_block": launch[2],
                    "streaming": launch[3]},
     }
