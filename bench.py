@@ -353,6 +353,52 @@ def run_warm_form(args, torch, hap, synth) -> dict:
     return out
 
 
+def run_image_form(args, torch, hap, synth) -> dict:
+    """Image-style form (Section 4): RGB pixels of the sizes of the paper's two images
+    (103 x 103 and 120 x 100, from 16 colour blobs), negative Euclidean distances, random
+    preferences U[-1e6, 0] per point, L = 3, damping 0.5, 30 iterations, FP32."""
+    import numpy as np
+
+    from paper_1403_7394_amd import metrics
+    dev = torch.device("cuda:0")
+    out = {"form": "image", "results": {}}
+    for which in ("mandrill", "buttons"):
+        blobs, prefs, rp = synth.workload_image(which)
+        n = blobs.X.shape[0]
+        L = rp.levels
+        X = torch.from_numpy(blobs.X).to(dev)
+        ld = n + (-n) % 4
+        S = torch.empty((n, ld), dtype=torch.float32, device=dev)[:, :n]
+        p = torch.from_numpy(prefs.astype(np.float32)).to(dev)
+        ws = torch.empty(hap.workspace_size(n, L, hap.HAP_F32), dtype=torch.uint8, device=dev)
+        times = []
+        for rep in range(1 + max(1, args.steps)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hap.build_similarity(X, S, mode=hap.BUILD_DIRECT_L2)
+            h = hap.Hap(S, L, rp.damping, pref=p, workspace=ws)
+            res = h.iterate(rp.max_iters)
+            counts = [h.exemplars(l)[1] for l in range(L)]
+            labels = h.labels()
+            ns = [h.net_similarity(l) for l in range(L)]
+            torch.cuda.synchronize()
+            if rep > 0:
+                times.append(time.perf_counter() - t0)
+            h.close()
+        lab = labels.cpu().numpy()
+        t = float(np.mean(times))
+        out["results"][which] = {
+            "n": n, "levels": L, "iterations": res.iters, "seconds": t,
+            "updates_per_s": n * n * L * res.iters / t,
+            "exemplars_per_level": counts,
+            "purity_per_level": [metrics.purity(lab[l], blobs.truth) for l in range(L)],
+            "net_similarity_per_level": ns,
+            "paper_exemplars_per_level": [15, 7, 6] if which == "mandrill" else [154, 25, 11],
+        }
+        del S, ws
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -362,9 +408,10 @@ def main() -> int:
     ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration under rocprofv3)")
-    ap.add_argument("--form", choices=["plain", "precision", "batched", "warm"], default="plain",
+    ap.add_argument("--form", choices=["plain", "precision", "batched", "warm", "image"], default="plain",
                     help="plain: the headline line; precision: the similarity build forms; "
-                         "batched: many problems in one launch; warm: the learned warm start")
+                         "batched: many problems in one launch; warm: the learned warm start; "
+                         "image: the paper's image-style workload (random preferences, Euclidean distance)")
     ap.add_argument("--form-iters", type=int, default=0, help="iterations for a form run (0 = the workload's)")
     ap.add_argument("--read-s", action="store_true", help="plain form: the row pass reads S (no points mode)")
     ap.add_argument("--schedule", choices=["sequential", "mrhap"], default="sequential",
@@ -393,6 +440,9 @@ def main() -> int:
         return 0
     if args.form == "warm":
         print(json.dumps(run_warm_form(args, torch, hap, synth)), flush=True)
+        return 0
+    if args.form == "image":
+        print(json.dumps(run_image_form(args, torch, hap, synth)), flush=True)
         return 0
     dev = torch.device("cuda:0")
     blobs, rp = synth.workload_plain_f32()

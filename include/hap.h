@@ -67,8 +67,11 @@ enum {
     HAP_BUILD_GEMM = 1,     /* -(|x_i|^2 + |x_j|^2 - 2 x_i.x_j) with the Gram matrix on MFMA
                                in the output precision (FP32 or FP64) */
     HAP_BUILD_BF16 = 2,     /* Gram matrix on BF16 MFMA with FP32 accumulation (FP32 output) */
-    HAP_BUILD_BF16X3 = 3    /* split x = hi + lo in BF16, x.y ~ hi.hi + hi.lo + lo.hi on MFMA,
+    HAP_BUILD_BF16X3 = 3,   /* split x = hi + lo in BF16, x.y ~ hi.hi + hi.lo + lo.hi on MFMA,
                                FP32 accumulation (FP32 output) */
+    HAP_BUILD_DIRECT_L2 = 4, /* negative Euclidean distance -sqrt(sum of squared differences), the
+                               similarity the paper uses for images (Section 4); FP64 sum and root,
+                               rounded once (VALU; any d) */
 };
 
 /* Preference (diagonal s^l_jj) sources. */

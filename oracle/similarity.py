@@ -49,15 +49,16 @@ def noise_uniform(seed: int, n: int, rows=None) -> np.ndarray:
     return (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
 
 
-def similarity(X: np.ndarray) -> np.ndarray:
-    """s_ij = -sum_k (x_ik - x_jk)^2 in FP64 (diagonal 0)."""
+def similarity(X: np.ndarray, squared: bool = True) -> np.ndarray:
+    """s_ij = -sum_k (x_ik - x_jk)^2 in FP64 (diagonal 0); squared=False gives the negative
+    Euclidean distance -sqrt(sum_k (x_ik - x_jk)^2) the paper uses for images (Section 4)."""
     X = np.asarray(X, dtype=np.float64)
     n, d = X.shape
     S = np.zeros((n, n))
     for k in range(d):
         diff = X[:, k][:, None] - X[:, k][None, :]
         S = S + diff * diff
-    return -S
+    return -S if squared else -np.sqrt(S)
 
 
 def add_noise(S: np.ndarray, rel: float, seed: int) -> np.ndarray:

@@ -3,7 +3,8 @@
 //
 // HAP_BUILD_DIRECT: sum over coordinates of (x_ik - x_jk)^2, accumulated in FP64
 // in coordinate order with separate multiply and add roundings (no contraction),
-// negated and rounded once to the output type.  Each 256-thread workgroup owns a
+// negated and rounded once to the output type.  HAP_BUILD_DIRECT_L2 takes the FP64
+// square root of the sum before negating (the negative Euclidean distance).  Each 256-thread workgroup owns a
 // 64 x 64 output tile; the two 64-point slices of X are staged through LDS in
 // chunks of 16 coordinates; every thread owns 4 rows x 4 consecutive columns so a
 // wavefront stores 4 rows of 64 contiguous elements.
@@ -28,7 +29,7 @@ __device__ __forceinline__ unsigned long long splitmix64_first(unsigned long lon
 constexpr int kTile = 64;
 constexpr int kDk = 16;
 
-template <typename TX, typename TS>
+template <typename TX, typename TS, bool L2>
 __global__ __launch_bounds__(256) void build_direct_kernel(const TX *__restrict__ X, int n, int d, int64_t ldx,
                                                            TS *__restrict__ S, int64_t lds, double noise_rel,
                                                            unsigned long long seed) {
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(256) void build_direct_kernel(const TX *__restrict_
         for (int b = 0; b < 4; ++b) {
             const int j = j0 + tx * 4 + b;
             if (j >= n) continue;
-            double s = -acc[a][b];
+            double s = L2 ? -sqrt(acc[a][b]) : -acc[a][b];
             if (i == j) {
                 s = 0.0;
             } else if (noise_rel > 0.0) {
@@ -356,11 +357,17 @@ __global__ __launch_bounds__(256) void build_mfma_f64_kernel(const double *__res
 
 hipError_t launch_build(const void *X, int64_t n, int64_t d, int64_t ldx, int x_dtype, void *S, int64_t lds,
                         int s_dtype, int mode, double noise_rel, uint64_t seed, hipStream_t st) {
-    if (mode == HAP_BUILD_DIRECT) {
+    if (mode == HAP_BUILD_DIRECT || mode == HAP_BUILD_DIRECT_L2) {
         const dim3 grid((unsigned)((n + kTile - 1) / kTile), (unsigned)((n + kTile - 1) / kTile));
 #define HAP_BD(TX, TS)                                                                                          \
-    hipLaunchKernelGGL((build_direct_kernel<TX, TS>), grid, dim3(256), 0, st, (const TX *)X, (int)n, (int)d,    \
-                       ldx, (TS *)S, lds, noise_rel, (unsigned long long)seed)
+    do {                                                                                                        \
+        if (mode == HAP_BUILD_DIRECT_L2)                                                                        \
+            hipLaunchKernelGGL((build_direct_kernel<TX, TS, true>), grid, dim3(256), 0, st, (const TX *)X,     \
+                               (int)n, (int)d, ldx, (TS *)S, lds, noise_rel, (unsigned long long)seed);        \
+        else                                                                                                    \
+            hipLaunchKernelGGL((build_direct_kernel<TX, TS, false>), grid, dim3(256), 0, st, (const TX *)X,    \
+                               (int)n, (int)d, ldx, (TS *)S, lds, noise_rel, (unsigned long long)seed);        \
+    } while (0)
         if (x_dtype == HAP_F32 && s_dtype == HAP_F32) HAP_BD(float, float);
         else if (x_dtype == HAP_F32 && s_dtype == HAP_F64) HAP_BD(float, double);
         else if (x_dtype == HAP_F64 && s_dtype == HAP_F32) HAP_BD(double, float);

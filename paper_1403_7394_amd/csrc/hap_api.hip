@@ -414,7 +414,7 @@ hap_status hap_build_similarity(const void *X, int64_t n, int64_t d, int64_t ldx
     if (!dtype_ok(x_dtype) || !dtype_ok(s_dtype)) return fail_arg("hap_build_similarity: dtype", HAP_E_DTYPE);
     if (!(noise_rel >= 0.0) || !std::isfinite(noise_rel)) return fail_arg("hap_build_similarity: noise_rel");
     if (noise_rel > 0.0 && s_dtype != HAP_F64) return fail_arg("hap_build_similarity: noise needs FP64 output", HAP_E_DTYPE);
-    if (build_mode < HAP_BUILD_DIRECT || build_mode > HAP_BUILD_BF16X3)
+    if (build_mode < HAP_BUILD_DIRECT || build_mode > HAP_BUILD_DIRECT_L2)
         return fail_arg("hap_build_similarity: unknown build mode");
     if (build_mode == HAP_BUILD_GEMM && x_dtype != s_dtype)
         return fail_arg("hap_build_similarity: the GEMM build needs X and S of the same type", HAP_E_DTYPE);

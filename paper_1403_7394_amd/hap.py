@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_PKG, "libhap.so")
 
 HAP_OK, HAP_E_ARG, HAP_E_DTYPE, HAP_E_OOM, HAP_E_HIP, HAP_E_STATE, HAP_E_UNSUPPORTED = range(7)
 HAP_F32, HAP_F64 = 0, 1
-BUILD_DIRECT, BUILD_GEMM, BUILD_BF16, BUILD_BF16X3 = 0, 1, 2, 3
+BUILD_DIRECT, BUILD_GEMM, BUILD_BF16, BUILD_BF16X3, BUILD_DIRECT_L2 = 0, 1, 2, 3, 4
 PREF_MEDIAN, PREF_SCALAR, PREF_VECTOR = 0, 1, 2
 LAUNCH_STREAM = 2
 LAUNCH_EAGER = 4

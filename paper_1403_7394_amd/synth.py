@@ -139,6 +139,30 @@ def workload_warm_train(k: int, rep: int, n: int = 8192) -> Blobs:
                           sigma_hi=1.0, sizes="multinomial", dtype=np.float32)
 
 
+def rgb_pixels(seed: int, n: int, k: int = 16, sigma_lo: float = 4.0, sigma_hi: float = 20.0) -> Blobs:
+    """n RGB pixels from k colour blobs: centres U[0,255]^3, sigma U[sigma_lo, sigma_hi] per
+    blob, multinomial sizes, rounded to integer intensities and clipped to [0,255]; FP32."""
+    b = gaussian_blobs(seed, n, 3, k, centre="uniform", centre_scale=127.5, sigma_lo=sigma_lo,
+                       sigma_hi=sigma_hi, sizes="multinomial", dtype=np.float64)
+    X = np.clip(np.rint(b.X + 127.5), 0.0, 255.0).astype(np.float32)
+    return Blobs(X=np.ascontiguousarray(X), truth=b.truth, seed=seed, meta=dict(b.meta, kind="rgb"))
+
+
+def random_preferences(seed: int, n: int, lo: float = -1e6, hi: float = 0.0) -> np.ndarray:
+    """Per-point preferences U[lo, hi] (FP64)."""
+    return _rng(seed).uniform(lo, hi, size=n)
+
+
+def workload_image(which: str = "mandrill"):
+    """Image-style workload: RGB pixels of the sizes of the paper's two images (103 x 103 and
+    120 x 100) from 16 colour blobs, preferences U[-1e6, 0] per point, L = 3, damping 0.5,
+    30 iterations (Section 4).  Returns (Blobs, preferences, RunParams)."""
+    n, seed = {"mandrill": (103 * 103, 1006), "buttons": (120 * 100, 1007)}[which]
+    b = rgb_pixels(seed, n)
+    return b, random_preferences(seed + 50, n), RunParams(levels=3, damping=0.5, max_iters=30, stable_iters=0,
+                                                          dtype="f32", noise_rel=0.0, noise_seed=seed)
+
+
 def small_blobs(seed: int, n: int, d: int = 2, k: int = 4, dtype=np.float64, scale: float = 10.0) -> Blobs:
     """Generic small test input: k blobs, centres U[-scale,scale]^d, sigma 1, multinomial sizes."""
     return gaussian_blobs(seed, n, d, k, centre="uniform", centre_scale=scale, sigma_lo=1.0,

@@ -1,0 +1,47 @@
+"""Image-style workload (Section 4): negative Euclidean distances between integer RGB pixels and
+random per-point preferences, on the GPU against the oracle (bit-identical with row-ordered
+column sums)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import hap_ref
+from oracle import similarity as sim
+from paper_1403_7394_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.mark.parametrize("n,dt", [(300, torch.float64), (1000, torch.float32), (257, torch.float32)])
+def test_euclidean_build_bit_exact(hap_gpu, n, dt):
+    b = synth.rgb_pixels(1600 + n, n)
+    X = torch.from_numpy(b.X).to(DEV)
+    ld = n + (-n) % 4
+    S = torch.zeros((n, ld), dtype=dt, device=DEV)[:, :n]
+    hap_gpu.build_similarity(X, S, mode=hap_gpu.BUILD_DIRECT_L2)
+    ref = sim.similarity(b.X, squared=False).astype(np.float64 if dt == torch.float64 else np.float32)
+    assert np.array_equal(S.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("n,dt,T", [(300, np.float64, 30), (1000, np.float32, 30)])
+def test_image_style_run_bit_identical(hap_gpu, n, dt, T):
+    b = synth.rgb_pixels(1610 + n, n)
+    p = synth.random_preferences(1611 + n, n).astype(dt)
+    L, lam = 3, 0.5
+    S = sim.similarity(b.X, squared=False).astype(dt)
+    tdt = torch.float64 if dt == np.float64 else torch.float32
+    ld = n + (-n) % 4
+    St = torch.zeros((n, ld), dtype=tdt, device=DEV)[:, :n]
+    St.copy_(torch.from_numpy(S))
+    h = hap_gpu.Hap(St, L, lam, pref=torch.from_numpy(p).to(DEV))
+    h.set_launch(rows_per_block=1)
+    h.iterate(T)
+    labels = h.labels().cpu().numpy()
+    msgs = [{k: v.cpu().numpy() for k, v in h.messages(l).items()} for l in range(L)]
+    h.close()
+    r = hap_ref.hap(S, p, L, lam, T, dtype=dt)
+    assert np.array_equal(labels, r.labels)
+    for l in range(L):
+        assert np.array_equal(msgs[l]["rho"], r.state.rho[l]), l
+        assert np.array_equal(msgs[l]["alpha"], r.state.alpha[l]), l

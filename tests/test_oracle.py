@@ -311,3 +311,14 @@ def test_net_similarity_definition():
     S = np.array([[0., -1., -4.], [-1., 0., -9.], [-4., -9., 0.]])
     # exemplars {0, 2}: point 1 joins 0
     assert sim.net_similarity(S, -2.0, np.array([0, 0, 2])) == -2.0 - 1.0 - 2.0
+
+
+def test_unsquared_similarity_matches_scipy_euclidean():
+    from scipy.spatial.distance import cdist
+    b = synth.rgb_pixels(61, 50)
+    S = sim.similarity(b.X, squared=False)
+    ref = -cdist(b.X.astype(np.float64), b.X.astype(np.float64), metric="euclidean")
+    np.testing.assert_allclose(S, ref, rtol=1e-15, atol=1e-12)
+    assert np.all(np.diag(S) == 0.0)
+    # integer pixels: every squared distance is an integer, so the root of a perfect square is exact
+    assert np.all(b.X == np.rint(b.X)) and b.X.min() >= 0 and b.X.max() <= 255
