@@ -157,17 +157,30 @@ __global__ __launch_bounds__(256) void norms_kernel_f64(const double *__restrict
 // with 16-byte loads issued all at once (so a chunk costs one memory latency, not one per
 // k step), zero-filled past n and d; fragments are then read from LDS.  The same LDS holds
 // the output tile for the epilogue.
-constexpr int kKc = 64;               // coordinates per staged chunk
-constexpr int kXs = kKc + 4;          // padded LDS row of a staged slab
-constexpr int kTs = 128 + 4;          // padded LDS row of the output tile
-constexpr int kSmemFloats = (2 * 128 * kXs > 128 * kTs) ? 2 * 128 * kXs : 128 * kTs;
+constexpr int kTs = 128 + 4;          // padded LDS row of the output tile (64 rows at a time)
+// Coordinates per staged chunk: 32 (36 KB of LDS, four workgroups per CU) for the FP32 and
+// BF16 forms; BF16x3 needs more registers for its split operands, so it keeps fewer
+// workgroups per CU and stages 64 coordinates at a time (fewer barriers).
+template <int MODE> constexpr int build_kc() { return MODE == kModeBF16x3 ? 64 : 32; }
+template <int MODE> constexpr int build_smem_floats() {
+    // staged slabs, or the output rows of one epilogue pass (128 rows for BF16x3, else 64)
+    return (2 * 128 * (build_kc<MODE>() + 4) > (MODE == kModeBF16x3 ? 128 : 64) * kTs)
+               ? 2 * 128 * (build_kc<MODE>() + 4)
+               : (MODE == kModeBF16x3 ? 128 : 64) * kTs;
+}
+template <int MODE> constexpr int build_min_waves() { return MODE == kModeBF16x3 ? 1 : 4; }
 
+// FP32 and BF16 forms: a register budget of four waves per SIMD (128); with 36 KB of LDS per
+// workgroup several workgroups share a CU, so one workgroup's epilogue stores overlap
+// another's staging loads.
 template <int MODE>
-__global__ __launch_bounds__(256) void build_mfma_f32_kernel(const float *__restrict__ X, int n, int d, int64_t ldx,
+__global__ __launch_bounds__(256, (build_min_waves<MODE>())) void build_mfma_f32_kernel(const float *__restrict__ X, int n, int d, int64_t ldx,
                                                              const float *__restrict__ norms, float *__restrict__ S,
                                                              int64_t lds) {
 #pragma clang fp contract(off)
-    __shared__ float smem[kSmemFloats];
+    constexpr int kKc = build_kc<MODE>();
+    constexpr int kXs = kKc + 4;          // padded LDS row of a staged slab
+    __shared__ float smem[build_smem_floats<MODE>()];
     float(*xs)[128][kXs] = reinterpret_cast<float(*)[128][kXs]>(smem);   // [0]: rows i, [1]: rows j
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -217,6 +230,28 @@ __global__ __launch_bounds__(256) void build_mfma_f32_kernel(const float *__rest
                     for (int b = 0; b < 4; ++b)
                         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a], fb[b], acc[a][b], 0, 0, 0);
             }
+        } else if (MODE == kModeBF16) {
+            // B fragments for the whole k step, A fragments one block row at a time (fewer
+            // live registers)
+            for (int kk = 0; kk < kc; kk += 32) {
+                bf16x8 hb[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float *pb = &xs[1][wj + 16 * q + lr][kk + 8 * lg];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) hb[q][e] = to_bf16(pb[e]);
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    bf16x8 ha;
+                    const float *pa = &xs[0][wi + 16 * a + lr][kk + 8 * lg];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) ha[e] = to_bf16(pa[e]);
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha, hb[b], acc[a][b], 0, 0, 0);
+                }
+            }
         } else {
             for (int kk = 0; kk < kc; kk += 32) {
                 bf16x8 ha[4], hb[4], la[4], lb[4];
@@ -250,46 +285,54 @@ __global__ __launch_bounds__(256) void build_mfma_f32_kernel(const float *__rest
         }
         __syncthreads();
     }
-    // Epilogue: form S in the MFMA layout (lane l, register r of a block holds row
-    // 4*(l/16) + r, column l%16) into the LDS tile, then write the 128 x 128 tile row by row
-    // with 16-byte stores (each row segment is 512 contiguous bytes).
+    // Epilogue, kRows rows of the tile at a time (FP32/BF16: two halves, waves 0-1 own rows
+    // 0-63 and waves 2-3 rows 64-127; BF16x3: the whole tile): form S in the MFMA layout
+    // (lane l, register r of a block holds row 4*(l/16) + r, column l%16) into the LDS tile,
+    // then write it row by row with 16-byte stores (each row segment is 512 contiguous bytes).
+    constexpr int kRows = (MODE == kModeBF16x3) ? 128 : 64;
     float(*tile)[kTs] = reinterpret_cast<float(*)[kTs]>(smem);
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int il = wi + 16 * a + 4 * lg + r;
-            const int i = bi + il;
-            const float ni = norms[min(i, n - 1)];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int jl = wj + 16 * b + lr;
-                const int j = bj + jl;
-                const float v = -((ni + norms[min(j, n - 1)]) - 2.f * acc[a][b][r]);
-                tile[il][jl] = (i == j) ? 0.f : fminf(0.f, v);
-            }
-        }
-    }
-    __syncthreads();
     const int col4 = (tid & 31) * 4;
     const int jg = bj + col4;
     const bool vec_ok = ((lds & 3) == 0) && ((((uintptr_t)S) & 15) == 0);
-    for (int rr = tid >> 5; rr < 128; rr += 8) {
-        const int i = bi + rr;
-        if (i >= n) break;
-        float *dst = S + (int64_t)i * lds + jg;
-        if (vec_ok && jg + 3 < n) {
-            f32x4 v;
-            v[0] = tile[rr][col4];
-            v[1] = tile[rr][col4 + 1];
-            v[2] = tile[rr][col4 + 2];
-            v[3] = tile[rr][col4 + 3];
-            *(f32x4 *)dst = v;
-        } else {
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (jg + e < n) dst[e] = tile[rr][col4 + e];
+    for (int pass = 0; pass < 128 / kRows; ++pass) {
+        if (kRows == 128 || (wave >> 1) == pass) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int il = (kRows == 128 ? wi : 0) + 16 * a + 4 * lg + r;   // row inside the pass
+                    const int i = bi + kRows * pass + il;
+                    const float ni = norms[min(i, n - 1)];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const int jl = wj + 16 * b + lr;
+                        const int j = bj + jl;
+                        const float v = -((ni + norms[min(j, n - 1)]) - 2.f * acc[a][b][r]);
+                        tile[il][jl] = (i == j) ? 0.f : fminf(0.f, v);
+                    }
+                }
+            }
         }
+        __syncthreads();
+        for (int rr = tid >> 5; rr < kRows; rr += 8) {
+            const int i = bi + kRows * pass + rr;
+            if (i >= n) break;
+            float *dst = S + (int64_t)i * lds + jg;
+            if (vec_ok && jg + 3 < n) {
+                f32x4 v;
+                v[0] = tile[rr][col4];
+                v[1] = tile[rr][col4 + 1];
+                v[2] = tile[rr][col4 + 2];
+                v[3] = tile[rr][col4 + 3];
+                *(f32x4 *)dst = v;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (jg + e < n) dst[e] = tile[rr][col4 + e];
+            }
+        }
+        __syncthreads();
     }
 }
 

@@ -1,6 +1,10 @@
 """Short runs of the hot path for hardware-counter profiling.
 
     python paper_1403_7394_amd/profile_run.py [--sweeps K] [--copy-gib G] [--n N]
+    python paper_1403_7394_amd/profile_run.py --builds
+
+--builds: the similarity of the 32768-point, 64-dimensional workload built once in each
+mode (direct, FP32 GEMM, BF16, BF16x3 on the matrix cores), nothing else.
 
 Builds the FP32 similarity of the 8192-point, 64-blob 2-D workload on the GPU, runs K full
 sweeps (all three levels, damping 0.9, no stop rule; the row pass in points mode unless
@@ -25,6 +29,7 @@ def main() -> int:
     ap.add_argument("--copy-gib", type=float, default=1.0)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--read-s", action="store_true", help="row pass reads S (default: points mode)")
+    ap.add_argument("--builds", action="store_true", help="profile the similarity builds instead")
     args = ap.parse_args()
 
     import torch
@@ -36,6 +41,17 @@ def main() -> int:
         return 2
     hap.load()
     dev = torch.device("cuda:0")
+    if args.builds:
+        blobs, _ = synth.workload_precision()
+        n = blobs.X.shape[0]
+        X = torch.from_numpy(blobs.X).to(dev)
+        S = torch.empty((n, n), dtype=torch.float32, device=dev)
+        for name, mode in (("direct", hap.BUILD_DIRECT), ("gemm_f32", hap.BUILD_GEMM), ("bf16", hap.BUILD_BF16),
+                           ("bf16x3", hap.BUILD_BF16X3)):
+            hap.build_similarity(X, S, mode=mode)
+            torch.cuda.synchronize()
+            print(f"build {name}: {n} x {n} from d = {blobs.X.shape[1]}", flush=True)
+        return 0
     if args.copy_gib > 0:
         words = int(args.copy_gib * (1 << 30)) // 4
         src = torch.ones(words, dtype=torch.float32, device=dev)
