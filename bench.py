@@ -210,7 +210,7 @@ def run_batched_form(args, torch, hap, synth) -> dict:
     bt.close()
     return {"form": "batched", "workload": f"{len(sizes)} problems, N ~ U{{64..2048}}, d=16, L={L}, "
             f"damping {rp.damping}, {iters} iterations", "sum_n2": int(sum(n * n for n in sizes)),
-            "launch": {"threads": shape[0], "workgroups": shape[1]},
+            "launch": {"threads": shape[0], "workgroups": shape[1], "row_groups": shape[2]},
             "batched_s": t_batch, "plain_s": t_plain, "speedup_vs_plain": t_plain / t_batch,
             "batched_updates_per_s": upd / t_batch, "plain_updates_per_s": upd / t_plain,
             "label_agreement_min": min(agree), "label_agreement_mean": float(np.mean(agree)),

@@ -266,10 +266,16 @@ HAP_API hap_status hap_batch_create(hap_batch **out, int32_t count, const int32_
 HAP_API hap_status hap_batch_run(hap_batch *batch, const void *X, double damping, int32_t max_iters,
                                  int32_t stable_iters, int32_t *labels, double *net_similarity, int32_t *iters,
                                  void *stream);
-/* Launch shape of the persistent kernel: threads per workgroup (256 or 512) and the
- * number of workgroups (>= 1).  0 keeps the current value.  For the autotuner. */
-HAP_API hap_status hap_batch_set_launch(hap_batch *batch, int32_t threads, int32_t workgroups);
-HAP_API hap_status hap_batch_get_launch(hap_batch *batch, int32_t *threads, int32_t *workgroups);
+/* Launch shape of the persistent kernel: threads per workgroup, the number of workgroups
+ * (>= 1) and the row groups per workgroup.  With G row groups a workgroup sweeps G rows of
+ * its problem at once (each group owning NT/G threads); the rows' column-sum contributions
+ * are still added in row order, so every shape computes the same values bit for bit.
+ * (threads, row_groups) is one of (256, 1), (512, 1), (512, 2), (512, 4), (1024, 4); any
+ * other pair is rejected with HAP_ERR_ARG and changes nothing.  0 keeps the current value.
+ * For the autotuner. */
+HAP_API hap_status hap_batch_set_launch(hap_batch *batch, int32_t threads, int32_t workgroups, int32_t row_groups);
+HAP_API hap_status hap_batch_get_launch(hap_batch *batch, int32_t *threads, int32_t *workgroups,
+                                        int32_t *row_groups);
 HAP_API hap_status hap_batch_destroy(hap_batch *batch);
 
 /*

@@ -6,8 +6,8 @@ size bucket in a JSON file ($HAP_TUNING_CACHE, default ~/.cache/hap_mi355x/tunin
 
 * tune_sweep(h):  threads / chunks / rows per workgroup / streaming of the row pass of a
   single problem (Hap), timed with the library's per-launch event timing.
-* tune_batch(bt, X, damping):  threads and workgroup count of the batched persistent
-  kernel (HapBatch), timed over a short run of the whole batch.
+* tune_batch(bt, X, damping):  threads, workgroup count and row groups of the batched
+  persistent kernel (HapBatch), timed over a short run of the whole batch.
 """
 from __future__ import annotations
 
@@ -117,33 +117,44 @@ def batch_signature(sizes) -> str:
     return ",".join(f"{b}x{hist[b]}" for b in sorted(hist))
 
 
+def batch_candidates(cus: int, count: int):
+    """(threads, workgroups, row_groups) shapes tried for a batch of count problems."""
+    out = []
+    for threads, groups in ((512, 4), (1024, 4), (512, 2), (256, 1), (512, 1)):
+        for per_cu in (1, 2, 4):
+            wg = min(cus * per_cu, max(1, count))
+            if (threads, wg, groups) not in out:
+                out.append((threads, wg, groups))
+    return out
+
+
 def tune_batch(bt: "hap.HapBatch", X, damping: float, iters: int = 10, use_cache: bool = True):
-    """Pick threads and workgroup count of the persistent batched kernel for this batch."""
+    """Pick threads, workgroup count and row groups of the persistent batched kernel for
+    this batch (every shape computes the same bits, so only time decides)."""
     import torch
     key = f"batch:{_arch()}:d{bt.d}:L{bt.levels}:{batch_signature(bt.sizes)}"
     if use_cache:
         hit = _load_cache().get(key)
-        if hit:
-            bt.set_launch(hit[0], hit[1])
-            return tuple(hit[:2])
+        if hit and len(hit) == 4:
+            try:
+                bt.set_launch(*hit[:3])
+                return tuple(hit[:3])
+            except hap.HapError:
+                pass
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     out = bt.outputs(X.device)
     best, best_ms = None, float("inf")
-    for threads in (256, 512):
-        for per_cu in (1, 2, 3, 4):
-            wg = min(cus * per_cu, max(1, bt.count))
-            bt.set_launch(threads, wg)
-            bt.run(X, damping, 1, out=out)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            bt.run(X, damping, iters, out=out)
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1)
-            if ms < best_ms:
-                best, best_ms = (threads, wg), ms
-            if wg >= bt.count:
-                break
+    for shape in batch_candidates(cus, bt.count):
+        bt.set_launch(*shape)
+        bt.run(X, damping, 1, out=out)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        bt.run(X, damping, iters, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        if ms < best_ms:
+            best, best_ms = shape, ms
     bt.set_launch(*best)
     _store(key, list(best) + [best_ms])
     return best

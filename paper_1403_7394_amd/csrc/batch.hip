@@ -32,6 +32,7 @@ struct BatchArgs {
 
 namespace {
 
+typedef Vec<float>::type float4v;
 constexpr int kBins = 2048;
 
 __device__ __forceinline__ unsigned int fkey(float f) {
@@ -135,14 +136,186 @@ __device__ float median_instance(const float *__restrict__ S, int n, int ld, uns
     return (float)(((double)lo + (double)hi_v) / 2.0);
 }
 
-template <int NT, int CH>
+
+// The rows of one instance in G row groups of NTG threads (NT = G * NTG): at step k group
+// g handles row row0 + k*G + g, so G rows are in flight per workgroup; every group takes
+// the same number of steps and barriers.  Per row the work is that of sweep_rows (Eq.
+// 2.1-2.6: finish alpha^{t-1}, reduce c/e and the top two of alpha + s, then rho^t).  The
+// column sums stay in row order: groups 1..G-1 publish their rows' contributions through
+// LDS and group 0 adds them, in row order, before it adds its own next row, so the sums
+// (in group 0's registers) are the sequential column sums.
+template <int NTG, int NCH, int G, bool FIRST>
+__device__ __forceinline__ void sweep_rows_grouped(const SweepArgs<float> &a, const int t, const int row0,
+                                                   const int row1, const float4v (&Bv)[NCH], float4v (&qv)[NCH],
+                                                   float (*sh_m1)[G][NTG / 64], int (*sh_k1)[G][NTG / 64],
+                                                   float (*sh_m2)[G][NTG / 64], float (*sh_cv)[G][NTG / 64],
+                                                   int (*sh_ck)[G][NTG / 64], float4v (*contrib)[G][NCH][G > 1 ? NTG : 1]) {
+#pragma clang fp contract(off)
+    constexpr int VW = 4;
+    constexpr int NWG = NTG / 64;
+    const int tid = threadIdx.x;
+    const int grp = tid / NTG, ltid = tid % NTG;
+    const int lane = tid & 63, wid = ltid >> 6;
+    const int n = a.n;
+    const int64_t ldw = a.ldw;
+    const float lam = a.lam, oml = a.oml;
+    const float zero = 0.f, ninf = neg_inf<float>();
+    const bool has_tau = a.tau != nullptr;
+    const int base = ltid * VW;
+    const int steps = (row1 - row0 + G - 1) / G;
+    float4v xs[NCH], xr[NCH], xa[NCH];
+    for (int k = 0; k < steps; ++k) {
+        const int buf = k & 1;
+        const int i = row0 + k * G + grp;
+        const bool active = i < row1;
+        float m1 = ninf, m2 = ninf, cv = ninf;
+        int k1 = INT_MAX, ck = INT_MAX;
+        int dcol = i - base;
+        float p_i = 0.f;
+        if (active) {
+            const float *Srow = a.S + (int64_t)i * a.lds;
+            const float *Rrow = a.R + (int64_t)i * ldw;
+            float *Arow = a.A + (int64_t)i * ldw;
+            p_i = a.pref[i];
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int j0 = c * NTG * VW + base;
+                if (j0 < n) {
+                    xs[c] = __builtin_nontemporal_load((const float4v *)(Srow + j0));
+                    xr[c] = *(const float4v *)(Rrow + j0);
+                    xa[c] = *(const float4v *)(Arow + j0);
+                } else {
+                    xs[c] = (float4v)(0.f);
+                    xr[c] = (float4v)(0.f);
+                    xa[c] = (float4v)(ninf);
+                }
+            }
+            // phase 1: finish alpha^{t-1}, reduce c/e over alpha + rho and the top two of alpha + s
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int j0 = c * NTG * VW + base;
+#pragma unroll
+                for (int v = 0; v < VW; ++v) {
+                    const int j = c * NTG * VW + v;
+                    const bool diag = dcol == j;
+                    const float sj = diag ? p_i : xs[c][v];
+                    xs[c][v] = sj;
+                    const float rj = xr[c][v];
+                    float al = xa[c][v];
+                    if constexpr (!FIRST) {
+                        const float Bj = Bv[c][v];
+                        const float ah = diag ? Bj - rj : fminf(zero, Bj - fmaxf(zero, rj));
+                        al = lam * al + oml * ah;
+                        xa[c][v] = al;
+                        const float cx = al + rj;
+                        const bool gsel = cx > cv;
+                        cv = gsel ? cx : cv;
+                        ck = gsel ? j : ck;
+                    }
+                    const float y = al + sj;
+                    const bool g1 = y > m1;
+                    m2 = g1 ? m1 : fmaxf(m2, y);
+                    k1 = g1 ? j : k1;
+                    m1 = g1 ? y : m1;
+                }
+                if constexpr (!FIRST) {
+                    if (j0 < n) __builtin_nontemporal_store(xa[c], (float4v *)(Arow + j0));
+                }
+            }
+            k1 = (k1 == INT_MAX) ? INT_MAX : k1 + base;
+            ck = (ck == INT_MAX) ? INT_MAX : ck + base;
+            wave_reduce<float, !FIRST>(m1, k1, m2, cv, ck);
+            if (lane == 0) {
+                sh_m1[buf][grp][wid] = m1;
+                sh_k1[buf][grp][wid] = k1;
+                sh_m2[buf][grp][wid] = m2;
+                if constexpr (!FIRST) {
+                    sh_cv[buf][grp][wid] = cv;
+                    sh_ck[buf][grp][wid] = ck;
+                }
+            }
+        }
+        __syncthreads();
+        // group 0: the previous step's rows of groups 1..G-1, in row order, before its own row
+        if (grp == 0 && k > 0) {
+            const int pb = buf ^ 1;
+#pragma unroll
+            for (int gg = 1; gg < G; ++gg) {
+                if (row0 + (k - 1) * G + gg >= row1) break;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) qv[c] += contrib[pb][gg][c][ltid];
+            }
+        }
+        if (active) {
+            float *Rrow = a.R + (int64_t)i * ldw;
+            m1 = sh_m1[buf][grp][0];
+            k1 = sh_k1[buf][grp][0];
+            m2 = sh_m2[buf][grp][0];
+#pragma unroll
+            for (int w = 1; w < NWG; ++w)
+                top2_merge(m1, k1, m2, sh_m1[buf][grp][w], sh_k1[buf][grp][w], sh_m2[buf][grp][w]);
+            if constexpr (!FIRST) {
+                if (ltid == 0) {
+                    cv = sh_cv[buf][grp][0];
+                    ck = sh_ck[buf][grp][0];
+                    for (int w = 1; w < NWG; ++w) argmax_merge(cv, ck, sh_cv[buf][grp][w], sh_ck[buf][grp][w]);
+                    a.C[i] = cv;
+                    if (a.phi_down) a.phi_down[i] = m1;
+                    const int old = a.E[i];
+                    a.E[i] = ck;
+                    if (t >= 3 && old != ck) atomicOr(&a.ds->changed, 1);
+                }
+            }
+            // phase 2: rho^t and this row's column-sum contribution
+            asm volatile("" : "+v"(dcol));
+            const int k1r = k1 - base;
+            const float tau_i = has_tau ? a.tau[i] : zero;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int j0 = c * NTG * VW + base;
+                float4v out, q;
+#pragma unroll
+                for (int v = 0; v < VW; ++v) {
+                    const int j = c * NTG * VW + v;
+                    const float m = (j == k1r) ? m2 : m1;
+                    const float rh = has_tau ? xs[c][v] + fminf(tau_i, -m) : xs[c][v] - m;
+                    const float rn = lam * xr[c][v] + oml * rh;
+                    out[v] = rn;
+                    q[v] = (dcol == j) ? rn : fmaxf(zero, rn);
+                }
+                if (grp == 0)
+                    qv[c] += q;
+                else
+                    contrib[buf][grp][c][ltid] = q;
+                if (j0 < n) __builtin_nontemporal_store(out, (float4v *)(Rrow + j0));
+            }
+        }
+    }
+    __syncthreads();
+    // the last step's rows of groups 1..G-1
+    if (grp == 0 && steps > 0) {
+        const int pb = (steps - 1) & 1;
+#pragma unroll
+        for (int gg = 1; gg < G; ++gg) {
+            if (row0 + (steps - 1) * G + gg >= row1) break;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) qv[c] += contrib[pb][gg][c][ltid];
+        }
+    }
+}
+
+template <int NT, int G, int CH>
 __global__ __launch_bounds__(NT) void batch_kernel(BatchArgs g) {
 #pragma clang fp contract(off)
     using V = Vec<float>::type;
     constexpr int VW = 4;
     constexpr int NW = NT / 64;
-    __shared__ float sh_m1[2][NW], sh_m2[2][NW], sh_cv[2][NW];
-    __shared__ int sh_k1[2][NW], sh_ck[2][NW];
+    constexpr int NTG = NT / G;          // threads per row group
+    __shared__ float sh_cv[2][NW];
+    __shared__ int sh_ck[2][NW];
+    __shared__ float gm1[2][G][NTG / 64], gm2[2][G][NTG / 64], gcv[2][G][NTG / 64];
+    __shared__ int gk1[2][G][NTG / 64], gck[2][G][NTG / 64];
+    __shared__ float4v contrib[2][G][CH][G > 1 ? NTG : 1];
     __shared__ unsigned int hist[kBins];
     __shared__ double xs[64 * 32];
     __shared__ int sh[4];
@@ -217,23 +390,25 @@ __global__ __launch_bounds__(NT) void batch_kernel(BatchArgs g) {
                 a.lam = g.lam;
                 a.oml = g.oml;
                 a.ds = ds;
+                const int ltid = tid % NTG;
                 V Bv[CH], qv[CH];
 #pragma unroll
                 for (int c = 0; c < CH; ++c) {
-                    const int j0 = c * NT * VW + tid * VW;
+                    const int j0 = c * NTG * VW + ltid * VW;
                     Bv[c] = (t > 1 && j0 < n) ? *(const V *)(a.B + j0) : (V)(0.f);
                     qv[c] = (V)(0.f);
                 }
                 if (t == 1)
-                    sweep_rows<float, NT, CH, true, true>(a, t, 0, n, Bv, qv, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
+                    sweep_rows_grouped<NTG, CH, G, true>(a, t, 0, n, Bv, qv, gm1, gk1, gm2, gcv, gck, contrib);
                 else
-                    sweep_rows<float, NT, CH, false, true>(a, t, 0, n, Bv, qv, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
+                    sweep_rows_grouped<NTG, CH, G, false>(a, t, 0, n, Bv, qv, gm1, gk1, gm2, gcv, gck, contrib);
                 __syncthreads();   // c^l, phi^{l-1}, labels of every row are written
-                // column sums (complete, in row order), tau^{l+1}, B^{l-1} and B^l at the top
+                // column sums (complete, in row order, held by row group 0), tau^{l+1}, B^{l-1}
+                // and B^l at the top
 #pragma unroll
                 for (int c = 0; c < CH; ++c) {
-                    const int j0 = c * NT * VW + tid * VW;
-                    if (j0 >= n) continue;
+                    const int j0 = c * NTG * VW + ltid * VW;
+                    if (tid >= NTG || j0 >= n) continue;
                     *(V *)(vp(l, 1) + j0) = qv[c];
                     if (l + 1 < L) *(V *)(vp(l + 1, 3) + j0) = *(const V *)(vp(l, 4) + j0) + qv[c];
                     if (l == L - 1) *(V *)(vp(l, 5) + j0) = qv[c];
@@ -341,7 +516,8 @@ __global__ void batch_reset(int32_t *queue) { queue[0] = 0; }
 
 hipError_t launch_batch(const float *X, int64_t d, const BatchDesc *desc, const int *order, int count, int levels,
                         double lam, int max_iters, int stable_iters, float *wsf, int32_t *wsi, int32_t *queue,
-                        int32_t *labels, double *ns, int32_t *iters, int threads, int workgroups, hipStream_t st) {
+                        int32_t *labels, double *ns, int32_t *iters, int threads, int workgroups, int groups,
+                        hipStream_t st) {
     BatchArgs g;
     g.X = X;
     g.d = d;
@@ -360,11 +536,19 @@ hipError_t launch_batch(const float *X, int64_t d, const BatchDesc *desc, const 
     g.ns = ns;
     g.iters = iters;
     hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, st, queue);
-    switch (threads) {
-        case 256: hipLaunchKernelGGL((batch_kernel<256, 2>), dim3(workgroups), dim3(256), 0, st, g); break;
-        case 512: hipLaunchKernelGGL((batch_kernel<512, 1>), dim3(workgroups), dim3(512), 0, st, g); break;
-        default: return hipErrorInvalidValue;
-    }
+    // threads x row groups: every row group covers 2048 columns
+    if (threads == 256 && groups == 1)
+        hipLaunchKernelGGL((batch_kernel<256, 1, 2>), dim3(workgroups), dim3(256), 0, st, g);
+    else if (threads == 512 && groups == 1)
+        hipLaunchKernelGGL((batch_kernel<512, 1, 1>), dim3(workgroups), dim3(512), 0, st, g);
+    else if (threads == 512 && groups == 2)
+        hipLaunchKernelGGL((batch_kernel<512, 2, 2>), dim3(workgroups), dim3(512), 0, st, g);
+    else if (threads == 512 && groups == 4)
+        hipLaunchKernelGGL((batch_kernel<512, 4, 4>), dim3(workgroups), dim3(512), 0, st, g);
+    else if (threads == 1024 && groups == 4)
+        hipLaunchKernelGGL((batch_kernel<1024, 4, 2>), dim3(workgroups), dim3(1024), 0, st, g);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

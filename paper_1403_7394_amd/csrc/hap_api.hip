@@ -888,7 +888,7 @@ struct hap_batch {
     int32_t *queue = nullptr;        // device
     float *wsf = nullptr;
     int32_t *wsi = nullptr;
-    int threads = 512, workgroups = 512;
+    int threads = 512, workgroups = 512, row_groups = 4;
 };
 
 namespace {
@@ -1009,24 +1009,31 @@ hap_status hap_batch_run(hap_batch *b, const void *X, double damping, int32_t ma
     if (max_iters < 0 || stable_iters < 0) return fail_arg("hap_batch_run: negative count");
     hipError_t e = hap::launch_batch((const float *)X, b->d, b->desc, b->order, b->count, b->levels, damping, max_iters,
                                      stable_iters, b->wsf, b->wsi, b->queue, labels, net_similarity, iters, b->threads,
-                                     b->workgroups, (hipStream_t)stream);
+                                     b->workgroups, b->row_groups, (hipStream_t)stream);
     if (e != hipSuccess) return fail_hip(e, "hap_batch_run");
     return HAP_OK;
 }
 
-hap_status hap_batch_set_launch(hap_batch *b, int32_t threads, int32_t workgroups) {
+hap_status hap_batch_set_launch(hap_batch *b, int32_t threads, int32_t workgroups, int32_t row_groups) {
     if (!b) return fail_arg("hap_batch_set_launch: null pointer");
-    if (threads && threads != 256 && threads != 512) return fail_arg("hap_batch_set_launch: threads must be 256 or 512");
     if (workgroups < 0) return fail_arg("hap_batch_set_launch: workgroups must be >= 1");
-    if (threads) b->threads = threads;
+    const int th = threads ? threads : b->threads;
+    const int rg = row_groups ? row_groups : b->row_groups;
+    const bool ok = (rg == 1 && (th == 256 || th == 512)) || (rg == 2 && th == 512) || (rg == 4 && (th == 512 || th == 1024));
+    if (!ok)
+        return fail_arg("hap_batch_set_launch: (threads, row_groups) must be (256, 1), (512, 1), (512, 2), (512, 4) "
+                        "or (1024, 4)");
+    b->threads = th;
+    b->row_groups = rg;
     if (workgroups) b->workgroups = workgroups;
     return HAP_OK;
 }
 
-hap_status hap_batch_get_launch(hap_batch *b, int32_t *threads, int32_t *workgroups) {
+hap_status hap_batch_get_launch(hap_batch *b, int32_t *threads, int32_t *workgroups, int32_t *row_groups) {
     if (!b) return fail_arg("hap_batch_get_launch: null pointer");
     if (threads) *threads = b->threads;
     if (workgroups) *workgroups = b->workgroups;
+    if (row_groups) *row_groups = b->row_groups;
     return HAP_OK;
 }
 

@@ -129,7 +129,8 @@ __host__ __device__ inline int64_t batch_ints(int ld, int levels) {
 
 hipError_t launch_batch(const float *X, int64_t d, const BatchDesc *desc, const int *order, int count, int levels,
                         double lam, int max_iters, int stable_iters, float *wsf, int32_t *wsi, int32_t *queue,
-                        int32_t *labels, double *ns, int32_t *iters, int threads, int workgroups, hipStream_t st);
+                        int32_t *labels, double *ns, int32_t *iters, int threads, int workgroups, int groups,
+                        hipStream_t st);
 
 // Warm-start perceptron (mlp.hip).  Offsets of the flat parameter vector (floats) and of the
 // workspace regions (bytes) for `rows` rows.

@@ -86,8 +86,8 @@ def _declare(lib):
         "hap_batch_workspace_size": (I32, [I32, _c_i32p, I64, I32, ctypes.POINTER(SZ)]),
         "hap_batch_create": (I32, [ctypes.POINTER(V), I32, _c_i32p, I64, I32, V, SZ, V]),
         "hap_batch_run": (I32, [V, V, D, I32, I32, V, V, V, V]),
-        "hap_batch_set_launch": (I32, [V, I32, I32]),
-        "hap_batch_get_launch": (I32, [V, _c_i32p, _c_i32p]),
+        "hap_batch_set_launch": (I32, [V, I32, I32, I32]),
+        "hap_batch_get_launch": (I32, [V, _c_i32p, _c_i32p, _c_i32p]),
         "hap_batch_destroy": (I32, [V]),
         "hap_warm_features": (I32, [V, V, I64]),
         "hap_warm_targets": (I32, [V, V, I64]),
@@ -425,13 +425,15 @@ class HapBatch:
         o, n = self.offsets[b], self.sizes[b]
         return labels[self.levels * o: self.levels * (o + n)].view(self.levels, n)
 
-    def set_launch(self, threads=0, workgroups=0):
-        _check("hap_batch_set_launch", self._lib.hap_batch_set_launch(self._h, threads, workgroups))
+    def set_launch(self, threads=0, workgroups=0, row_groups=0):
+        _check("hap_batch_set_launch", self._lib.hap_batch_set_launch(self._h, threads, workgroups, row_groups))
 
     def get_launch(self):
-        a, b = ctypes.c_int32(), ctypes.c_int32()
-        _check("hap_batch_get_launch", self._lib.hap_batch_get_launch(self._h, ctypes.byref(a), ctypes.byref(b)))
-        return a.value, b.value
+        """(threads, workgroups, row_groups)"""
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check("hap_batch_get_launch", self._lib.hap_batch_get_launch(self._h, ctypes.byref(a), ctypes.byref(b),
+                                                                      ctypes.byref(c)))
+        return a.value, b.value, c.value
 
     def close(self):
         if getattr(self, "_h", None):

@@ -61,6 +61,32 @@ def test_batch_matches_fp32_oracle_exactly(hap_gpu):
         assert abs(ns[b, L] - sum(ns[b, :L])) <= 1e-12 * abs(ns[b, L])
 
 
+@pytest.mark.parametrize("row_groups,threads", [(2, 512), (4, 512), (4, 1024)])
+def test_batch_row_groups_match_fp32_oracle_exactly(hap_gpu, row_groups, threads):
+    """Row groups sweep several rows of a problem at once; sizes cover fewer rows than
+    groups, a ragged last step and the full 2048-column width."""
+    sizes = [3, 5, 130, 2048, 1029]
+    Xs = _problems(sizes, seed=700)
+    L, lam, T = 3, 0.8, 25
+    labels, ns, iters = _run_batch(hap_gpu, Xs, L, lam, T, launch=(threads, 2, row_groups))
+    for b, X in enumerate(Xs):
+        r, ns_ref = _oracle(X, L, lam, T)
+        assert np.array_equal(labels[b], r.labels), b
+        assert iters[b] == T
+        for l in range(L):
+            assert abs(ns[b, l] - ns_ref[l]) <= 1e-12 * abs(ns_ref[l]) + 1e-300, (b, l)
+
+
+def test_batch_row_groups_stop_rule(hap_gpu):
+    Xs = _problems([60, 90, 201], d=4, seed=400)
+    L, lam, K = 1, 0.9, 20
+    labels, ns, iters = _run_batch(hap_gpu, Xs, L, lam, 800, K, launch=(512, 3, 4))
+    for b, X in enumerate(Xs):
+        r, _ = _oracle(X, L, lam, 800, K)
+        assert iters[b] == r.iters, b
+        assert np.array_equal(labels[b], r.labels), b
+
+
 def test_batch_stop_rule_matches_oracle(hap_gpu):
     Xs = _problems([60, 90, 200], d=4, seed=400)
     L, lam, K = 1, 0.9, 20
@@ -72,8 +98,11 @@ def test_batch_stop_rule_matches_oracle(hap_gpu):
         assert np.array_equal(labels[b], r.labels), b
 
 
-@pytest.mark.parametrize("launch", [(256, 1), (512, 3), (256, 1000)])
+@pytest.mark.parametrize("launch", [(256, 1, 1), (512, 3, 1), (256, 1000, 1), (512, 5, 2), (512, 2, 4),
+                                    (1024, 7, 4)])
 def test_batch_launch_shapes_agree(hap_gpu, launch):
+    """Every launch shape, row groups included, gives the same bits (the column sums of a
+    problem are added in row order whatever the shape)."""
     Xs = _problems([300, 33, 1500, 64, 512], seed=500)
     base = _run_batch(hap_gpu, Xs, 3, 0.8, 12)
     got = _run_batch(hap_gpu, Xs, 3, 0.8, 12, launch=launch)
