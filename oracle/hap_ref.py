@@ -21,8 +21,17 @@ Readings of points the paper leaves open (each is listed in the design notes):
   * max_{k != j} runs over every column k != j including k = i (whose
     similarity is the preference); a maximum attained twice gives M2 = M1.
   * argmax ties go to the lowest index.
-  * The similarity is the same at every level (the optional Eq. 2.7 update is
-    off); the diagonal s^l_jj holds the level-l preference p^l_j.
+  * The similarity is the same at every level unless kappa != 0 (the optional
+    Eq. 2.7 update is off by default); the diagonal s^l_jj holds the level-l
+    preference p^l_j.
+  * Eq. 2.7 (kappa != 0, level-sequential schedule only): the maximum over j != i
+    leaves one number per row, so the update adds a per-row offset to the
+    off-diagonal of the next level's similarity, s^{l+1}_ij = s_ij + delta^{l+1}_i
+    with delta^{l+1}_i = delta^l_i + kappa * max_{j != i}(alpha^l_ij + rho^l_ij) and
+    delta^1 = 0.  It runs as the last step of level l in every iteration (after the
+    c update, from that iteration's alpha^l and rho^l), so delta is recomputed in
+    every iteration and not accumulated over iterations; the diagonal keeps the
+    preference.
   * Stopping with K > 0: after each iteration t the labels of every level are
     compared with those of iteration t-1; the stable count goes up by one when
     none changed (t >= 2) and resets to 0 otherwise; the run stops at the end of
@@ -47,14 +56,15 @@ class HapState:
     c: np.ndarray        # (L, N) cluster preference, Eq. 2.6
     phi: np.ndarray      # (L, N) downward message, Eq. 2.5 (phi^l is sent by level l+1)
     tau: np.ndarray      # (L, N) upward message, Eq. 2.4 (tau^1 = +inf)
+    delta: np.ndarray | None = None    # (L, N) Eq. 2.7 row offsets of s^l (delta^1 = 0)
     t: int = 0           # completed iterations
     stable: int = 0      # consecutive iterations with unchanged labels
     labels: np.ndarray | None = None   # (L, N) labels of iteration t
 
     def copy(self) -> "HapState":
         return HapState(self.rho.copy(), self.alpha.copy(), self.c.copy(), self.phi.copy(),
-                        self.tau.copy(), self.t, self.stable,
-                        None if self.labels is None else self.labels.copy())
+                        self.tau.copy(), None if self.delta is None else self.delta.copy(), self.t,
+                        self.stable, None if self.labels is None else self.labels.copy())
 
 
 @dataclass
@@ -74,11 +84,27 @@ def level_similarity(S: np.ndarray, pref_l: np.ndarray, dtype=np.float64) -> np.
     return s
 
 
+def offset_similarity(S: np.ndarray, pref_l: np.ndarray, delta_l: np.ndarray, dtype=np.float64) -> np.ndarray:
+    """s^l under Eq. 2.7: S_ij + delta^l_i off the diagonal, the level-l preferences on it."""
+    S = np.asarray(S, dtype=dtype)
+    s = S + np.asarray(delta_l, dtype=dtype)[:, None]
+    np.fill_diagonal(s, pref_l)
+    return s
+
+
+def offdiag_max(v: np.ndarray) -> np.ndarray:
+    """max_{j != i} v_ij of every row (-inf for a 1 x 1 matrix)."""
+    w = np.array(v, copy=True)
+    np.fill_diagonal(w, -np.inf)
+    return np.max(w, axis=1)
+
+
 def init_state(N: int, L: int, alpha0: np.ndarray | None = None, dtype=np.float64) -> HapState:
     """Algorithm 1 initialisation: alpha = rho = 0, tau = +inf, phi = c = 0."""
     alpha = np.zeros((L, N, N), dtype) if alpha0 is None else np.array(alpha0, dtype=dtype, copy=True)
     return HapState(rho=np.zeros((L, N, N), dtype), alpha=alpha, c=np.zeros((L, N), dtype),
-                    phi=np.zeros((L, N), dtype), tau=np.full((L, N), np.inf, dtype))
+                    phi=np.zeros((L, N), dtype), tau=np.full((L, N), np.inf, dtype),
+                    delta=np.zeros((L, N), dtype))
 
 
 def responsibility(s: np.ndarray, alpha: np.ndarray, tau: np.ndarray | None) -> np.ndarray:
@@ -154,7 +180,7 @@ def _iteration_mrhap(st: HapState, s, L: int, lam, oml, Q, record, c_zero: bool)
 
 def hap(S, pref, levels: int, damping: float, max_iters: int, stable_iters: int = 0,
         alpha0=None, state: HapState | None = None, record=None, c_zero: bool = False,
-        dtype=np.float64, schedule: str = "sequential") -> HapResult:
+        dtype=np.float64, schedule: str = "sequential", kappa: float = 0.0) -> HapResult:
     """Run HAP (Algorithm 1), in FP64 unless `dtype` says otherwise.
 
     The paper fixes no precision.  dtype=np.float32 evaluates the same steps with every
@@ -172,9 +198,15 @@ def hap(S, pref, levels: int, damping: float, max_iters: int, stable_iters: int 
     schedule "sequential": the levels one after another inside an iteration (Algorithm 1);
            "mrhap": the MapReduce schedule of Section 3 (every level from the previous
            iteration's state; tau and c not updated in the first iteration).
+    kappa  Eq. 2.7 weight in [0, 1]; 0 (the default) keeps s^l = s at every level.  Defined
+           for the level-sequential schedule only.
     """
     if schedule not in ("sequential", "mrhap"):
         raise ValueError(schedule)
+    if not 0.0 <= float(kappa) <= 1.0:
+        raise ValueError("kappa must lie in [0, 1]")
+    if float(kappa) != 0.0 and schedule != "sequential":
+        raise ValueError("the level-wise similarity update is defined for the level-sequential schedule")
     dt = np.dtype(dtype).type
     S = np.asarray(S, dtype=dt)
     N = S.shape[0]
@@ -189,6 +221,10 @@ def hap(S, pref, levels: int, damping: float, max_iters: int, stable_iters: int 
     s = [level_similarity(S, p[l], dt) for l in range(L)]
 
     st = init_state(N, L, alpha0, dt) if state is None else state.copy()
+    if st.delta is None:
+        st.delta = np.zeros((L, N), dt)
+    kap = dt(kappa)
+    use_kappa = float(kappa) != 0.0
     Q = np.zeros((L, N), dt)
     converged = False
     for _ in range(max_iters):
@@ -196,6 +232,8 @@ def hap(S, pref, levels: int, damping: float, max_iters: int, stable_iters: int 
         if schedule == "mrhap":
             _iteration_mrhap(st, s, L, lam, oml, Q, record, c_zero)
         for l in (range(L) if schedule == "sequential" else ()):
+            if use_kappa and l > 0:
+                s[l] = offset_similarity(S, p[l], st.delta[l], dt)   # s^l of this iteration (Eq. 2.7)
             # Eq. 2.1, then damp
             rhat = responsibility(s[l], st.alpha[l], None if l == 0 else st.tau[l])
             st.rho[l] = lam * st.rho[l] + oml * rhat
@@ -210,6 +248,9 @@ def hap(S, pref, levels: int, damping: float, max_iters: int, stable_iters: int 
                 st.phi[l - 1] = np.max(st.alpha[l] + s[l], axis=1)
             if l < L - 1 and not c_zero:
                 st.c[l] = np.max(st.alpha[l] + st.rho[l], axis=1)
+            # Eq. 2.7 (optional): row offsets of the next level's similarity
+            if use_kappa and l < L - 1:
+                st.delta[l + 1] = st.delta[l] + kap * offdiag_max(st.alpha[l] + st.rho[l])
             if record is not None:
                 record(st.t, l, st)
         if stable_iters > 0:

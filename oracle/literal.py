@@ -11,6 +11,9 @@ loops and no algebraic shortcut:
   Eq. 2.5  phi^{l-1}_i = max_k(alpha^l_ik + s^l_ik)
   Eq. 2.6  c^l_i = max_j(alpha^l_ij + rho^l_ij)
   Eq. 2.8  e^l_i = argmax_j(alpha^l_ij + rho^l_ij), lowest index on ties
+  Eq. 2.7  (optional, kappa given) s^{l+1}_ij = s_ij + delta^{l+1}_i for j != i, with the row
+           offset delta^{l+1}_i = delta^l_i + kappa * max_{j != i}(alpha^l_ij + rho^l_ij),
+           delta^1 = 0, recomputed in every iteration after the level's c update
 The schedule and readings are the same as in ``hap_ref`` (schedule="mrhap" gives the
 MapReduce schedule of Section 3: every level from the previous iteration's state, tau and
 c not updated in the first iteration).  The cost is O(L N^3) per iteration, so this is for
@@ -39,10 +42,11 @@ def _colsum_plus(rho_l, j, N, zero, c_j):
     return acc
 
 
-def hap_literal(S, pref, levels, damping, iters, num=Fraction, schedule="sequential"):
+def hap_literal(S, pref, levels, damping, iters, num=Fraction, schedule="sequential", kappa=None):
     """S: N x N nested lists/array (diagonal ignored); pref: L x N; damping: number.
 
-    Returns (labels, rho, alpha, c, phi, tau) as nested lists of `num`.
+    Returns (labels, rho, alpha, c, phi, tau) as nested lists of `num`, and when `kappa` is
+    given (level-sequential schedule only) the row offsets delta (L x N) as a seventh item.
     """
     N = len(S)
     L = int(levels)
@@ -56,6 +60,10 @@ def hap_literal(S, pref, levels, damping, iters, num=Fraction, schedule="sequent
     c = [[zero] * N for _ in range(L)]
     phi = [[zero] * N for _ in range(L)]
     tau = [[None] * N for _ in range(L)]
+    delta = [[zero] * N for _ in range(L)]
+    kap = None if kappa is None else (num(kappa) if not isinstance(kappa, num) else kappa)
+    if kap is not None and schedule != "sequential":
+        raise ValueError("the level-wise similarity update is defined for the level-sequential schedule")
 
     def rho_update(l):
         # Eq. 2.1 with damping
@@ -127,6 +135,19 @@ def hap_literal(S, pref, levels, damping, iters, num=Fraction, schedule="sequent
                 phi[l - 1] = [max(alpha[l][i][k] + s[l][i][k] for k in range(N)) for i in range(N)]
             if l < L - 1:
                 c[l] = c_of(l)
+            # Eq. 2.7: the next level's similarity, row offsets from this level's messages
+            if kap is not None and l < L - 1:
+                for i in range(N):
+                    mx = None
+                    for j in range(N):
+                        if j != i:
+                            v = alpha[l][i][j] + rho[l][i][j]
+                            if mx is None or v > mx:
+                                mx = v
+                    delta[l + 1][i] = delta[l][i] + kap * mx
+                    for j in range(N):
+                        if j != i:
+                            s[l + 1][i][j] = num(S[i][j]) + delta[l + 1][i]
 
     labels = []
     for l in range(L):
@@ -139,4 +160,6 @@ def hap_literal(S, pref, levels, damping, iters, num=Fraction, schedule="sequent
                     best, arg = v, j
             row.append(arg)
         labels.append(row)
+    if kap is not None:
+        return labels, rho, alpha, c, phi, tau, delta
     return labels, rho, alpha, c, phi, tau
