@@ -416,6 +416,9 @@ def main() -> int:
     ap.add_argument("--read-s", action="store_true", help="plain form: the row pass reads S (no points mode)")
     ap.add_argument("--schedule", choices=["sequential", "mrhap"], default="sequential",
                     help="plain form: Algorithm 1's level-sequential schedule or the MapReduce one (Section 3)")
+    ap.add_argument("--kappa", type=float, default=0.0,
+                    help="plain form: weight of the optional level-wise similarity update (Eq. 2.7); "
+                         "> 0 makes the row pass read S")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -459,12 +462,12 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
 
-    points = not args.read_s
+    points = not args.read_s and args.kappa == 0.0
     schedule = hap.SCHEDULE_MRHAP if args.schedule == "mrhap" else hap.SCHEDULE_SEQUENTIAL
 
     def step(profile: bool):
         hap.build_similarity(X, S)
-        h = hap.Hap(S, L, rp.damping, workspace=ws, schedule=schedule)
+        h = hap.Hap(S, L, rp.damping, workspace=ws, schedule=schedule, kappa=args.kappa)
         if points:
             h.set_points(X)
         if profile:
@@ -508,7 +511,8 @@ def main() -> int:
     bytes_per_launch = alg_bytes_total / max(row_n, 1)
     avg_launch_s = row_ms / max(row_n, 1) * 1e-3
     achieved = bytes_per_launch / avg_launch_s / 1e9
-    traffic = measured_traffic(points, first_sweeps * L, row_n - first_sweeps * L)
+    # the counters were taken on the plain row pass; the Eq. 2.7 instance is another kernel
+    traffic = measured_traffic(points, first_sweeps * L, row_n - first_sweeps * L) if args.kappa == 0.0 else None
     ms_per_step = elapsed / args.steps * 1e3
     value = n * n * L * sweeps / elapsed
 
@@ -530,6 +534,7 @@ def main() -> int:
                         "median preference, 500 iterations or 50 stable",
             "row_pass": "points mode (s_ij recomputed from the points)" if points else "reads S",
             "schedule": args.schedule,
+            "kappa": args.kappa,
             "n": n, "levels": L, "damping": rp.damping, "max_iters": rp.max_iters,
             "stable_iters": rp.stable_iters, "seed": blobs.seed,
         },
@@ -540,7 +545,8 @@ def main() -> int:
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "row pass (sweep_kernel, points mode)" if points else "row pass (sweep_kernel)",
+            "kernel": ("row pass (sweep_kernel, points mode)" if points else
+                       "row pass (sweep_kernel, S read, Eq. 2.7 row offsets)" if args.kappa else "row pass (sweep_kernel)"),
             "avg_launch_us": avg_launch_s * 1e6,
             "alg_bytes_per_launch": bytes_per_launch,
             "launches_timed": row_n,

@@ -98,7 +98,21 @@ typedef struct {
     int32_t schedule;           /* HAP_SCHEDULE_* */
     const double *pref_scalar;  /* host [levels], HAP_PREF_SCALAR only */
     const void *pref_vec;       /* device [levels*n] in the working type, HAP_PREF_VECTOR only */
+    double kappa;               /* Eq. 2.7 weight in [0, 1]; 0 = the update is off (see below) */
 } hap_params;
+
+/*
+ * Optional level-wise similarity update (Eq. 2.7, the optional step of Algorithm 1),
+ * kappa > 0, level-sequential schedule only (hap_init rejects it with HAP_SCHEDULE_MRHAP,
+ * and a kappa outside [0, 1], with HAP_E_ARG).  The maximum of Eq. 2.7 runs over j != i,
+ * so it gives one value per row: level l+1 uses s^{l+1}_ij = s_ij + delta^{l+1}_i off the
+ * diagonal (the diagonal keeps the preference), with
+ *   delta^{l+1}_i = delta^l_i + kappa * max_{j != i}(alpha^l_ij + rho^l_ij),  delta^1 = 0,
+ * computed in every iteration as the last step of level l, from that iteration's alpha^l
+ * and rho^l (not accumulated over iterations).  No N x N matrix is stored; each level below
+ * the top adds two row-parallel passes per iteration (3 and 2 N^2 reads).  Net similarity
+ * (hap_net_similarity) is still taken on S.
+ */
 
 typedef struct hap_ctx hap_ctx;
 
@@ -188,6 +202,13 @@ HAP_API hap_status hap_preference(hap_ctx *ctx, double *out);
  */
 HAP_API hap_status hap_read_messages(hap_ctx *ctx, int32_t level, void *rho, void *alpha, int64_t ld,
                              void *c, void *phi, void *tau);
+
+/*
+ * Eq. 2.7 row offsets delta^l of level `level` after the last completed iteration: delta
+ * device [n] in the working type (all 0 at level 0, and at every level when kappa = 0).
+ * Synchronises the stream.
+ */
+HAP_API hap_status hap_similarity_offsets(hap_ctx *ctx, int32_t level, void *delta);
 
 /*
  * Override the sweep launch shape: threads per row (64..1024, power of two),

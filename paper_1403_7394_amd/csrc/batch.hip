@@ -385,6 +385,7 @@ __global__ __launch_bounds__(NT) void batch_kernel(BatchArgs g) {
                 a.tau_q = nullptr;
                 a.tau_store = nullptr;
                 a.mrhap = 0;
+                a.delta = nullptr;
                 a.n = n;
                 a.rb = n;
                 a.lam = g.lam;

@@ -46,7 +46,8 @@ struct hap_ctx {
 
     // workspace regions
     char *R = nullptr, *A = nullptr, *pref = nullptr, *Q = nullptr, *phi = nullptr, *tau = nullptr, *C = nullptr,
-         *B = nullptr;
+         *B = nullptr, *delta = nullptr;
+    double kappa = 0.0;           // Eq. 2.7 weight (0: the update is off)
     int32_t *E = nullptr, *Efinal = nullptr, *mark = nullptr, *count = nullptr;
     char *Qpart = nullptr;
     DevState *ds = nullptr;
@@ -87,7 +88,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-    size_t R, A, pref, Q, phi, tau, C, B, E, Efinal, mark, count, Qpart, ds, dbl, sel, total;
+    size_t R, A, pref, Q, phi, tau, C, B, delta, E, Efinal, mark, count, Qpart, ds, dbl, sel, total;
     int64_t ldw;
     int nb_cap;
 };
@@ -112,6 +113,7 @@ Layout make_layout(int64_t n, int L, size_t esz) {
     lo.tau = take(vec * L);
     lo.C = take(vec * L);
     lo.B = take(vec * L);
+    lo.delta = take(vec * L);
     lo.E = take((size_t)lo.ldw * 4 * L);
     lo.Efinal = take((size_t)lo.ldw * 4 * L);
     lo.mark = take((size_t)lo.ldw * 4);
@@ -156,6 +158,7 @@ LevelPtrs<T> level_ptrs(const hap_ctx *c, int l) {
     p.B = (T *)c->B + (size_t)c->ldw * l;
     p.E = c->E + (size_t)c->ldw * l;
     p.Efinal = c->Efinal + (size_t)c->ldw * l;
+    p.delta = (T *)c->delta + (size_t)c->ldw * l;
     return p;
 }
 
@@ -260,11 +263,15 @@ hap_status run_sweeps(hap_ctx *c, int count, int K) {
     ex.X = (const T *)c->X;
     ex.ldx = c->ldx;
     ex.d = c->d;
+    const bool kappa = c->kappa != 0.0;
     auto row = [&](int l, T *qp) -> hap_status {
         LevelPtrs<T> lv = level_ptrs<T>(c, l);
         LevelPtrs<T> down = level_ptrs<T>(c, l > 0 ? l - 1 : 0);
-        T *phi_down = l > 0 ? down.phi : nullptr;
+        // with the Eq. 2.7 update phi^{l-1} comes from level_phi (it needs the offsets of the
+        // previous iteration, the row pass applies this iteration's)
+        T *phi_down = (l > 0 && !kappa) ? down.phi : nullptr;
         hap::SweepExtra<T> e = ex;
+        if (kappa && l > 0) e.delta = lv.delta;
         const T *tau_l = nullptr;
         if (c->schedule == HAP_SCHEDULE_MRHAP) {
             e.mrhap = 1;
@@ -310,6 +317,17 @@ hap_status run_sweeps(hap_ctx *c, int count, int K) {
             for (int l = 0; l < L; ++l) {
                 hap_status s = row(l, Qpart[0]);
                 if (s == HAP_OK) s = col(l, Qpart[0], true);
+                if (s == HAP_OK && kappa && l + 1 < L) {
+                    // Eq. 2.7: phi^l of iteration t-1, then the offsets delta^{l+1} of iteration t
+                    LevelPtrs<T> lv = level_ptrs<T>(c, l);
+                    LevelPtrs<T> up = level_ptrs<T>(c, l + 1);
+                    HIP_TRY(hap::launch_level_phi<T>((const T *)c->S, c->lds, up, lv.phi, (int)c->n, c->ldw, c->lam,
+                                                     c->ds, c->stream),
+                            c);
+                    HIP_TRY(hap::launch_level_delta<T>(lv, up.delta, (int)c->n, c->ldw, c->lam, c->kappa, c->ds,
+                                                       c->stream),
+                            c);
+                }
                 if (s != HAP_OK) return s;
             }
         }
@@ -478,6 +496,9 @@ hap_status hap_init(hap_ctx **out, const void *S, int64_t n, int64_t lds, int32_
     }
     if (p->schedule != HAP_SCHEDULE_SEQUENTIAL && p->schedule != HAP_SCHEDULE_MRHAP)
         return fail_arg("hap_init: schedule");
+    if (!(p->kappa >= 0.0 && p->kappa <= 1.0)) return fail_arg("hap_init: kappa must be in [0, 1]");
+    if (p->kappa != 0.0 && p->schedule != HAP_SCHEDULE_SEQUENTIAL)
+        return fail_arg("hap_init: the level-wise similarity update (kappa > 0) needs the level-sequential schedule");
     const size_t esz = dtype_size(dtype);
     Layout lo = make_layout(n, p->levels, esz);
     Launch lc = default_launch(n, esz);
@@ -501,6 +522,7 @@ hap_status hap_init(hap_ctx **out, const void *S, int64_t n, int64_t lds, int32_
     c->ldw = lo.ldw;
     c->L = p->levels;
     c->schedule = p->schedule;
+    c->kappa = p->kappa;
     c->dtype = dtype;
     c->esz = esz;
     c->lam = p->damping;
@@ -529,6 +551,7 @@ hap_status hap_init(hap_ctx **out, const void *S, int64_t n, int64_t lds, int32_
     c->tau = base + lo.tau;
     c->C = base + lo.C;
     c->B = base + lo.B;
+    c->delta = base + lo.delta;
     c->E = (int32_t *)(base + lo.E);
     c->Efinal = (int32_t *)(base + lo.Efinal);
     c->mark = (int32_t *)(base + lo.mark);
@@ -745,12 +768,14 @@ hap_status hap_read_messages(hap_ctx *c, int32_t level, void *rho, void *alpha, 
         } else if (c->dtype == HAP_F32) {
             LevelPtrs<float> up = level_ptrs<float>(c, level + 1);
             HIP_TRY(hap::launch_finalize<float>((const float *)c->S, c->lds, up, (int)c->n, c->ldw, c->lam, c->t_host,
-                                                nullptr, nullptr, 0, nullptr, (float *)phi, c->ds, st),
+                                                nullptr, nullptr, 0, nullptr, (float *)phi, c->ds, st,
+                                                c->kappa != 0.0 ? up.delta : nullptr),
                     c);
         } else {
             LevelPtrs<double> up = level_ptrs<double>(c, level + 1);
             HIP_TRY(hap::launch_finalize<double>((const double *)c->S, c->lds, up, (int)c->n, c->ldw, c->lam, c->t_host,
-                                                 nullptr, nullptr, 0, nullptr, (double *)phi, c->ds, st),
+                                                 nullptr, nullptr, 0, nullptr, (double *)phi, c->ds, st,
+                                                 c->kappa != 0.0 ? up.delta : nullptr),
                     c);
         }
     }
@@ -779,6 +804,16 @@ hap_status hap_read_messages(hap_ctx *c, int32_t level, void *rho, void *alpha, 
         }
     }
     HIP_TRY(hipStreamSynchronize(st), c);
+    return HAP_OK;
+}
+
+hap_status hap_similarity_offsets(hap_ctx *c, int32_t level, void *delta) {
+    if (!c || !delta) return fail_arg("hap_similarity_offsets: null pointer");
+    if (level < 0 || level >= c->L) return fail_arg("hap_similarity_offsets: level out of range");
+    if (c->failed) return fail_arg("hap_similarity_offsets: context failed earlier", HAP_E_STATE);
+    const char *src = c->delta + (size_t)c->ldw * c->esz * level;
+    HIP_TRY(hipMemcpyAsync(delta, src, (size_t)c->n * c->esz, hipMemcpyDeviceToDevice, c->stream), c);
+    HIP_TRY(hipStreamSynchronize(c->stream), c);
     return HAP_OK;
 }
 

@@ -59,6 +59,7 @@ struct LevelPtrs {
     T *B;              // [ldw] availability base c + phi + Q (Q at the top level) of the last sweep
     int32_t *E;        // [ldw] labels of the last label pass
     int32_t *Efinal;   // [ldw] labels reported by hap_exemplars
+    T *delta;          // [ldw] Eq. 2.7 row offsets of s^l (0 at l = 0 and while the update is off)
 };
 
 // Host launchers (defined in the .hip files).
@@ -73,6 +74,7 @@ struct SweepExtra {
     const T *tau_c = nullptr, *tau_q = nullptr;
     T *tau_store = nullptr;
     int mrhap = 0;
+    const T *delta = nullptr;   // Eq. 2.7 row offsets of this level's similarity
 };
 template <typename T>
 hipError_t launch_sweep_level(const T *S, int64_t lds, const LevelPtrs<T> &lv, T *phi_down,
@@ -85,7 +87,20 @@ hipError_t launch_colsum(const T *Qpart, int64_t ldw, int nb, int n, const Level
 template <typename T>
 hipError_t launch_finalize(const T *S, int64_t lds, const LevelPtrs<T> &lv, int n, int64_t ldw, double lam, int t,
                            int32_t *labels_out, T *alpha_out, int64_t lda, T *c_out, T *phi_out, DevState *ds,
-                           hipStream_t st);
+                           hipStream_t st, const T *delta = nullptr);
+// Optional level-wise similarity update (Eq. 2.7), level-sequential schedule.  Run after the
+// column sums of level l in iteration t, before the row pass of level l+1:
+//   launch_level_phi:   phi^l = max_k(alpha^{l+1,t-1}_ik + s^{l+1,t-1}_ik), alpha^{l+1,t-1}
+//                       finished on the fly from the state of level l+1 (up), with up.delta still
+//                       holding the offsets of iteration t-1; nothing in iteration 1 (phi^l = 0)
+//   launch_level_delta: delta^{l+1}_i = delta^l_i + kappa * max_{j != i}(alpha^{l,t}_ij + rho^{l,t}_ij),
+//                       alpha^{l,t} finished on the fly with B_j = (c^l_j + phi^l_j) + Q^l_j
+template <typename T>
+hipError_t launch_level_phi(const T *S, int64_t lds, const LevelPtrs<T> &up, T *phi_out, int n, int64_t ldw,
+                            double lam, const DevState *ds, hipStream_t st);
+template <typename T>
+hipError_t launch_level_delta(const LevelPtrs<T> &lv, T *delta_next, int n, int64_t ldw, double lam, double kappa,
+                              const DevState *ds, hipStream_t st);
 bool launch_supported(int threads, int chunks, int elem_size);
 template <typename T>
 hipError_t launch_alpha_pad(T *A, int64_t rows, int n, int64_t ldw, hipStream_t st);

@@ -34,6 +34,10 @@ struct SweepArgs {
     const T *tau_c, *tau_q;
     T *tau_store;
     int mrhap;
+    // Eq. 2.7 (optional): row offsets of this level's similarity, s_ij + delta_i off the
+    // diagonal (read by the D < 0 instances of the register-resident row pass and by the
+    // streaming row pass); nullptr when the update is off
+    const T *delta;
 };
 
 // The upward message this row pass clips with (Eq. 2.1 at l > 1), or false for no clip.
@@ -100,6 +104,9 @@ struct RowRegs {
 // from initialisation and stay -inf or NaN, which '>' and fmax ignore.  Padding columns of
 // R, A and the column partials are never read back as results.
 //
+// D < 0: S is read and the row offset a.delta[i] of the optional level-wise similarity
+// update (Eq. 2.7) is added to it.
+//
 // D > 0 (points mode): instead of reading S, s_ij is recomputed from the D coordinates of
 // points i and j exactly as the direct similarity build computes it (squared differences
 // summed in FP64 in coordinate order, no contraction, negated, rounded once), so the values
@@ -122,9 +129,10 @@ __device__ __forceinline__ void load_row(const SweepArgs<T> &a, int i, RowRegs<T
     for (int c = 0; c < NCH; ++c) {
         const int j0 = c * NT * VW + threadIdx.x * VW;
         if (!TAIL || j0 < a.n) {
-            if constexpr (D == 0) {
+            if constexpr (D <= 0) {
                 // S streams through once per level: non-temporal, so it does not displace R/A lines
                 x.s[c] = __builtin_nontemporal_load((const V *)(Srow + j0));
+                if constexpr (D < 0) x.s[c] = x.s[c] + a.delta[i];   // Eq. 2.7 row offset
             } else {
 #pragma unroll
                 for (int v = 0; v < VW; ++v) {

@@ -139,12 +139,15 @@ __device__ __forceinline__ void stream_rows(const SweepArgs<T> &a, const int t, 
         const __amdgpu_buffer_rsrc_t rA = row_rsrc(a.A + (int64_t)i * ldw, ldw * (int64_t)sizeof(T));
         const T p_i = a.pref[i];
         const int dcol = i - base;
+        const bool has_d = a.delta != nullptr;
+        const T d_i = has_d ? a.delta[i] : zero;
         T m1 = ninf, m2 = ninf, cv = ninf;
         int k1 = INT_MAX, ck = INT_MAX;   // offsets from base until the reduction
         // phase 1
         for (int c = 0; c < nch; ++c) {
             const int off0 = c * NT * VW;   // this chunk's column offset from base
-            const V sv = buf_load<V, 0>(rS, voff, c * CB);
+            V sv = buf_load<V, 0>(rS, voff, c * CB);
+            if (has_d) sv = sv + d_i;
             const V rv = buf_load<V, 0>(rR, voff, c * CB);
             V av = buf_load<V, 0>(rA, voff, c * CB);
             V bv = (V)(zero);
@@ -216,7 +219,8 @@ __device__ __forceinline__ void stream_rows(const SweepArgs<T> &a, const int t, 
         if (a.tau_store && tid == 0) a.tau_store[i] = has_tau ? tau_i : pos_inf<T>();
         for (int c = 0; c < nch; ++c) {
             const int off0 = c * NT * VW;
-            const V sv = buf_load<V, 0>(rS, voff, c * CB);
+            V sv = buf_load<V, 0>(rS, voff, c * CB);
+            if (has_d) sv = sv + d_i;
             const V rv = buf_load<V, 0>(rR, voff, c * CB);
             V out;
 #pragma unroll
@@ -307,6 +311,11 @@ __global__ __launch_bounds__(16 * NG) void colsum_kernel(ColArgs<T> a) {
     using V = typename Vec<T>::type;
     constexpr int VW = Vec<T>::N;
     __shared__ V sh[NG][16];
+    // After an early stop the row passes do nothing and the shared partial buffer is stale, so
+    // the levels below the top keep their sums.  The top level's partials are the last ones
+    // written, so its launch (which also applies the stop rule, and is the only one that can
+    // set the flag) recomputes the same values.
+    if (!a.last && a.ds->done) return;
     // 16 column vectors per workgroup; group g sums partial rows g, g+NG, g+2NG, ... in order
     const int col = threadIdx.x & 15, g = threadIdx.x >> 4;
     const int j0 = (blockIdx.x * 16 + col) * VW;
@@ -376,6 +385,7 @@ struct FinArgs {
     int64_t lda;
     T *c_out;
     T *phi_out;
+    const T *delta;      // Eq. 2.7 row offsets of this level's s, or nullptr
     int n, t;
     T lam, oml;
     DevState *ds;
@@ -398,10 +408,13 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs<T> a) {
     const T *Rrow = a.R + (int64_t)i * a.ldw;
     const T *Arow = a.A + (int64_t)i * a.ldw;
     const T p_i = a.pref[i];
+    const bool has_d = a.delta != nullptr;
+    const T d_i = has_d ? a.delta[i] : zero;
     T mx = neg_inf<T>(), cv = neg_inf<T>();
     int ck = INT_MAX;
     for (int j0 = tid * VW; j0 < n; j0 += NT * VW) {
-        const V sv = *(const V *)(Srow + j0);
+        V sv = *(const V *)(Srow + j0);
+        if (has_d) sv = sv + d_i;
         const V rv = *(const V *)(Rrow + j0);
         V av = *(const V *)(Arow + j0);
         const V bv = *(const V *)(a.B + j0);
@@ -544,6 +557,7 @@ hipError_t launch_sweep_level(const T *S, int64_t lds, const LevelPtrs<T> &lv, T
     a.tau_q = ex.tau_q;
     a.tau_store = ex.tau_store;
     a.mrhap = ex.mrhap;
+    a.delta = ex.delta;
     const int nb = (n + lc.rows_per_block - 1) / lc.rows_per_block;
     const bool tail = (int64_t)lc.threads * lc.chunks * Vec<T>::N != n;
     if (lc.streaming) {
@@ -554,6 +568,7 @@ hipError_t launch_sweep_level(const T *S, int64_t lds, const LevelPtrs<T> &lv, T
             hipLaunchKernelGGL((sweep_stream_kernel<T, 1024, false>), dim3(nb), dim3(1024), 0, st, a, lc.chunks);
         return hipGetLastError();
     }
+    if (ex.delta != nullptr) return launch_resident<T, -1>(a, lc, nb, tail, st);   // reads S (no points mode)
     if (X == nullptr) return launch_resident<T, 0>(a, lc, nb, tail, st);
     if constexpr (sizeof(T) == 4) {
         if (d == 2) return launch_resident<T, 2>(a, lc, nb, tail, st);
@@ -594,7 +609,7 @@ hipError_t launch_colsum(const T *Qpart, int64_t ldw, int nb, int n, const Level
 template <typename T>
 hipError_t launch_finalize(const T *S, int64_t lds, const LevelPtrs<T> &lv, int n, int64_t ldw, double lam, int t,
                            int32_t *labels_out, T *alpha_out, int64_t lda, T *c_out, T *phi_out, DevState *ds,
-                           hipStream_t st) {
+                           hipStream_t st, const T *delta) {
     FinArgs<T> a;
     a.S = S;
     a.lds = lds;
@@ -609,6 +624,7 @@ hipError_t launch_finalize(const T *S, int64_t lds, const LevelPtrs<T> &lv, int 
     a.lda = lda;
     a.c_out = c_out;
     a.phi_out = phi_out;
+    a.delta = delta;
     a.n = n;
     a.t = t;
     a.lam = (T)lam;
@@ -635,7 +651,7 @@ hipError_t launch_alpha_pad(T *A, int64_t rows, int n, int64_t ldw, hipStream_t 
     template hipError_t launch_colsum<T>(const T *, int64_t, int, int, const LevelPtrs<T> &, const LevelPtrs<T> *, \
                                          T *, bool, bool, int, bool, DevState *, hipStream_t);                    \
     template hipError_t launch_finalize<T>(const T *, int64_t, const LevelPtrs<T> &, int, int64_t, double, int,   \
-                                           int32_t *, T *, int64_t, T *, T *, DevState *, hipStream_t);
+                                           int32_t *, T *, int64_t, T *, T *, DevState *, hipStream_t, const T *);
 HAP_INSTANTIATE(float)
 HAP_INSTANTIATE(double)
 #undef HAP_INSTANTIATE

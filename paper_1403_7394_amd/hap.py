@@ -26,7 +26,8 @@ SCHEDULE_SEQUENTIAL, SCHEDULE_MRHAP = 0, 1
 EXPORTS = (
     "hap_version", "hap_status_string", "hap_last_error", "hap_build_similarity",
     "hap_median_offdiag", "hap_workspace_size", "hap_init", "hap_iterate", "hap_exemplars",
-    "hap_net_similarity", "hap_preference", "hap_read_messages", "hap_set_launch", "hap_set_points",
+    "hap_net_similarity", "hap_preference", "hap_read_messages", "hap_similarity_offsets", "hap_set_launch",
+    "hap_set_points",
     "hap_get_launch", "hap_profile", "hap_profile_read", "hap_destroy",
     "hap_batch_workspace_size", "hap_batch_create", "hap_batch_run", "hap_batch_set_launch",
     "hap_batch_get_launch", "hap_batch_destroy",
@@ -53,6 +54,7 @@ class hap_params(ctypes.Structure):
         ("schedule", ctypes.c_int32),
         ("pref_scalar", ctypes.POINTER(ctypes.c_double)),
         ("pref_vec", ctypes.c_void_p),
+        ("kappa", ctypes.c_double),
     ]
 
 
@@ -89,6 +91,7 @@ def _declare(lib):
         "hap_batch_set_launch": (I32, [V, I32, I32, I32]),
         "hap_batch_get_launch": (I32, [V, _c_i32p, _c_i32p, _c_i32p]),
         "hap_batch_destroy": (I32, [V]),
+        "hap_similarity_offsets": (I32, [V, I32, V]),
         "hap_warm_features": (I32, [V, V, I64]),
         "hap_warm_targets": (I32, [V, V, I64]),
         "hap_set_warm_start": (I32, [V, V, I64]),
@@ -188,7 +191,7 @@ class Hap:
     """One HAP problem on the GPU (wraps a hap_ctx).  S must outlive this object."""
 
     def __init__(self, S, levels: int, damping: float, pref=None, workspace=None, stream=None,
-                 schedule: int = SCHEDULE_SEQUENTIAL):
+                 schedule: int = SCHEDULE_SEQUENTIAL, kappa: float = 0.0):
         import torch
         lib = load()
         self._lib = lib
@@ -202,7 +205,9 @@ class Hap:
         p.levels = levels
         p.damping = float(damping)
         p.schedule = int(schedule)
+        p.kappa = float(kappa)
         self.schedule = int(schedule)
+        self.kappa = float(kappa)
         self._eager = False
         self._pref_keep = None
         if pref is None:
@@ -292,6 +297,13 @@ class Hap:
         P = lambda t: ctypes.c_void_p(t.data_ptr())
         _check("hap_read_messages", self._lib.hap_read_messages(self._ctx, level, P(rho), P(alpha), self.n, P(c), P(phi), P(tau)))
         return dict(rho=rho, alpha=alpha, c=c, phi=phi, tau=tau)
+
+    def offsets(self, level: int):
+        """Eq. 2.7 row offsets delta^l (n) of `level` after the last sweep (0 when kappa = 0)."""
+        import torch
+        d = torch.empty(self.n, dtype=self.dtype, device=self.S.device)
+        _check("hap_similarity_offsets", self._lib.hap_similarity_offsets(self._ctx, level, ctypes.c_void_p(d.data_ptr())))
+        return d
 
     def set_launch(self, threads=0, chunks=0, rows_per_block=0, streaming=None, eager=None):
         """Launch shape; streaming / eager None keep the current choice (both set together)."""

@@ -77,6 +77,13 @@ def test_init_rejects_bad_arguments_without_touching_the_device(lib):
     assert lib.hap_init(ctypes.byref(ctx), fake, 10, 12, hap.HAP_F32, ctypes.byref(p), None, 0, None) == hap.HAP_E_ARG
     assert b"non-finite" in lib.hap_last_error()
     p.pref_mode = hap.PREF_MEDIAN
+    # Eq. 2.7 weight: in [0, 1], and only with the level-sequential schedule
+    for kappa, schedule in [(1.5, hap.SCHEDULE_SEQUENTIAL), (-0.25, hap.SCHEDULE_SEQUENTIAL),
+                            (float("nan"), hap.SCHEDULE_SEQUENTIAL), (0.5, hap.SCHEDULE_MRHAP)]:
+        p.kappa, p.schedule = kappa, schedule
+        assert lib.hap_init(ctypes.byref(ctx), fake, 10, 12, hap.HAP_F32, ctypes.byref(p), None, 0, None) == hap.HAP_E_ARG
+        assert b"kappa" in lib.hap_last_error()
+    p.kappa, p.schedule = 0.0, hap.SCHEDULE_SEQUENTIAL
     p.struct_size = 8
     assert lib.hap_init(ctypes.byref(ctx), fake, 10, 12, hap.HAP_F32, ctypes.byref(p), None, 0, None) == hap.HAP_E_ARG
     assert not ctx.value
@@ -86,6 +93,7 @@ def test_null_context_calls_fail_cleanly(lib):
     out = ctypes.c_int32()
     assert lib.hap_iterate(None, 1, 0, ctypes.byref(out), None) == hap.HAP_E_ARG
     assert lib.hap_exemplars(None, 0, None, None) == hap.HAP_E_ARG
+    assert lib.hap_similarity_offsets(None, 0, None) == hap.HAP_E_ARG
     assert lib.hap_destroy(None) == hap.HAP_OK
     d = ctypes.c_double()
     assert lib.hap_net_similarity(None, 0, None, 0, 0, 0, ctypes.byref(d)) == hap.HAP_E_ARG

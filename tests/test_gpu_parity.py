@@ -409,6 +409,38 @@ def test_resume_and_determinism(hap_gpu):
         h.close()
 
 
+@pytest.mark.parametrize("schedule", ["sequential", "mrhap"])
+def test_state_after_an_early_stop_and_continuing(hap_gpu, schedule):
+    """After a stop the state is that of iteration stop + 1 (the row pass that detected the
+    stop ran one more iteration), for every level, and later sweeps of the same launch chunk
+    leave it untouched; continuing from there follows the oracle's trajectory."""
+    b, rp = synth.workload_small_f64()
+    S = sim.add_noise(sim.similarity(b.X), rp.noise_rel, rp.noise_seed)
+    p = sim.median_offdiag(S)
+    L, lam, K = 3, 0.9, 15
+    r = hap_ref.hap(S, p, L, lam, 400, stable_iters=K, schedule=schedule)
+    assert r.converged and r.iters % 16 != 15     # the stop falls inside a chunk of sweeps
+    sched = hap_gpu.SCHEDULE_MRHAP if schedule == "mrhap" else hap_gpu.SCHEDULE_SEQUENTIAL
+    h = hap_gpu.Hap(to_device(S), L, lam, schedule=sched)
+    h.set_launch(0, 0, 1)
+    res = h.iterate(400, K)
+    assert res.converged and res.iters == r.iters
+    assert np.array_equal(h.labels().cpu().numpy(), r.labels)
+    for extra, total in ((0, r.iters + 1), (9, r.iters + 10)):
+        if extra:
+            h.iterate(extra)
+        rn = hap_ref.hap(S, p, L, lam, total, schedule=schedule)
+        for l in range(L):
+            m = h.messages(l)
+            for k, ref in (("rho", rn.state.rho[l]), ("alpha", rn.state.alpha[l])):
+                assert np.array_equal(m[k].cpu().numpy(), ref), (extra, k, l)
+            if l > 0:
+                assert np.array_equal(m["tau"].cpu().numpy(), rn.state.tau[l]), (extra, "tau", l)
+        if extra:
+            assert np.array_equal(h.labels().cpu().numpy(), rn.labels)
+    h.close()
+
+
 def test_full_size_plain_f32_first_sweeps(hap_gpu):
     """8192 points, 64 blobs (the FP32 roofline workload): three sweeps against the oracle."""
     b, rp = synth.workload_plain_f32()
