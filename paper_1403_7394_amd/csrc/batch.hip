@@ -163,6 +163,7 @@ __device__ __forceinline__ void sweep_rows_grouped(const SweepArgs<float> &a, co
     const bool has_tau = a.tau != nullptr;
     const int base = ltid * VW;
     const int steps = (row1 - row0 + G - 1) / G;
+    int chg = 0;   // a label of this group's rows changed (the group's thread 0)
     float4v xs[NCH], xr[NCH], xa[NCH];
     for (int k = 0; k < steps; ++k) {
         const int buf = k & 1;
@@ -263,7 +264,7 @@ __device__ __forceinline__ void sweep_rows_grouped(const SweepArgs<float> &a, co
                     if (a.phi_down) a.phi_down[i] = m1;
                     const int old = a.E[i];
                     a.E[i] = ck;
-                    if (t >= 3 && old != ck) atomicOr(&a.ds->changed, 1);
+                    chg |= (t >= 3 && old != ck) ? 1 : 0;
                 }
             }
             // phase 2: rho^t and this row's column-sum contribution
@@ -291,6 +292,7 @@ __device__ __forceinline__ void sweep_rows_grouped(const SweepArgs<float> &a, co
             }
         }
     }
+    if (chg) atomicOr(&a.ds->changed, 1);
     __syncthreads();
     // the last step's rows of groups 1..G-1
     if (grp == 0 && steps > 0) {

@@ -181,6 +181,7 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, c
 
     RowRegs<T, NT, NCH> x;
     int buf = 0;
+    int chg = 0;   // a label of this workgroup's rows changed (thread 0; one atomic per workgroup)
     for (int i = row0; i < row1; ++i, buf ^= 1) {
         load_row<T, NT, NCH, TAIL, D>(a, i, x, cp);
         T *Rrow = a.R + (int64_t)i * ldw;
@@ -251,7 +252,7 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, c
                 if (a.phi_down) a.phi_down[i] = m1;
                 const int old = a.E[i];
                 a.E[i] = ck;
-                if (t >= 3 && old != ck) atomicOr(&a.ds->changed, 1);
+                chg |= (t >= 3 && old != ck) ? 1 : 0;
             }
         } else {
             if (a.mrhap && tid == 0 && a.phi_down) a.phi_down[i] = m1;
@@ -279,6 +280,7 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, c
             if (!TAIL || j0 < n) __builtin_nontemporal_store(out, (V *)(Rrow + j0));
         }
     }
+    if (chg) atomicOr(&a.ds->changed, 1);
 }
 
 }  // namespace hap

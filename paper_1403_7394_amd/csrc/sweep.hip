@@ -30,14 +30,8 @@
 
 namespace hap {
 
-// Waves per SIMD the register allocation must allow: the FP32 512-thread row pass reading S
-// fits in 128 registers without spilling, which lets two workgroups share a CU (two rows in
-// flight per CU instead of one).
-template <typename T, int NT, int D>
-constexpr int sweep_min_waves() { return (sizeof(T) == 4 && NT == 512 && D == 0) ? 4 : 1; }
-
 template <typename T, int NT, int NCH, bool TAIL, int D>
-__global__ __launch_bounds__(NT, (sweep_min_waves<T, NT, D>())) void sweep_kernel(SweepArgs<T> a) {
+__global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
 #pragma clang fp contract(off)
     using V = typename Vec<T>::type;
     constexpr int VW = Vec<T>::N;
@@ -133,6 +127,7 @@ __device__ __forceinline__ void stream_rows(const SweepArgs<T> &a, const int t, 
     const int voff = tid * 16;
     const __amdgpu_buffer_rsrc_t rB = row_rsrc(a.B, ldw * (int64_t)sizeof(T));
     int buf = 0;
+    int chg = 0;   // a label of this workgroup's rows changed (thread 0; one atomic per workgroup)
     for (int i = row0; i < row1; ++i, buf ^= 1) {
         const __amdgpu_buffer_rsrc_t rS = row_rsrc(a.S + (int64_t)i * a.lds, a.lds * (int64_t)sizeof(T));
         const __amdgpu_buffer_rsrc_t rR = row_rsrc(a.R + (int64_t)i * ldw, ldw * (int64_t)sizeof(T));
@@ -207,7 +202,7 @@ __device__ __forceinline__ void stream_rows(const SweepArgs<T> &a, const int t, 
                 if (a.phi_down) a.phi_down[i] = m1;
                 const int old = a.E[i];
                 a.E[i] = ck;
-                if (t >= 3 && old != ck) atomicOr(&a.ds->changed, 1);
+                chg |= (t >= 3 && old != ck) ? 1 : 0;
             }
         } else {
             if (a.mrhap && tid == 0 && a.phi_down) a.phi_down[i] = m1;
@@ -241,6 +236,7 @@ __device__ __forceinline__ void stream_rows(const SweepArgs<T> &a, const int t, 
                 buf_store<V, 0>(q, rQ, voff, c * CB);
         }
     }
+    if (chg) atomicOr(&a.ds->changed, 1);
 }
 
 template <typename T, int NT, bool TAIL>
