@@ -169,7 +169,9 @@ HAP_API hap_status hap_init(hap_ctx **out, const void *S, int64_t n, int64_t lds
  * persist across calls, so a run can be continued.  iters_done (host, may be
  * NULL) receives the total iterations completed (the stop iteration after an
  * early stop); converged (host, may be NULL) is 1 when the stable count reached
- * K.  Synchronises the stream.
+ * K.  The stop is detected one iteration late, so after an early stop the labels are
+ * those of the stop iteration while the messages (hap_read_messages) are those of the
+ * next one; a further call continues from there.  Synchronises the stream.
  */
 HAP_API hap_status hap_iterate(hap_ctx *ctx, int32_t max_iters, int32_t stable_iters,
                        int32_t *iters_done, int32_t *converged);
@@ -237,8 +239,9 @@ HAP_API hap_status hap_get_launch(hap_ctx *ctx, int32_t *threads, int32_t *chunk
  * with the build's arithmetic (FP64 accumulation in coordinate order, rounded once), which
  * gives the same values as reading S and saves one N^2 read per level and iteration (about
  * a fifth of the sweep's traffic).  The one-off passes (median, labels, net similarity) and
- * the streaming row pass still read S.  FP32 contexts, d = 2 or 3.  X must stay valid
- * while the context iterates.  X = NULL switches the mode off.
+ * the streaming row pass still read S, and so does every row pass of a context with
+ * kappa > 0.  FP32 contexts, d = 2 or 3.  X must stay valid while the context iterates.
+ * X = NULL switches the mode off.
  */
 HAP_API hap_status hap_set_points(hap_ctx *ctx, const void *X, int64_t d, int64_t ldx, int32_t x_dtype);
 
