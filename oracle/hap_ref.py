@@ -111,9 +111,11 @@ def responsibility(s: np.ndarray, alpha: np.ndarray, tau: np.ndarray | None) -> 
     """Undamped Eq. 2.1 for one level: s_ij + min(tau_i, -max_{k!=j}(alpha_ik + s_ik)).
 
     tau=None is the l = 1 case (tau = +inf), giving s_ij - max_{k!=j}(...).
+    s may also be a block of whole rows (r x N, each row's own diagonal entry holding its
+    preference); tau then has r entries.
     """
-    N = s.shape[0]
-    rows = np.arange(N)
+    N = s.shape[1]
+    rows = np.arange(s.shape[0])
     v = alpha + s
     k1 = np.argmax(v, axis=1)                 # first maximum (lowest index)
     M1 = v[rows, k1]

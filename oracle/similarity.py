@@ -61,6 +61,18 @@ def similarity(X: np.ndarray, squared: bool = True) -> np.ndarray:
     return -S if squared else -np.sqrt(S)
 
 
+def similarity_rows(X: np.ndarray, rows, squared: bool = True) -> np.ndarray:
+    """Rows `rows` of similarity(X), with the same arithmetic (FP64, coordinates in order),
+    for problems too large to hold the whole matrix."""
+    X = np.asarray(X, dtype=np.float64)
+    rows = np.asarray(rows)
+    S = np.zeros((rows.size, X.shape[0]))
+    for k in range(X.shape[1]):
+        diff = X[rows, k][:, None] - X[:, k][None, :]
+        S = S + diff * diff
+    return -S if squared else -np.sqrt(S)
+
+
 def add_noise(S: np.ndarray, rel: float, seed: int) -> np.ndarray:
     """Off-diagonal tie-break noise: s_ij + (rel * |s_ij|) * u_ij (FP64)."""
     S = np.array(S, dtype=np.float64, copy=True)

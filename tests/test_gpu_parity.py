@@ -478,3 +478,45 @@ def test_full_size_plain_f32_invariants(hap_gpu):
         assert torch.equal(m["rho"], hs[1].messages(l)["rho"])
     for h in hs:
         h.close()
+
+
+@pytest.mark.parametrize("dtype,n", [(np.float32, 65536), (np.float64, 32768)])
+def test_maximum_size_on_sampled_rows(hap_gpu, dtype, n):
+    """The largest supported problem (65536 points in FP32, 32768 in FP64; the streaming row
+    pass with 16 chunks): the build and the first sweep's responsibilities on sampled rows
+    are bit-identical to the oracle's rows (ρ^1 needs no column sums, so each sampled row
+    is computed alone); four more sweeps keep the off-diagonal availabilities of those rows
+    non-positive and the labels in range."""
+    b, _ = synth.workload_plain_f32(n=n)
+    Xh = b.X.astype(dtype)
+    tdt = torch.float32 if dtype == np.float32 else torch.float64
+    X = torch.from_numpy(Xh).to(DEV)
+    S = torch.empty((n, n), dtype=tdt, device=DEV)
+    hap_gpu.build_similarity(X, S)
+    rows = np.array([0, 1, 4095, 4096, n // 2 - 1, n // 2 + 7, n - 2, n - 1])
+    s_rows = sim.similarity_rows(Xh, rows).astype(dtype)
+    assert np.array_equal(S[torch.from_numpy(rows).to(DEV)].cpu().numpy(), s_rows)
+    p = dtype(np.median(s_rows[:, :4096]))
+    lam = 0.5
+    h = hap_gpu.Hap(S, 1, lam, pref=float(p))
+    assert h.get_launch()[3]                # long rows: the streaming row pass
+    h.iterate(1)
+    m = h.messages(0)
+    rho = m["rho"][torch.from_numpy(rows).to(DEV)].cpu().numpy()
+    del m
+    s_lvl = s_rows.copy()
+    s_lvl[np.arange(rows.size), rows] = p
+    rhat = hap_ref.responsibility(s_lvl, np.zeros_like(s_lvl), None)
+    want = dtype(lam) * np.zeros_like(s_lvl) + dtype(1.0 - lam) * rhat
+    assert np.array_equal(rho, want)
+    h.iterate(4)
+    m = h.messages(0)
+    a = m["alpha"][torch.from_numpy(rows).to(DEV)].cpu().numpy()
+    del m
+    a[np.arange(rows.size), rows] = -1.0
+    assert np.all(a <= 0.0)
+    lab, k = h.exemplars(0)
+    assert int(lab.min()) >= 0 and int(lab.max()) < n and 1 <= k <= n
+    h.close()
+    del S
+    torch.cuda.empty_cache()

@@ -277,6 +277,26 @@ def test_similarity_matches_scipy_sqeuclidean():
     assert np.all(np.diag(S) == 0)
 
 
+def test_row_blocks_match_the_full_matrix():
+    """similarity_rows and a row block of responsibility give the rows of the full-matrix
+    results (the blocks serve sampled checks of problems too large for the oracle)."""
+    b = synth.small_blobs(102, 60, d=3, k=4)
+    rows = np.array([0, 7, 31, 59])
+    ref = -cdist(b.X[rows], b.X, "sqeuclidean")
+    blk = sim.similarity_rows(b.X, rows)
+    assert np.max(np.abs(blk - ref)) <= 1e-12 * np.abs(ref).max()
+    assert np.array_equal(blk, sim.similarity(b.X)[rows])
+    assert np.array_equal(sim.similarity_rows(b.X, rows, squared=False), sim.similarity(b.X, squared=False)[rows])
+    S = sim.similarity(b.X)
+    np.fill_diagonal(S, -5.0)
+    A = np.minimum(0.0, np.random.default_rng(3).standard_normal((60, 60)))
+    tau = np.random.default_rng(4).standard_normal(60)
+    for t in (None, tau):
+        full = hap_ref.responsibility(S, A, t)
+        part = hap_ref.responsibility(S[rows], A[rows], None if t is None else t[rows])
+        assert np.array_equal(part, full[rows])
+
+
 def test_splitmix64_published_outputs():
     gamma = 0x9E3779B97F4A7C15
     with open(os.path.join(GOLDEN, "splitmix64.txt")) as f:
