@@ -136,3 +136,28 @@ def test_warm_calls_reject_a_null_context(lib):
     assert lib.hap_warm_targets(None, fake, 3) == hap.HAP_E_ARG
     assert lib.hap_set_warm_start(None, None, 0) == hap.HAP_E_ARG
     assert lib.hap_iterate_warm(None, None, 0, 10, 5, None, None, None) == hap.HAP_E_ARG
+
+
+def test_batch_planning_checks_arguments(lib):
+    b = ctypes.c_size_t()
+    sizes = (ctypes.c_int32 * 3)(100, 2048, 2)
+    assert lib.hap_batch_workspace_size(3, sizes, 16, 3, ctypes.byref(b)) == hap.HAP_OK
+    # per problem: S, then R and A per level (n x ld floats each), plus vectors
+    need = sum(n * ((n + 63) // 64 * 64) * 4 * (1 + 2 * 3) for n in (100, 2048, 2))
+    assert need <= b.value < need * 1.1
+    assert lib.hap_batch_workspace_size(3, sizes, 16, 3, None) == hap.HAP_E_ARG
+    assert lib.hap_batch_workspace_size(0, sizes, 16, 3, ctypes.byref(b)) == hap.HAP_E_ARG
+    assert lib.hap_batch_workspace_size(3, None, 16, 3, ctypes.byref(b)) == hap.HAP_E_ARG
+    assert lib.hap_batch_workspace_size(3, sizes, 33, 3, ctypes.byref(b)) == hap.HAP_E_ARG
+    assert lib.hap_batch_workspace_size(3, sizes, 16, 0, ctypes.byref(b)) == hap.HAP_E_ARG
+    for bad in (1, 2049):
+        one = (ctypes.c_int32 * 1)(bad)
+        assert lib.hap_batch_workspace_size(1, one, 16, 3, ctypes.byref(b)) == hap.HAP_E_ARG
+        assert b"2048" in lib.hap_last_error()
+    out = ctypes.c_void_p()
+    fake = ctypes.c_void_p(4096 + 1)     # misaligned: rejected before any device call
+    assert lib.hap_batch_create(ctypes.byref(out), 3, sizes, 16, 3, fake, 1 << 40, None) == hap.HAP_E_ARG
+    assert lib.hap_batch_create(None, 3, sizes, 16, 3, None, 0, None) == hap.HAP_E_ARG
+    assert not out.value
+    assert lib.hap_batch_set_launch(None, 512, 1, 4) == hap.HAP_E_ARG
+    assert lib.hap_batch_destroy(None) == hap.HAP_OK
