@@ -2,9 +2,14 @@
 
     python paper_1403_7394_amd/profile_run.py [--sweeps K] [--copy-gib G] [--n N]
     python paper_1403_7394_amd/profile_run.py --builds
+    python paper_1403_7394_amd/profile_run.py --batch [--iters T] [--copy-gib G]
 
 --builds: the similarity of the 32768-point, 64-dimensional workload built once in each
 mode (direct, FP32 GEMM, BF16, BF16x3 on the matrix cores), nothing else.
+
+--batch: the batched workload (512 problems, N ~ U{64..2048}, d = 16, L = 3, damping 0.8)
+run once for T iterations (default 200) in the launch shape (1024 threads, 512 workgroups,
+4 row groups), after the calibration copy.
 
 Builds the FP32 similarity of the 8192-point, 64-blob 2-D workload on the GPU, runs K full
 sweeps (all three levels, damping 0.9, no stop rule; the row pass in points mode unless
@@ -30,6 +35,8 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--read-s", action="store_true", help="row pass reads S (default: points mode)")
     ap.add_argument("--builds", action="store_true", help="profile the similarity builds instead")
+    ap.add_argument("--batch", action="store_true", help="profile the batched form instead")
+    ap.add_argument("--iters", type=int, default=200, help="--batch: iterations")
     args = ap.parse_args()
 
     import torch
@@ -60,6 +67,21 @@ def main() -> int:
         torch.cuda.synchronize()
         print(f"copy: {words * 4} bytes read, {words * 4} bytes written", flush=True)
         del src, dst
+    if args.batch:
+        import numpy as np
+        problems, rp = synth.workload_batched()
+        sizes = [b.X.shape[0] for b in problems]
+        X = torch.from_numpy(np.concatenate([b.X for b in problems])).to(dev)
+        bt = hap.HapBatch(sizes, problems[0].X.shape[1], rp.levels)
+        bt.set_launch(1024, 512, 4)
+        out = bt.outputs(dev)
+        torch.cuda.synchronize()
+        print(f"batch ready: {len(sizes)} problems, sum n^2 = {sum(k * k for k in sizes)}", flush=True)
+        bt.run(X, rp.damping, args.iters, out=out)
+        torch.cuda.synchronize()
+        print(f"batch done: {args.iters} iterations", flush=True)
+        bt.close()
+        return 0
     blobs, rp = synth.workload_plain_f32(n=args.n)
     n = blobs.X.shape[0]
     X = torch.from_numpy(blobs.X).to(dev)
