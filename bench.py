@@ -231,12 +231,13 @@ def run_warm_form(args, torch, hap, synth) -> dict:
     n_eval = blobs.X.shape[0]
     iters = args.form_iters if args.form_iters else rp.max_iters
     K = rp.stable_iters
+    kappa = args.kappa
     out = {"form": "warm", "workload": f"{n_eval} points, d=32, 1024 blobs, FP32, damping {rp.damping}, "
            f"up to {iters} iterations or {K} stable; network trained on 25 runs of 8192 2-D points",
-           "levels": {}}
+           "kappa": kappa, "levels": {}}
     n_tr = 8192
     S_tr = torch.empty((n_tr, n_tr), dtype=torch.float32, device=dev)
-    for L in (3, 1):
+    for L in [int(v) for v in args.warm_levels.split(",")]:
         t0 = time.perf_counter()
         ws = torch.empty(hap.workspace_size(n_tr, L, hap.HAP_F32), dtype=torch.uint8, device=dev)
         Fs, Ts, conv_tr = [], [], 0
@@ -244,7 +245,7 @@ def run_warm_form(args, torch, hap, synth) -> dict:
             for rep in range(5):
                 b = synth.workload_warm_train(k, rep, n=n_tr)
                 hap.build_similarity(torch.from_numpy(b.X).to(dev), S_tr)
-                h = hap.Hap(S_tr, L, rp.damping, workspace=ws)
+                h = hap.Hap(S_tr, L, rp.damping, workspace=ws, kappa=kappa if L > 1 else 0.0)
                 res = h.iterate(iters, K)
                 conv_tr += int(res.converged)
                 Fs.append(h.warm_features())
@@ -278,7 +279,7 @@ def run_warm_form(args, torch, hap, synth) -> dict:
         def run(warm: bool):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            h = hap.Hap(S, L, rp.damping, workspace=ws)
+            h = hap.Hap(S, L, rp.damping, workspace=ws, kappa=kappa if L > 1 else 0.0)
             fell, t_pred = False, 0.0
             if warm:
                 Y = m.forward(h.warm_features())
@@ -327,7 +328,7 @@ def run_warm_form(args, torch, hap, synth) -> dict:
             hap.build_similarity(torch.from_numpy(b.X).to(dev), S_tr)
             rows = {}
             for warm in (False, True):
-                h = hap.Hap(S_tr, L, rp.damping, workspace=ws_h)
+                h = hap.Hap(S_tr, L, rp.damping, workspace=ws_h, kappa=kappa if L > 1 else 0.0)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 if warm:
@@ -417,8 +418,9 @@ def main() -> int:
     ap.add_argument("--schedule", choices=["sequential", "mrhap"], default="sequential",
                     help="plain form: Algorithm 1's level-sequential schedule or the MapReduce one (Section 3)")
     ap.add_argument("--kappa", type=float, default=0.0,
-                    help="plain form: weight of the optional level-wise similarity update (Eq. 2.7); "
+                    help="plain and warm forms: weight of the optional level-wise similarity update (Eq. 2.7); "
                          "> 0 makes the row pass read S")
+    ap.add_argument("--warm-levels", default="3,1", help="warm form: the level counts to train and evaluate")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
