@@ -141,3 +141,29 @@ def test_batch_graph_capture_replays(hap_gpu):
             assert torch.equal(a, b_)
         assert torch.isfinite(junk)
     bt.close()
+
+
+def test_full_size_batch_on_sampled_problems(hap_gpu):
+    """The batched workload at its full size (512 problems, N ~ U{64..2048}, d = 16, L = 3,
+    damping 0.8) in the launch shape the benchmark's autotuner picked (1024
+    threads, 512 workgroups, 4 row groups), 8 iterations: the smallest, a middle and the
+    largest problem are bit-identical to the FP32 oracle (labels, and net similarity to
+    1e-12); every problem reports 8 iterations and valid labels."""
+    problems, rp = synth.workload_batched()
+    sizes = [b.X.shape[0] for b in problems]
+    X = torch.from_numpy(np.concatenate([b.X for b in problems])).to(DEV)
+    bt = hap_gpu.HapBatch(sizes, 16, rp.levels)
+    bt.set_launch(1024, 512, 4)
+    T = 8
+    labels, ns, iters = bt.run(X, rp.damping, T)
+    torch.cuda.synchronize()
+    assert bool(torch.all(iters == T))
+    order = np.argsort(sizes, kind="stable")
+    for b in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        lab = bt.labels_of(labels, b).cpu().numpy()
+        assert lab.min() >= 0 and lab.max() < sizes[b]
+        r, ns_ref = _oracle(problems[b].X, rp.levels, rp.damping, T)
+        assert np.array_equal(lab, r.labels), (b, sizes[b])
+        for l in range(rp.levels):
+            assert abs(ns[b, l].item() - ns_ref[l]) <= 1e-12 * abs(ns_ref[l]), (b, l)
+    bt.close()

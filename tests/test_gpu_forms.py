@@ -87,3 +87,38 @@ def test_gemm_build_f64_with_noise_within_bound(hap_gpu):
     rel = np.abs(S1.cpu().numpy() - S0.cpu().numpy()) / np.maximum(np.abs(ref), 1e-300)
     off = ~np.eye(200, dtype=bool)
     assert 0.3e-6 < np.median(rel[off]) < 0.7e-6
+
+
+def test_full_size_builds_on_sampled_rows(hap_gpu):
+    """The precision workload at its full size (32768 points, d = 64): every build mode, on
+    sampled rows against the FP64 oracle's rows, within the bounds above; the whole matrix
+    has a zero diagonal and no positive entry."""
+    b, _ = synth.workload_precision()
+    n, d = b.X.shape
+    X64 = b.X.astype(np.float64)
+    X = torch.from_numpy(b.X).to(DEV)
+    rows = np.array([0, 1, 127, 128, 4095, 16384, 32766, 32767])
+    ref = sim.similarity_rows(X64, rows)
+    nrm = np.sum(X64 * X64, axis=1)
+    norm_sum = nrm[rows][:, None] + nrm[None, :]
+    xn = np.sqrt(nrm)
+    xs = xn[rows][:, None] + xn[None, :]
+    dist = np.sqrt(-ref)
+    S = torch.empty((n, n), dtype=torch.float32, device=DEV)
+    ridx = torch.from_numpy(rows).to(DEV)
+    for mode, bound in (
+            (hap_gpu.BUILD_DIRECT, None),
+            (hap_gpu.BUILD_GEMM, (d + 4) * U32 * norm_sum),
+            (hap_gpu.BUILD_BF16, 2 * dist * 2.0 ** -8 * xs + (2.0 ** -8 * xs) ** 2 + (d + 4) * U32 * norm_sum),
+            (hap_gpu.BUILD_BF16X3, 2 * dist * 2.0 ** -16 * xs + 2.0 ** -16 * xs ** 2 * (1 + 2.0 ** -15)
+             + (3 * d + 4) * U32 * norm_sum)):
+        S.fill_(1.0)
+        hap_gpu.build_similarity(X, S, mode=mode)
+        got = S[ridx].cpu().numpy().astype(np.float64)
+        if bound is None:
+            assert np.array_equal(got, ref.astype(np.float32).astype(np.float64)), mode
+        else:
+            assert np.all(np.abs(got - ref) <= bound), mode
+        assert float(S.max()) <= 0.0 and bool(torch.all(torch.diagonal(S) == 0)), mode
+    del S
+    torch.cuda.empty_cache()
