@@ -49,6 +49,38 @@ def _top_order(row: np.ndarray, cols: np.ndarray) -> np.ndarray:
     return np.lexsort((cols, -row))
 
 
+def _point_part(row: np.ndarray, cols: np.ndarray, p_i: float):
+    """Features 0..19 of one point, its soft counts D_m (m = 0..5) and its neighbourhood,
+    from its off-diagonal similarities `row` at columns `cols`."""
+    f = np.zeros(NFEAT)
+    a = abs(p_i)
+    order = _top_order(row, cols)[:NTOP]
+    top = row[order]
+    nbrs = cols[order]
+    if top.size < NTOP:
+        top = np.concatenate([top, np.full(NTOP - top.size, top[-1])])
+    cnt = int(np.count_nonzero(row > p_i))
+    f[:NTOP] = top / a
+    f[16] = p_i / a
+    f[17] = cnt / row.size
+    f[18] = row.mean() / a
+    f[19] = np.log1p(cnt) / 10.0
+    D = np.zeros(NSCALE)
+    for m in range(NSCALE):
+        q = 2.0 ** -m
+        D[m] = np.sum(np.maximum(0.0, row - q * p_i)) / a
+    return f, D, nbrs
+
+
+def _density_contrast(D_i: np.ndarray, D_nbrs: np.ndarray) -> np.ndarray:
+    """Features 26..31: (D_m(i) - M_m(i)) / max(D_m(i), M_m(i)), M_m(i) the largest D_m over
+    the neighbourhood (0 when both are 0)."""
+    M = D_nbrs.max(axis=0)
+    top = np.maximum(D_i, M)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return np.where(top > 0, (D_i - M) / np.where(top > 0, top, 1.0), 0.0)
+
+
 def row_features(S: np.ndarray, pref) -> np.ndarray:
     """(n, 32) features of every point (see the module header); n >= 2."""
     S = np.asarray(S, dtype=np.float64)
@@ -61,29 +93,34 @@ def row_features(S: np.ndarray, pref) -> np.ndarray:
     nbrs = []
     for i in range(n):
         cols = np.delete(np.arange(n), i)
-        row = S[i, cols]
-        a = abs(p[i])
-        order = _top_order(row, cols)[:NTOP]
-        top = row[order]
-        nbrs.append(cols[order])
-        if top.size < NTOP:
-            top = np.concatenate([top, np.full(NTOP - top.size, top[-1])])
-        cnt = int(np.count_nonzero(row > p[i]))
-        F[i, :NTOP] = top / a
-        F[i, 16] = p[i] / a
-        F[i, 17] = cnt / row.size
-        F[i, 18] = row.mean() / a
-        F[i, 19] = np.log1p(cnt) / 10.0
-        for m in range(NSCALE):
-            q = 2.0 ** -m
-            D[i, m] = np.sum(np.maximum(0.0, row - q * p[i])) / a
+        F[i], D[i], nb = _point_part(S[i, cols], cols, p[i])
+        nbrs.append(nb)
     F[:, 20:26] = np.log1p(D) / 10.0
     for i in range(n):
-        M = D[nbrs[i]].max(axis=0)
-        top = np.maximum(D[i], M)
-        with np.errstate(invalid="ignore", divide="ignore"):
-            F[i, 26:32] = np.where(top > 0, (D[i] - M) / np.where(top > 0, top, 1.0), 0.0)
+        F[i, 26:32] = _density_contrast(D[i], D[nbrs[i]])
     return F
+
+
+def row_features_sampled(row_of, n: int, pref, rows) -> np.ndarray:
+    """Features of the points `rows` only, for problems too large to hold S: row_of(i)
+    returns row i of S (length n, FP64).  Reads the rows of the sampled points and of their
+    neighbourhoods; the values equal the matching rows of row_features(S, pref)."""
+    p = np.broadcast_to(np.asarray(pref, dtype=np.float64), (n,))
+    parts = {}
+
+    def part(i):
+        if i not in parts:
+            cols = np.delete(np.arange(n), i)
+            parts[i] = _point_part(np.asarray(row_of(i), dtype=np.float64)[cols], cols, p[i])
+        return parts[i]
+
+    out = np.zeros((len(rows), NFEAT))
+    for k, i in enumerate(rows):
+        f, D_i, nb = part(int(i))
+        out[k] = f
+        out[k, 20:26] = np.log1p(D_i) / 10.0
+        out[k, 26:32] = _density_contrast(D_i, np.stack([part(int(j))[1] for j in nb]))
+    return out
 
 
 def g_fwd(v):

@@ -280,3 +280,25 @@ def test_end_to_end_warm_start_runs(hap_gpu):
     ex = np.unique(lab)
     assert np.array_equal(lab[ex], ex)
     h.close()
+
+
+def test_full_size_features_on_sampled_rows(hap_gpu):
+    """The warm-start evaluation workload at its full size (65536 points, d = 32, 1024 blobs,
+    FP32): features of sampled points against the oracle, which reads only the rows of those
+    points and of their neighbourhoods (a fixed scalar preference on both sides)."""
+    b, _ = synth.workload_warm_eval()
+    n = b.X.shape[0]
+    X = torch.from_numpy(b.X).to(DEV)
+    S = torch.empty((n, n), dtype=torch.float32, device=DEV)
+    hap_gpu.build_similarity(X, S)
+    rows = np.array([0, 1, 777, 32768, 50000, n - 1])
+    sample = sim.similarity_rows(b.X, rows).astype(np.float32)
+    p = float(np.median(sample[:, :8192]))
+    h = hap_gpu.Hap(S, 1, 0.9, pref=p)
+    got = h.warm_features()[torch.from_numpy(rows).to(DEV)].cpu().numpy()
+    h.close()
+    del S
+    torch.cuda.empty_cache()
+    row_of = lambda i: sim.similarity_rows(b.X, [i]).astype(np.float32)[0].astype(np.float64)
+    ref = warm.row_features_sampled(row_of, n, np.float64(np.float32(p)), rows)
+    check_features(got, ref)

@@ -191,3 +191,13 @@ def test_training_fits_a_realisable_teacher():
     idx = synth.minibatch_order(7, 512, 64, 600)
     losses, _, _ = warm.train(P, X, T, idx, 64, 600, 3e-3)
     assert losses[-20:].mean() < 0.05 * losses[:5].mean()
+
+
+def test_sampled_features_equal_full_features():
+    b = synth.small_blobs(76, 90, d=3, k=5)
+    S = sim.similarity(b.X)
+    p = sim.median_offdiag(S)
+    F = warm.row_features(S, p)
+    rows = [0, 13, 44, 89]
+    G = warm.row_features_sampled(lambda i: S[i], 90, p, rows)
+    assert np.array_equal(G, F[rows])
