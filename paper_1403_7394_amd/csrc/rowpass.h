@@ -104,52 +104,22 @@ struct RowRegs {
 // from initialisation and stay -inf or NaN, which '>' and fmax ignore.  Padding columns of
 // R, A and the column partials are never read back as results.
 //
-// D < 0: S is read and the row offset a.delta[i] of the optional level-wise similarity
-// update (Eq. 2.7) is added to it.
-//
-// D > 0 (points mode): instead of reading S, s_ij is recomputed from the D coordinates of
-// points i and j exactly as the direct similarity build computes it (squared differences
-// summed in FP64 in coordinate order, no contraction, negated, rounded once), so the values
-// equal those of an S built that way and one N^2 read per level and sweep is saved.
+// D < 0: the row offset a.delta[i] of the optional level-wise similarity update (Eq. 2.7)
+// is added to the S values read.  (D > 0, the points mode, has its own row pass below.)
 template <typename T, int NT, int NCH, bool TAIL, int D>
-__device__ __forceinline__ void load_row(const SweepArgs<T> &a, int i, RowRegs<T, NT, NCH> &x,
-                                         const ColPoints<T, NCH, D> &cp) {
-#pragma clang fp contract(off)
+__device__ __forceinline__ void load_row(const SweepArgs<T> &a, int i, RowRegs<T, NT, NCH> &x) {
     using V = typename Vec<T>::type;
     constexpr int VW = Vec<T>::N;
     const T *Srow = a.S + (int64_t)i * a.lds;
     const T *Rrow = a.R + (int64_t)i * a.ldw;
     const T *Arow = a.A + (int64_t)i * a.ldw;
-    double xi[D > 0 ? D : 1];
-    if constexpr (D > 0) {
-#pragma unroll
-        for (int k = 0; k < D; ++k) xi[k] = (double)a.X[(int64_t)i * a.ldx + k];
-    }
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         const int j0 = c * NT * VW + threadIdx.x * VW;
         if (!TAIL || j0 < a.n) {
-            if constexpr (D <= 0) {
-                // S streams through once per level: non-temporal, so it does not displace R/A lines
-                x.s[c] = __builtin_nontemporal_load((const V *)(Srow + j0));
-                if constexpr (D < 0) x.s[c] = x.s[c] + a.delta[i];   // Eq. 2.7 row offset
-            } else {
-#pragma unroll
-                for (int v = 0; v < VW; ++v) {
-                    double acc = 0.0;
-#pragma unroll
-                    for (int k = 0; k < D; ++k) {
-                        // opaque per row, so the FP64 conversions are not hoisted out of the row
-                        // loop (that would double the registers holding the column points)
-                        T xj = cp.x[c][v][k];
-                        asm volatile("" : "+v"(xj));
-                        const double df = xi[k] - (double)xj;
-                        const double sq = df * df;
-                        acc = acc + sq;
-                    }
-                    x.s[c][v] = (T)(-acc);
-                }
-            }
+            // S streams through once per level: non-temporal, so it does not displace R/A lines
+            x.s[c] = __builtin_nontemporal_load((const V *)(Srow + j0));
+            if constexpr (D < 0) x.s[c] = x.s[c] + a.delta[i];   // Eq. 2.7 row offset
             x.r[c] = *(const V *)(Rrow + j0);
             x.a[c] = *(const V *)(Arow + j0);
         } else {
@@ -167,8 +137,7 @@ template <typename T, int NT, int NCH, bool FIRST, bool TAIL, int D = 0>
 __device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, const int row0, const int row1,
                                            const typename Vec<T>::type (&Bv)[NCH], typename Vec<T>::type (&qv)[NCH],
                                            T (*sh_m1)[NT / 64], int (*sh_k1)[NT / 64], T (*sh_m2)[NT / 64],
-                                           T (*sh_cv)[NT / 64], int (*sh_ck)[NT / 64],
-                                           const ColPoints<T, NCH, D> &cp = ColPoints<T, NCH, D>{}) {
+                                           T (*sh_cv)[NT / 64], int (*sh_ck)[NT / 64]) {
 #pragma clang fp contract(off)
     using V = typename Vec<T>::type;
     constexpr int VW = Vec<T>::N;
@@ -183,7 +152,7 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, c
     int buf = 0;
     int chg = 0;   // a label of this workgroup's rows changed (thread 0; one atomic per workgroup)
     for (int i = row0; i < row1; ++i, buf ^= 1) {
-        load_row<T, NT, NCH, TAIL, D>(a, i, x, cp);
+        load_row<T, NT, NCH, TAIL, D>(a, i, x);
         T *Rrow = a.R + (int64_t)i * ldw;
         T *Arow = a.A + (int64_t)i * ldw;
         const T p_i = a.pref[i];
@@ -263,6 +232,231 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, c
         const int k1r = k1 - base;
         T tau_i = zero;
         const bool has_tau = row_tau(a, i, t, tau_i);
+        if (a.tau_store && tid == 0) a.tau_store[i] = has_tau ? tau_i : pos_inf<T>();
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int j0 = c * NT * VW + base;
+            V out;
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                const int j = c * NT * VW + v;
+                const T m = (j == k1r) ? m2 : m1;
+                const T rh = has_tau ? x.s[c][v] + fmin(tau_i, -m) : x.s[c][v] - m;
+                const T rn = lam * x.r[c][v] + oml * rh;
+                out[v] = rn;
+                qv[c][v] += (dcol == j) ? rn : fmax(zero, rn);
+            }
+            if (!TAIL || j0 < n) __builtin_nontemporal_store(out, (V *)(Rrow + j0));
+        }
+    }
+    if (chg) atomicOr(&a.ds->changed, 1);
+}
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// Points mode with the rho and alpha rows prefetched one row ahead into LDS by DMA
+// (global_load_lds, 16 bytes per lane; lane l of a wave writes 16 bytes at the wave's LDS
+// base + 16 l, so each thread later reads back exactly the 16 bytes its lane fetched).  The
+// per-row scalars (preference, coordinates of point i, tau_i, the previous label) of up to
+// kWin rows are staged in LDS at the start of each window, so no global load sits inside a
+// row: the only wait at the top of a row is for its own prefetch, issued one row earlier.
+constexpr int kWin = 64;
+
+template <typename T, int NT, int NCH, int D>
+struct PointsLds {
+    T row[2][2][NCH][NT * Vec<T>::N];   // [buffer][rho, alpha][chunk][column]
+    T p[kWin];
+    T tau[kWin];
+    T x[kWin][D > 0 ? D : 1];
+    int e[kWin];
+};
+
+template <typename T, int NT, int NCH, bool TAIL>
+__device__ __forceinline__ void prefetch_rows(const SweepArgs<T> &a, int i, T (*dst)[NCH][NT * Vec<T>::N]) {
+    constexpr int VW = Vec<T>::N;
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const T *Rrow = a.R + (int64_t)i * a.ldw;
+    const T *Arow = a.A + (int64_t)i * a.ldw;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const int j0 = c * NT * VW + tid * VW;
+        if (!TAIL || j0 < a.n) {
+            __builtin_amdgcn_global_load_lds((const void *)(Rrow + j0), (lds_void_t *)(&dst[0][c][wave * 64 * VW]), 16,
+                                             0, 0);
+            __builtin_amdgcn_global_load_lds((const void *)(Arow + j0), (lds_void_t *)(&dst[1][c][wave * 64 * VW]), 16,
+                                             0, 0);
+        }
+    }
+}
+
+template <typename T, int NT, int NCH, bool FIRST, bool TAIL, int D>
+__device__ __forceinline__ void sweep_rows_points(const SweepArgs<T> &a, const int t, const int row0, const int row1,
+                                                  const typename Vec<T>::type (&Bv)[NCH],
+                                                  typename Vec<T>::type (&qv)[NCH], T (*sh_m1)[NT / 64],
+                                                  int (*sh_k1)[NT / 64], T (*sh_m2)[NT / 64], T (*sh_cv)[NT / 64],
+                                                  int (*sh_ck)[NT / 64], const ColPoints<T, NCH, D> &cp,
+                                                  PointsLds<T, NT, NCH, D> &L) {
+#pragma clang fp contract(off)
+    using V = typename Vec<T>::type;
+    constexpr int VW = Vec<T>::N;
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int n = a.n;
+    const int64_t ldw = a.ldw;
+    const T lam = a.lam, oml = a.oml;
+    const T zero = T(0), ninf = neg_inf<T>();
+    const bool mr = a.tau_c != nullptr;
+    const bool has_tau = mr ? (t >= 2) : (a.tau != nullptr);
+
+    RowRegs<T, NT, NCH> x;
+    int buf = 0;
+    int chg = 0;
+    // the column coordinates were loaded before this function: take them here, so that the
+    // wait for them is not placed inside the row loop (where it would also wait for the
+    // prefetch of the next row)
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int v = 0; v < VW; ++v)
+#pragma unroll
+            for (int d = 0; d < D; ++d) asm volatile("" ::"v"(cp.x[c][v][d]));
+    if (row0 < row1) prefetch_rows<T, NT, NCH, TAIL>(a, row0, L.row[0]);
+    for (int i = row0; i < row1; ++i, buf ^= 1) {
+        const int r = (i - row0) % kWin;
+        if (r == 0) {
+            // stage the scalars of rows [i, i + kWin)
+            __syncthreads();
+            const int k = i + tid;
+            if (tid < kWin && k < row1) {
+                L.p[tid] = a.pref[k];
+                L.tau[tid] = has_tau ? (mr ? a.tau_c[k] + a.tau_q[k] : a.tau[k]) : zero;
+#pragma unroll
+                for (int d = 0; d < D; ++d) L.x[tid][d] = a.X[(int64_t)k * a.ldx + d];
+                L.e[tid] = a.E[k];
+            }
+            __syncthreads();
+        }
+        // this row's rho and alpha from the prefetch buffer, then the next row's prefetch.  The
+        // compiler does not order LDS reads after an asynchronous LDS DMA, so the wait for it
+        // is explicit (it also covers the row's earlier stores; the prefetch had the whole
+        // previous row to land), and the memory clobber keeps the reads below it.
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int j0 = c * NT * VW + tid * VW;
+            if (!TAIL || j0 < n) {
+                x.r[c] = *(const V *)(&L.row[buf][0][c][tid * VW]);
+                x.a[c] = *(const V *)(&L.row[buf][1][c][tid * VW]);
+            } else {
+                x.r[c] = (V)(zero);
+                x.a[c] = (V)(ninf);
+            }
+        }
+        if (i + 1 < row1) prefetch_rows<T, NT, NCH, TAIL>(a, i + 1, L.row[buf ^ 1]);
+        // s_ij from the coordinates, with the direct build's arithmetic
+        double xi[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) xi[d] = (double)L.x[r][d];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int j0 = c * NT * VW + tid * VW;
+            if (!TAIL || j0 < n) {
+#pragma unroll
+                for (int v = 0; v < VW; ++v) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) {
+                        T xj = cp.x[c][v][d];
+                        asm volatile("" : "+v"(xj));
+                        const double df = xi[d] - (double)xj;
+                        const double sq = df * df;
+                        acc = acc + sq;
+                    }
+                    x.s[c][v] = (T)(-acc);
+                }
+            } else {
+                x.s[c] = (V)(zero);
+            }
+        }
+        T *Rrow = a.R + (int64_t)i * ldw;
+        T *Arow = a.A + (int64_t)i * ldw;
+        const T p_i = L.p[r];
+        const int base = tid * VW;
+        int dcol = i - base;
+        T m1 = ninf, m2 = ninf, cv = ninf;
+        int k1 = INT_MAX, ck = INT_MAX;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int j0 = c * NT * VW + base;
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                const int j = c * NT * VW + v;
+                const bool diag = dcol == j;
+                const T sj = diag ? p_i : x.s[c][v];
+                x.s[c][v] = sj;
+                const T rj = x.r[c][v];
+                T al = x.a[c][v];
+                if constexpr (!FIRST) {
+                    const T Bj = Bv[c][v];
+                    const T ah = diag ? Bj - rj : fmin(zero, Bj - fmax(zero, rj));
+                    al = lam * al + oml * ah;
+                    x.a[c][v] = al;
+                    const T cx = al + rj;
+                    const bool g = cx > cv;
+                    cv = g ? cx : cv;
+                    ck = g ? j : ck;
+                }
+                const T y = al + sj;
+                const bool g1 = y > m1;
+                m2 = g1 ? m1 : fmax(m2, y);
+                k1 = g1 ? j : k1;
+                m1 = g1 ? y : m1;
+            }
+            if constexpr (!FIRST) {
+                if (!TAIL || j0 < n) __builtin_nontemporal_store(x.a[c], (V *)(Arow + j0));
+            }
+        }
+        k1 = (k1 == INT_MAX) ? INT_MAX : k1 + base;
+        ck = (ck == INT_MAX) ? INT_MAX : ck + base;
+        wave_reduce<T, !FIRST>(m1, k1, m2, cv, ck);
+        if (lane == 0) {
+            sh_m1[buf][wid] = m1;
+            sh_k1[buf][wid] = k1;
+            sh_m2[buf][wid] = m2;
+            if constexpr (!FIRST) {
+                sh_cv[buf][wid] = cv;
+                sh_ck[buf][wid] = ck;
+            }
+        }
+        // LDS exchange of the wave results: wait for this wave's LDS writes only (lgkmcnt 0; not
+        // for the global stores and the prefetch in flight, which a workgroup fence would
+        // wait for), then the barrier.  The empty asm statements keep the compiler from moving
+        // the LDS accesses across it.
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        m1 = sh_m1[buf][0];
+        k1 = sh_k1[buf][0];
+        m2 = sh_m2[buf][0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) top2_merge(m1, k1, m2, sh_m1[buf][w], sh_k1[buf][w], sh_m2[buf][w]);
+        if constexpr (!FIRST) {
+            if (tid == 0) {
+                cv = sh_cv[buf][0];
+                ck = sh_ck[buf][0];
+                for (int w = 1; w < NW; ++w) argmax_merge(cv, ck, sh_cv[buf][w], sh_ck[buf][w]);
+                a.C[i] = cv;
+                if (a.phi_down) a.phi_down[i] = m1;
+                a.E[i] = ck;
+                chg |= (t >= 3 && L.e[r] != ck) ? 1 : 0;
+            }
+        } else {
+            if (a.mrhap && tid == 0 && a.phi_down) a.phi_down[i] = m1;
+        }
+        asm volatile("" : "+v"(dcol));
+        const int k1r = k1 - base;
+        const T tau_i = L.tau[r];
         if (a.tau_store && tid == 0) a.tau_store[i] = has_tau ? tau_i : pos_inf<T>();
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {

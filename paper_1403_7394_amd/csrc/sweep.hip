@@ -69,10 +69,20 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
     }
     const int row0 = blockIdx.x * a.rb;
     const int row1 = min(n, row0 + a.rb);
-    if (first)
-        sweep_rows<T, NT, NCH, true, TAIL, D>(a, t, row0, row1, Bv, qv, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck, cp);
-    else
-        sweep_rows<T, NT, NCH, false, TAIL, D>(a, t, row0, row1, Bv, qv, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck, cp);
+    if constexpr (D > 0) {
+        __shared__ __attribute__((aligned(16))) PointsLds<T, NT, NCH, D> lds;
+        if (first)
+            sweep_rows_points<T, NT, NCH, true, TAIL, D>(a, t, row0, row1, Bv, qv, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck,
+                                                         cp, lds);
+        else
+            sweep_rows_points<T, NT, NCH, false, TAIL, D>(a, t, row0, row1, Bv, qv, sh_m1, sh_k1, sh_m2, sh_cv,
+                                                          sh_ck, cp, lds);
+    } else {
+        if (first)
+            sweep_rows<T, NT, NCH, true, TAIL, D>(a, t, row0, row1, Bv, qv, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
+        else
+            sweep_rows<T, NT, NCH, false, TAIL, D>(a, t, row0, row1, Bv, qv, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
+    }
 
     T *qrow = a.Qpart + (int64_t)blockIdx.x * ldw;
 #pragma unroll
