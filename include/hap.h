@@ -55,7 +55,7 @@ enum {
     HAP_E_OOM = 3,          /* device allocation failed */
     HAP_E_HIP = 4,          /* HIP runtime error; see hap_last_error() */
     HAP_E_STATE = 5,        /* context unusable after an earlier device error */
-    HAP_E_UNSUPPORTED = 6   /* size or mode not supported by this build */
+    HAP_E_UNSUPPORTED = 6   /* size or mode not supported by the library */
 };
 
 enum { HAP_F32 = 0, HAP_F64 = 1, HAP_BF16 = 2 };
