@@ -37,7 +37,11 @@ def _same(a, b, L):
 
 
 @pytest.mark.parametrize("n,d,launch", [(1000, 2, None), (1000, 2, (256, 1, 1)), (8192, 2, None),
-                                        (8192, 2, (1024, 2, 16)), (700, 3, None), (4096, 3, (512, 2, 8))])
+                                        (8192, 2, (1024, 2, 16)), (700, 3, None), (4096, 3, (512, 2, 8)),
+                                        # several 64-row windows of staged per-row values per workgroup
+                                        (700, 2, (256, 1, 130)), (1000, 3, (64, 4, 200)),
+                                        # tiny problems: most lanes idle
+                                        (2, 2, None), (5, 3, None), (65, 2, (64, 1, 65)), (129, 2, (64, 1, 3))])
 def test_points_mode_equals_reading_S(hap_gpu, n, d, launch):
     b = synth.small_blobs(1200 + n + d, n, d=d, k=6, dtype=np.float32)
     L, lam, T = 3, 0.9, 12
