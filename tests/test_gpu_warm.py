@@ -280,6 +280,16 @@ def test_end_to_end_warm_start_runs(hap_gpu):
     ex = np.unique(lab)
     assert np.array_equal(lab[ex], ex)
     h.close()
+    # what the network gains (or costs) against the cold start on the same problem; the cold
+    # start judges: a warm run that does not converge is replaced by the cold run's result
+    c = hap_gpu.Hap(to_device(S), 1, 0.9)
+    cres = c.iterate(300, 30)
+    clab = c.labels().cpu().numpy()[0]
+    c.close()
+    print(f"warm start: {res.iters} iterations (fell back: {fell}) against cold {cres.iters}; "
+          f"exemplar agreement {np.mean(lab == clab):.3f}")
+    if fell:
+        assert np.array_equal(lab, clab) and res.iters == cres.iters
 
 
 def test_full_size_features_on_sampled_rows(hap_gpu):
