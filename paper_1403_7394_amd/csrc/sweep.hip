@@ -102,10 +102,15 @@ template <typename V, int AUX>
 __device__ __forceinline__ V buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
     return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
 }
+// Stores take the chunk offset in the VGPR offset and a constant zero scalar offset: a store of
+// more than 64 bits reads its data registers after issue, and the compiler keeps a VALU write
+// of those registers one wait state away from the store only when the scalar offset is not a
+// register.  With an SGPR offset a write scheduled right behind the store has corrupted the
+// stored values of some lanes.
 template <typename V, int AUX>
 __device__ __forceinline__ void buf_store(V v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
     typedef unsigned int U4 __attribute__((ext_vector_type(4)));
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, v), r, voff, soff, AUX);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, v), r, voff + soff, 0, AUX);
 }
 constexpr int kNT = 2;  // cache-policy operand: non-temporal
 
@@ -119,6 +124,166 @@ constexpr int kLdsChunks = 8;
 
 template <typename T, int NT, bool FIRST, bool TAIL>
 __device__ __forceinline__ void stream_rows(const SweepArgs<T> &a, const int t, const int row0, const int row1,
+                                            const int nch, typename Vec<T>::type (*qs)[NT],
+                                            const __amdgpu_buffer_rsrc_t rQ, T (*sh_m1)[NT / 64],
+                                            int (*sh_k1)[NT / 64], T (*sh_m2)[NT / 64], T (*sh_cv)[NT / 64],
+                                            int (*sh_ck)[NT / 64]) {
+#pragma clang fp contract(off)
+    using V = typename Vec<T>::type;
+    constexpr int VW = Vec<T>::N;
+    constexpr int NW = NT / 64;
+    constexpr int CB = NT * VW * (int)sizeof(T);  // bytes per chunk
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int n = a.n;
+    const int64_t ldw = a.ldw;
+    const T lam = a.lam, oml = a.oml;
+    const T zero = T(0), ninf = neg_inf<T>();
+    const int base = tid * VW;
+    const int voff = tid * 16;
+    const __amdgpu_buffer_rsrc_t rB = row_rsrc(a.B, ldw * (int64_t)sizeof(T));
+    int buf = 0;
+    int chg = 0;   // a label of this workgroup's rows changed (thread 0; one atomic per workgroup)
+    // Software pipelining: every chunk's loads are issued one chunk ahead (and the first
+    // chunk of each phase before the preceding reduction or the previous row's last chunk),
+    // so the memory latency overlaps the arithmetic of the chunk before.
+    auto row_s = [&](int row) { return row_rsrc(a.S + (int64_t)row * a.lds, a.lds * (int64_t)sizeof(T)); };
+    auto row_w = [&](T *M, int row) { return row_rsrc(M + (int64_t)row * ldw, ldw * (int64_t)sizeof(T)); };
+    V sv = (V)(zero), rv = (V)(zero), av = (V)(zero), bv = (V)(zero);   // phase-1 operands of the next chunk
+    auto load1 = [&](__amdgpu_buffer_rsrc_t rS, __amdgpu_buffer_rsrc_t rR, __amdgpu_buffer_rsrc_t rA, int c) {
+        sv = buf_load<V, 0>(rS, voff, c * CB);
+        rv = buf_load<V, 0>(rR, voff, c * CB);
+        av = buf_load<V, 0>(rA, voff, c * CB);
+        if constexpr (!FIRST) bv = buf_load<V, 0>(rB, voff, c * CB);
+    };
+    if (row0 < row1) load1(row_s(row0), row_w(a.R, row0), row_w(a.A, row0), 0);
+    for (int i = row0; i < row1; ++i, buf ^= 1) {
+        const __amdgpu_buffer_rsrc_t rS = row_s(i);
+        const __amdgpu_buffer_rsrc_t rR = row_w(a.R, i);
+        const __amdgpu_buffer_rsrc_t rA = row_w(a.A, i);
+        const T p_i = a.pref[i];
+        const int dcol = i - base;
+        const bool has_d = a.delta != nullptr;
+        const T d_i = has_d ? a.delta[i] : zero;
+        T m1 = ninf, m2 = ninf, cv = ninf;
+        int k1 = INT_MAX, ck = INT_MAX;   // offsets from base until the reduction
+        V s2, r2;                         // phase-2 operands of the next chunk
+        // phase 1
+        for (int c = 0; c < nch; ++c) {
+            const int off0 = c * NT * VW;   // this chunk's column offset from base
+            V sc = sv, rc = rv, ac = av;
+            const V bc = bv;
+            if (c + 1 < nch) {
+                load1(rS, rR, rA, c + 1);
+            } else {
+                s2 = buf_load<V, 0>(rS, voff, 0);
+                r2 = buf_load<V, 0>(rR, voff, 0);
+            }
+            if (has_d) sc = sc + d_i;
+            if constexpr (TAIL) {
+                // columns past n: alpha reads as -inf so they never win a maximum
+                if (off0 + base >= n) ac = (V)(ninf);
+            }
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                const int j = off0 + v;
+                const bool diag = dcol == j;
+                const T sj = diag ? p_i : sc[v];
+                const T rj = rc[v];
+                T al = ac[v];
+                if constexpr (!FIRST) {
+                    const T ah = diag ? bc[v] - rj : fmin(zero, bc[v] - fmax(zero, rj));
+                    al = lam * al + oml * ah;
+                    ac[v] = al;
+                    const T cx = al + rj;
+                    const bool gg = cx > cv;
+                    cv = gg ? cx : cv;
+                    ck = gg ? j : ck;
+                }
+                const T y = al + sj;
+                const bool g1 = y > m1;
+                m2 = g1 ? m1 : fmax(m2, y);
+                k1 = g1 ? j : k1;
+                m1 = g1 ? y : m1;
+            }
+            if constexpr (!FIRST) buf_store<V, kNT>(ac, rA, voff, c * CB);
+        }
+        k1 = (k1 == INT_MAX) ? INT_MAX : k1 + base;
+        ck = (ck == INT_MAX) ? INT_MAX : ck + base;
+        wave_reduce<T, !FIRST>(m1, k1, m2, cv, ck);
+        if (lane == 0) {
+            sh_m1[buf][wid] = m1;
+            sh_k1[buf][wid] = k1;
+            sh_m2[buf][wid] = m2;
+            if constexpr (!FIRST) {
+                sh_cv[buf][wid] = cv;
+                sh_ck[buf][wid] = ck;
+            }
+        }
+        __syncthreads();
+        m1 = sh_m1[buf][0];
+        k1 = sh_k1[buf][0];
+        m2 = sh_m2[buf][0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) top2_merge(m1, k1, m2, sh_m1[buf][w], sh_k1[buf][w], sh_m2[buf][w]);
+        if constexpr (!FIRST) {
+            if (tid == 0) {
+                cv = sh_cv[buf][0];
+                ck = sh_ck[buf][0];
+                for (int w = 1; w < NW; ++w) argmax_merge(cv, ck, sh_cv[buf][w], sh_ck[buf][w]);
+                a.C[i] = cv;
+                if (a.phi_down) a.phi_down[i] = m1;
+                const int old = a.E[i];
+                a.E[i] = ck;
+                chg |= (t >= 3 && old != ck) ? 1 : 0;
+            }
+        } else {
+            if (a.mrhap && tid == 0 && a.phi_down) a.phi_down[i] = m1;
+        }
+        // phase 2
+        const int k1r = k1 - base;
+        T tau_i = zero;
+        const bool has_tau = row_tau(a, i, t, tau_i);
+        if (a.tau_store && tid == 0) a.tau_store[i] = has_tau ? tau_i : pos_inf<T>();
+        V qn = (V)(zero);   // column partial of the next chunk when it lives in Qpart
+        for (int c = 0; c < nch; ++c) {
+            const int off0 = c * NT * VW;
+            V sc = s2;
+            const V rc = r2;
+            const V qc = qn;
+            if (c + 1 < nch) {
+                s2 = buf_load<V, 0>(rS, voff, (c + 1) * CB);
+                r2 = buf_load<V, 0>(rR, voff, (c + 1) * CB);
+                if (c + 1 >= kLdsChunks) qn = buf_load<V, 0>(rQ, voff, (c + 1) * CB);
+            } else if (i + 1 < row1) {
+                load1(row_s(i + 1), row_w(a.R, i + 1), row_w(a.A, i + 1), 0);
+            }
+            if (has_d) sc = sc + d_i;
+            V out;
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                const int j = off0 + v;
+                const T sj = (dcol == j) ? p_i : sc[v];
+                const T m = (j == k1r) ? m2 : m1;
+                const T rh = has_tau ? sj + fmin(tau_i, -m) : sj - m;
+                out[v] = lam * rc[v] + oml * rh;
+            }
+            buf_store<V, kNT>(out, rR, voff, c * CB);
+            V q = (c < kLdsChunks) ? qs[c][tid] : qc;
+#pragma unroll
+            for (int v = 0; v < VW; ++v) q[v] += (dcol == off0 + v) ? out[v] : fmax(zero, out[v]);
+            if (c < kLdsChunks)
+                qs[c][tid] = q;
+            else
+                buf_store<V, 0>(q, rQ, voff, c * CB);
+        }
+    }
+    if (chg) atomicOr(&a.ds->changed, 1);
+}
+
+// FP64: the same pass without the software pipelining, whose second set of operands would
+// not fit the 128 registers of a 1024-thread workgroup.
+template <typename T, int NT, bool FIRST, bool TAIL>
+__device__ __forceinline__ void stream_rows_unpipelined(const SweepArgs<T> &a, const int t, const int row0, const int row1,
                                             const int nch, typename Vec<T>::type (*qs)[NT],
                                             const __amdgpu_buffer_rsrc_t rQ, T (*sh_m1)[NT / 64],
                                             int (*sh_k1)[NT / 64], T (*sh_m2)[NT / 64], T (*sh_cv)[NT / 64],
@@ -271,10 +436,19 @@ __global__ __launch_bounds__(NT) void sweep_stream_kernel(SweepArgs<T> a, int nc
     }
     const int row0 = blockIdx.x * a.rb;
     const int row1 = min(a.n, row0 + a.rb);
-    if (t == 1)
-        stream_rows<T, NT, true, TAIL>(a, t, row0, row1, nch, qs, rQ, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
-    else
-        stream_rows<T, NT, false, TAIL>(a, t, row0, row1, nch, qs, rQ, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
+    if constexpr (sizeof(T) == 4) {
+        if (t == 1)
+            stream_rows<T, NT, true, TAIL>(a, t, row0, row1, nch, qs, rQ, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
+        else
+            stream_rows<T, NT, false, TAIL>(a, t, row0, row1, nch, qs, rQ, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
+    } else {
+        if (t == 1)
+            stream_rows_unpipelined<T, NT, true, TAIL>(a, t, row0, row1, nch, qs, rQ, sh_m1, sh_k1, sh_m2, sh_cv,
+                                                       sh_ck);
+        else
+            stream_rows_unpipelined<T, NT, false, TAIL>(a, t, row0, row1, nch, qs, rQ, sh_m1, sh_k1, sh_m2, sh_cv,
+                                                        sh_ck);
+    }
     for (int c = 0; c < nch && c < kLdsChunks; ++c) buf_store<V, 0>(qs[c][threadIdx.x], rQ, threadIdx.x * 16, c * CB);
 }
 
