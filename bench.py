@@ -87,7 +87,22 @@ def cpu_baseline(X, rp, sweeps: int = 2):
         "sample": f"first {sweeps} of up to {rp.max_iters} sweeps (all {rp.levels} levels) of the same "
                   f"{n}-point workload, FP64 NumPy oracle; similarity build and median not timed",
         "seconds": wall,
+        "host": _host_info(),
     }
+
+
+def _host_info() -> dict:
+    """CPU count, usable cores and CPU model of the machine the oracle ran on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_count": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
 
 
 def run_precision_form(args, torch, hap, synth) -> dict:
