@@ -94,7 +94,9 @@ hipError_t launch_finalize(const T *S, int64_t lds, const LevelPtrs<T> &lv, int 
 //                       finished on the fly from the state of level l+1 (up), with up.delta still
 //                       holding the offsets of iteration t-1; nothing in iteration 1 (phi^l = 0)
 //   launch_level_delta: delta^{l+1}_i = delta^l_i + kappa * max_{j != i}(alpha^{l,t}_ij + rho^{l,t}_ij),
-//                       alpha^{l,t} finished on the fly with B_j = (c^l_j + phi^l_j) + Q^l_j
+//                       alpha^{l,t} finished on the fly with B_j = (c^l_j + phi^l_j) + Q^l_j, which
+//                       a first small launch writes to lv.B (the value the column sums of level
+//                       l+1 store there again)
 template <typename T>
 hipError_t launch_level_phi(const T *S, int64_t lds, const LevelPtrs<T> &up, T *phi_out, int n, int64_t ldw,
                             double lam, const DevState *ds, hipStream_t st);

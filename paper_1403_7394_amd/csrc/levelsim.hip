@@ -14,7 +14,9 @@
 // has used delta^{l+1,t}.  Two row-parallel passes between the column sums of level l and the
 // row pass of level l+1 resolve this (nothing is written to R or A):
 //   level_phi_kernel    reads S, R^{l+1}, A^{l+1}, B^{l+1}: phi^l with the offsets of t-1
-//   level_delta_kernel  reads R^l, A^l and the vectors c^l, phi^l, Q^l: delta^{l+1} of t
+//   level_base_kernel   forms the availability base B^{l,t} = (c^l + phi^l) + Q^l once (the
+//                       column sums of level l+1 write the same vector again later)
+//   level_delta_kernel  reads R^l, A^l and B^l: delta^{l+1} of t
 // The row pass of level l+1 then leaves phi^l alone.  Both passes are memory-bound streams
 // (3 and 2 N^2 reads); one workgroup per row, rows independent, rows streamed non-temporally
 // with two chunks per loop trip (7.1 TB/s for the phi pass at 8192 points).
@@ -32,10 +34,11 @@ struct LevelArgs {
     const T *__restrict__ A;
     int64_t ldw;
     const T *__restrict__ pref;
-    const T *__restrict__ B;       // phi pass: B^{l+1} of iteration t-1
-    const T *__restrict__ C;       // delta pass: c^l, phi^l, Q^l
+    const T *__restrict__ B;       // phi pass: B^{l+1} of iteration t-1; delta pass: B^l of t
+    const T *__restrict__ C;       // base pass: c^l, phi^l, Q^l
     const T *__restrict__ phi;
     const T *__restrict__ Q;
+    T *B_out;                      // base pass: B^l
     const T *__restrict__ delta_in;   // phi pass: delta^{l+1}; delta pass: delta^l
     T *out;                        // phi pass: phi^l; delta pass: delta^{l+1}
     int n;
@@ -114,7 +117,7 @@ __global__ __launch_bounds__(kThreads) void level_delta_kernel(LevelArgs<T> a) {
     for (int j0 = threadIdx.x * VW; j0 < n; j0 += kThreads * VW) {
         const V rv = __builtin_nontemporal_load((const V *)(Rrow + j0));
         const V av = __builtin_nontemporal_load((const V *)(Arow + j0));
-        const V bv = (*(const V *)(a.C + j0) + *(const V *)(a.phi + j0)) + *(const V *)(a.Q + j0);
+        const V bv = *(const V *)(a.B + j0);
 #pragma unroll
         for (int v = 0; v < VW; ++v) {
             const int j = j0 + v;
@@ -126,6 +129,18 @@ __global__ __launch_bounds__(kThreads) void level_delta_kernel(LevelArgs<T> a) {
     }
     mx = block_max(mx, sh);
     if (threadIdx.x == 0) a.out[i] = a.delta_in[i] + a.kappa * mx;
+}
+
+// B^l_j = (c^l_j + phi^l_j) + Q^l_j, in the order the column-sum kernel uses.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void level_base_kernel(LevelArgs<T> a) {
+#pragma clang fp contract(off)
+    using V = typename Vec<T>::type;
+    constexpr int VW = Vec<T>::N;
+    if (a.ds->done) return;
+    const int j0 = (blockIdx.x * kThreads + threadIdx.x) * VW;
+    if (j0 < a.n)
+        *(V *)(a.B_out + j0) = (*(const V *)(a.C + j0) + *(const V *)(a.phi + j0)) + *(const V *)(a.Q + j0);
 }
 
 }  // namespace
@@ -155,12 +170,20 @@ template <typename T>
 hipError_t launch_level_delta(const LevelPtrs<T> &lv, T *delta_next, int n, int64_t ldw, double lam, double kappa,
                               const DevState *ds, hipStream_t st) {
     LevelArgs<T> a{};
-    a.R = lv.R;
-    a.A = lv.A;
-    a.ldw = ldw;
     a.C = lv.C;
     a.phi = lv.phi;
     a.Q = lv.Q;
+    a.B_out = lv.B;
+    a.n = n;
+    a.ds = ds;
+    constexpr int per_block = kThreads * Vec<T>::N;
+    hipLaunchKernelGGL((level_base_kernel<T>), dim3((n + per_block - 1) / per_block), dim3(kThreads), 0, st, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    a.R = lv.R;
+    a.A = lv.A;
+    a.ldw = ldw;
+    a.B = lv.B;
     a.delta_in = lv.delta;
     a.out = delta_next;
     a.n = n;
