@@ -180,9 +180,28 @@ def _iteration_mrhap(st: HapState, s, L: int, lam, oml, Q, record, c_zero: bool)
             record(st.t, l, st)
 
 
+def _iteration_block(st: HapState, s, L: int, lam, oml, Q, R: int, record) -> None:
+    """One level-sequential iteration that updates rows [0, R) only (see `hap`, `rows`)."""
+    for l in range(L):
+        rhat = responsibility(s[l][:R], st.alpha[l][:R], None if l == 0 else st.tau[l][:R])
+        st.rho[l][:R] = lam * st.rho[l][:R] + oml * rhat
+        Q[l] = column_sums(st.rho[l])          # rows >= R hold zeros and add nothing
+        B = (st.c[l] + st.phi[l]) + Q[l] if l < L - 1 else Q[l].copy()
+        st.alpha[l][:R] = lam * st.alpha[l][:R] + oml * availability(st.rho[l], B)[:R]
+        if l < L - 1:
+            st.tau[l + 1] = st.c[l] + Q[l]
+        if l > 0:
+            st.phi[l - 1][:R] = np.max(st.alpha[l][:R] + s[l][:R], axis=1)
+        if l < L - 1:
+            st.c[l][:R] = np.max(st.alpha[l][:R] + st.rho[l][:R], axis=1)
+        if record is not None:
+            record(st.t, l, st)
+
+
 def hap(S, pref, levels: int, damping: float, max_iters: int, stable_iters: int = 0,
         alpha0=None, state: HapState | None = None, record=None, c_zero: bool = False,
-        dtype=np.float64, schedule: str = "sequential", kappa: float = 0.0) -> HapResult:
+        dtype=np.float64, schedule: str = "sequential", kappa: float = 0.0,
+        rows: int | None = None) -> HapResult:
     """Run HAP (Algorithm 1), in FP64 unless `dtype` says otherwise.
 
     The paper fixes no precision.  dtype=np.float32 evaluates the same steps with every
@@ -202,6 +221,11 @@ def hap(S, pref, levels: int, damping: float, max_iters: int, stable_iters: int 
            iteration's state; tau and c not updated in the first iteration).
     kappa  Eq. 2.7 weight in [0, 1]; 0 (the default) keeps s^l = s at every level.  Defined
            for the level-sequential schedule only.
+    rows   one block of a run split by rows (sequential schedule, kappa = 0): only rows
+           [0, rows) are updated; the others keep their initial messages, so they add nothing
+           to the column sums and the sums hold this block's contribution alone.  Per-row
+           quantities (c, phi) of the other rows stay at their initial values; tau is formed
+           for every column as in the full run.  None updates every row.
     """
     if schedule not in ("sequential", "mrhap"):
         raise ValueError(schedule)
@@ -209,6 +233,8 @@ def hap(S, pref, levels: int, damping: float, max_iters: int, stable_iters: int 
         raise ValueError("kappa must lie in [0, 1]")
     if float(kappa) != 0.0 and schedule != "sequential":
         raise ValueError("the level-wise similarity update is defined for the level-sequential schedule")
+    if rows is not None and (schedule != "sequential" or float(kappa) != 0.0):
+        raise ValueError("a row block is defined for the level-sequential schedule without kappa")
     dt = np.dtype(dtype).type
     S = np.asarray(S, dtype=dt)
     N = S.shape[0]
@@ -222,6 +248,9 @@ def hap(S, pref, levels: int, damping: float, max_iters: int, stable_iters: int 
         p = np.repeat(p[None, :], L, axis=0)
     s = [level_similarity(S, p[l], dt) for l in range(L)]
 
+    R = N if rows is None else int(rows)
+    if not 1 <= R <= N:
+        raise ValueError("rows must lie in [1, N]")
     st = init_state(N, L, alpha0, dt) if state is None else state.copy()
     if st.delta is None:
         st.delta = np.zeros((L, N), dt)
@@ -233,7 +262,9 @@ def hap(S, pref, levels: int, damping: float, max_iters: int, stable_iters: int 
         st.t += 1
         if schedule == "mrhap":
             _iteration_mrhap(st, s, L, lam, oml, Q, record, c_zero)
-        for l in (range(L) if schedule == "sequential" else ()):
+        if rows is not None:
+            _iteration_block(st, s, L, lam, oml, Q, R, record)
+        for l in (range(L) if schedule == "sequential" and rows is None else ()):
             if use_kappa and l > 0:
                 s[l] = offset_similarity(S, p[l], st.delta[l], dt)   # s^l of this iteration (Eq. 2.7)
             # Eq. 2.1, then damp
