@@ -246,6 +246,21 @@ HAP_API hap_status hap_get_launch(hap_ctx *ctx, int32_t *threads, int32_t *chunk
 HAP_API hap_status hap_set_points(hap_ctx *ctx, const void *X, int64_t d, int64_t ldx, int32_t x_dtype);
 
 /*
+ * One block of a run split by rows (the per-node message updates of Section 3, with each
+ * device owning a block of rows).  Subsequent hap_iterate calls update rows [0, rows)
+ * only: the row passes cover those rows, and the column sums, the availability bases and
+ * tau then hold that block's contribution alone, which is what one device of a row-split
+ * run computes before a collective adds the other blocks' sums.  The other rows keep
+ * their messages (the initial ones, in a fresh context) and add nothing to the sums; their
+ * labels and messages are not meaningful while a block is set.  rows = n (the default)
+ * is the whole problem.  The launch shape (rows per workgroup) applies to the block; a
+ * shape that does not fit is rejected (HAP_E_ARG).  Needs the sequential schedule and
+ * kappa = 0 when rows < n (HAP_E_UNSUPPORTED otherwise); HAP_E_ARG unless 1 <= rows <= n.
+ */
+HAP_API hap_status hap_set_row_count(hap_ctx *ctx, int64_t rows);
+HAP_API hap_status hap_get_row_count(hap_ctx *ctx, int64_t *rows);
+
+/*
  * Per-launch timing of the sweep kernels with HIP events recorded on the
  * context's stream around the launches.  enable = k >= 1 starts collecting (and
  * clears the totals) for the launches of every k-th sweep (1: every launch), 0 stops.

@@ -390,6 +390,7 @@ __global__ __launch_bounds__(NT) void batch_kernel(BatchArgs g) {
                 a.delta = nullptr;
                 a.n = n;
                 a.rb = n;
+                a.rows = n;
                 a.lam = g.lam;
                 a.oml = g.oml;
                 a.ds = ds;

@@ -29,6 +29,7 @@ struct hap_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     int64_t n = 0, lds = 0, ldw = 0;
+    int64_t rows = 0;             // the sweeps update rows [0, rows) (hap_set_row_count; n by default)
     int L = 0;
     int schedule = HAP_SCHEDULE_SEQUENTIAL;
     int dtype = HAP_F32;
@@ -199,7 +200,7 @@ Launch default_launch(int64_t n, size_t esz) {
     return lc;
 }
 
-bool launch_fits(const Launch &lc, int64_t n, size_t esz, int nb_cap) {
+bool launch_fits(const Launch &lc, int64_t n, int64_t rows, size_t esz, int nb_cap) {
     const int64_t vw = (int64_t)(16 / esz);
     if (lc.streaming) {
         if (lc.threads != 1024) return false;
@@ -209,7 +210,7 @@ bool launch_fits(const Launch &lc, int64_t n, size_t esz, int nb_cap) {
     }
     if ((int64_t)lc.threads * lc.chunks * vw < n) return false;
     if (lc.rows_per_block < 1) return false;
-    const int64_t nb = (n + lc.rows_per_block - 1) / lc.rows_per_block;
+    const int64_t nb = (rows + lc.rows_per_block - 1) / lc.rows_per_block;
     return nb <= nb_cap;
 }
 
@@ -257,12 +258,13 @@ hipError_t prof_collect(hap_ctx *c) {
 template <typename T>
 hap_status run_sweeps(hap_ctx *c, int count, int K) {
     const int L = c->L;
-    const int nb = (int)((c->n + c->lc.rows_per_block - 1) / c->lc.rows_per_block);
+    const int nb = (int)((c->rows + c->lc.rows_per_block - 1) / c->lc.rows_per_block);
     T *Qpart[2] = {(T *)c->Qpart, (T *)c->Qpart + (size_t)c->nb_cap * c->ldw};
     hap::SweepExtra<T> ex;
     ex.X = (const T *)c->X;
     ex.ldx = c->ldx;
     ex.d = c->d;
+    ex.rows = (int)c->rows;
     const bool kappa = c->kappa != 0.0;
     auto row = [&](int l, T *qp) -> hap_status {
         LevelPtrs<T> lv = level_ptrs<T>(c, l);
@@ -502,7 +504,7 @@ hap_status hap_init(hap_ctx **out, const void *S, int64_t n, int64_t lds, int32_
     const size_t esz = dtype_size(dtype);
     Layout lo = make_layout(n, p->levels, esz);
     Launch lc = default_launch(n, esz);
-    if (lc.threads == 0 || !launch_fits(lc, n, esz, lo.nb_cap))
+    if (lc.threads == 0 || !launch_fits(lc, n, n, esz, lo.nb_cap))
         return fail_arg("hap_init: n too large (at most 65536 points in FP32, 32768 in FP64)", HAP_E_UNSUPPORTED);
     if (workspace) {
         if (workspace_bytes < lo.total) return fail_arg("hap_init: workspace too small");
@@ -518,6 +520,7 @@ hap_status hap_init(hap_ctx **out, const void *S, int64_t n, int64_t lds, int32_
         return fail_hip(e, "hap_init: hipGetDevice");
     }
     c->n = n;
+    c->rows = n;
     c->lds = lds;
     c->ldw = lo.ldw;
     c->L = p->levels;
@@ -825,10 +828,30 @@ hap_status hap_set_launch(hap_ctx *c, int32_t threads, int32_t chunks, int32_t r
     if (rows_per_block) lc.rows_per_block = rows_per_block;
     if (flags >= 0) lc.streaming = (flags & HAP_LAUNCH_STREAM) != 0;
     lc.ordered = (lc.rows_per_block == 1);
-    if (!launch_fits(lc, c->n, c->esz, c->nb_cap)) return fail_arg("hap_set_launch: shape does not fit this problem");
+    if (!launch_fits(lc, c->n, c->rows, c->esz, c->nb_cap))
+        return fail_arg("hap_set_launch: shape does not fit this problem");
     c->lc = lc;
     if (flags >= 0) c->use_graphs = (flags & HAP_LAUNCH_EAGER) == 0;
     drop_graphs(c);
+    return HAP_OK;
+}
+
+hap_status hap_set_row_count(hap_ctx *c, int64_t rows) {
+    if (!c) return fail_arg("hap_set_row_count: null context");
+    if (rows < 1 || rows > c->n) return fail_arg("hap_set_row_count: rows must lie in [1, n]");
+    if (rows < c->n && (c->schedule != HAP_SCHEDULE_SEQUENTIAL || c->kappa != 0.0))
+        return fail_arg("hap_set_row_count: a row block needs the sequential schedule without kappa",
+                        HAP_E_UNSUPPORTED);
+    if (!launch_fits(c->lc, c->n, rows, c->esz, c->nb_cap))
+        return fail_arg("hap_set_row_count: the launch shape does not fit this row count");
+    c->rows = rows;
+    drop_graphs(c);
+    return HAP_OK;
+}
+
+hap_status hap_get_row_count(hap_ctx *c, int64_t *rows) {
+    if (!c || !rows) return fail_arg("hap_get_row_count: null argument");
+    *rows = c->rows;
     return HAP_OK;
 }
 

@@ -75,6 +75,7 @@ struct SweepExtra {
     T *tau_store = nullptr;
     int mrhap = 0;
     const T *delta = nullptr;   // Eq. 2.7 row offsets of this level's similarity
+    int rows = 0;               // rows [0, rows) only (one block of a run split by rows); 0: all
 };
 template <typename T>
 hipError_t launch_sweep_level(const T *S, int64_t lds, const LevelPtrs<T> &lv, T *phi_down,

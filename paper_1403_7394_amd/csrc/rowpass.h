@@ -23,6 +23,7 @@ struct SweepArgs {
     int32_t *E;
     T *__restrict__ Qpart;
     int n;
+    int rows;      // the pass covers rows [0, rows) (n, or one block of a run split by rows)
     int rb;
     T lam, oml;
     DevState *ds;

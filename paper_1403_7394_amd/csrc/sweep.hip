@@ -68,7 +68,7 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
             }
     }
     const int row0 = blockIdx.x * a.rb;
-    const int row1 = min(n, row0 + a.rb);
+    const int row1 = min(a.rows, row0 + a.rb);
     if constexpr (D > 0) {
         __shared__ __attribute__((aligned(16))) PointsLds<T, NT, NCH, D> lds;
         if (first)
@@ -435,7 +435,7 @@ __global__ __launch_bounds__(NT) void sweep_stream_kernel(SweepArgs<T> a, int nc
             buf_store<V, 0>((V)(T(0)), rQ, threadIdx.x * 16, c * CB);
     }
     const int row0 = blockIdx.x * a.rb;
-    const int row1 = min(a.n, row0 + a.rb);
+    const int row1 = min(a.rows, row0 + a.rb);
     if constexpr (sizeof(T) == 4) {
         if (t == 1)
             stream_rows<T, NT, true, TAIL>(a, t, row0, row1, nch, qs, rQ, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
@@ -728,6 +728,7 @@ hipError_t launch_sweep_level(const T *S, int64_t lds, const LevelPtrs<T> &lv, T
     a.Qpart = Qpart;
     a.n = n;
     a.rb = lc.rows_per_block;
+    a.rows = ex.rows > 0 ? ex.rows : n;
     a.lam = (T)lam;
     a.oml = (T)(1.0 - lam);
     a.ds = ds;
@@ -738,7 +739,7 @@ hipError_t launch_sweep_level(const T *S, int64_t lds, const LevelPtrs<T> &lv, T
     a.tau_store = ex.tau_store;
     a.mrhap = ex.mrhap;
     a.delta = ex.delta;
-    const int nb = (n + lc.rows_per_block - 1) / lc.rows_per_block;
+    const int nb = (a.rows + lc.rows_per_block - 1) / lc.rows_per_block;
     const bool tail = (int64_t)lc.threads * lc.chunks * Vec<T>::N != n;
     if (lc.streaming) {
         if (lc.threads != 1024 || lc.chunks < 1 || lc.chunks > 16) return hipErrorInvalidValue;

@@ -27,7 +27,7 @@ EXPORTS = (
     "hap_version", "hap_status_string", "hap_last_error", "hap_build_similarity",
     "hap_median_offdiag", "hap_workspace_size", "hap_init", "hap_iterate", "hap_exemplars",
     "hap_net_similarity", "hap_preference", "hap_read_messages", "hap_similarity_offsets", "hap_set_launch",
-    "hap_set_points",
+    "hap_set_points", "hap_set_row_count", "hap_get_row_count",
     "hap_get_launch", "hap_profile", "hap_profile_read", "hap_destroy",
     "hap_batch_workspace_size", "hap_batch_create", "hap_batch_run", "hap_batch_set_launch",
     "hap_batch_get_launch", "hap_batch_destroy",
@@ -81,6 +81,8 @@ def _declare(lib):
         "hap_read_messages": (I32, [V, I32, V, V, I64, V, V, V]),
         "hap_set_launch": (I32, [V, I32, I32, I32, I32]),
         "hap_set_points": (I32, [V, V, I64, I64, I32]),
+        "hap_set_row_count": (I32, [V, I64]),
+        "hap_get_row_count": (I32, [V, ctypes.POINTER(I64)]),
         "hap_get_launch": (I32, [V, _c_i32p, _c_i32p, _c_i32p, _c_i32p]),
         "hap_profile": (I32, [V, I32]),
         "hap_profile_read": (I32, [V, _c_dblp, ctypes.POINTER(I64), _c_dblp, ctypes.POINTER(I64)]),
@@ -316,6 +318,15 @@ class Hap:
             flags = (LAUNCH_STREAM if st else 0) | (LAUNCH_EAGER if ea else 0)
             self._eager = bool(ea)
         _check("hap_set_launch", self._lib.hap_set_launch(self._ctx, threads, chunks, rows_per_block, flags))
+
+    def set_row_count(self, rows: int):
+        """Update rows [0, rows) only: one block of a run split by rows (n: the whole problem)."""
+        _check("hap_set_row_count", self._lib.hap_set_row_count(self._ctx, int(rows)))
+
+    def get_row_count(self) -> int:
+        r = ctypes.c_int64()
+        _check("hap_get_row_count", self._lib.hap_get_row_count(self._ctx, ctypes.byref(r)))
+        return r.value
 
     def set_points(self, X=None):
         """Points mode: the row pass recomputes s_ij from X (the FP32 points S was built from

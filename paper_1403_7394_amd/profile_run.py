@@ -1,6 +1,6 @@
 """Short runs of the hot path for hardware-counter profiling.
 
-    python paper_1403_7394_amd/profile_run.py [--sweeps K] [--copy-gib G] [--n N]
+    python paper_1403_7394_amd/profile_run.py [--sweeps K] [--copy-gib G] [--n N] [--rows R] [--rb B]
     python paper_1403_7394_amd/profile_run.py --builds
     python paper_1403_7394_amd/profile_run.py --batch [--iters T] [--copy-gib G]
 
@@ -15,6 +15,8 @@ Builds the FP32 similarity of the 8192-point, 64-blob 2-D workload on the GPU, r
 sweeps (all three levels, damping 0.9, no stop rule; the row pass in points mode unless
 --read-s) and, before that, one device copy of
 G GiB (read G GiB, write G GiB) whose counter readings calibrate the HBM byte counters.
+--rows R updates rows [0, R) only (one device's block of a run split by rows, at its real
+shape R x N); --rb B sets the rows per workgroup.
 Every kernel runs on torch's current stream; a line is printed after each step.
 """
 from __future__ import annotations
@@ -33,6 +35,9 @@ def main() -> int:
     ap.add_argument("--sweeps", type=int, default=4)
     ap.add_argument("--copy-gib", type=float, default=1.0)
     ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--rows", type=int, default=0,
+                    help="update rows [0, rows) only: one block of a run split by rows (0: all)")
+    ap.add_argument("--rb", type=int, default=0, help="rows per workgroup (0: the default launch)")
     ap.add_argument("--read-s", action="store_true", help="row pass reads S (default: points mode)")
     ap.add_argument("--builds", action="store_true", help="profile the similarity builds instead")
     ap.add_argument("--batch", action="store_true", help="profile the batched form instead")
@@ -88,13 +93,17 @@ def main() -> int:
     S = torch.empty((n, n), dtype=torch.float32, device=dev)
     hap.build_similarity(X, S)
     h = hap.Hap(S, rp.levels, rp.damping)
+    if args.rows:
+        h.set_row_count(args.rows)
+    if args.rb:
+        h.set_launch(rows_per_block=args.rb)
     if not args.read_s:
         h.set_points(X)
     torch.cuda.synchronize()
     print(f"similarity and state ready: n={n} levels={rp.levels}", flush=True)
     res = h.iterate(args.sweeps)
     torch.cuda.synchronize()
-    print(f"sweeps done: {res.iters}; launch {h.get_launch()}", flush=True)
+    print(f"sweeps done: {res.iters}; launch {h.get_launch()}; rows {h.get_row_count()}", flush=True)
     h.close()
     return 0
 
