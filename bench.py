@@ -369,6 +369,108 @@ def run_warm_form(args, torch, hap, synth) -> dict:
     return out
 
 
+def run_profile_form(args, torch, hap, synth) -> int:
+    """Short runs of one part of the hot path for hardware-counter profiling (rocprofv3); a
+    line is printed after each step, every kernel runs on torch's current stream.
+
+    sweeps: the FP32 similarity of the 2-D 64-blob workload (--n points, default 8192), then
+      --sweeps full sweeps (L = 3, damping 0.9, no stop rule; points mode unless --read-s;
+      --rows R updates rows [0, R) only, one device's block of a run split by rows; --rb B sets
+      the rows per workgroup), after one device copy of --copy-gib GiB whose counter readings
+      calibrate the HBM byte counters.
+    builds: the similarity of the 32768-point, 64-dimensional workload built once in each mode
+      (direct, FP32 GEMM, BF16, BF16x3).
+    batch-once: the batched workload run once for --form-iters iterations (default 200) in the
+      launch shape --batch-launch, after the calibration copy."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    if args.form == "builds":
+        blobs, _ = synth.workload_precision()
+        n = blobs.X.shape[0]
+        X = torch.from_numpy(blobs.X).to(dev)
+        S = torch.empty((n, n), dtype=torch.float32, device=dev)
+        for name, mode in (("direct", hap.BUILD_DIRECT), ("gemm_f32", hap.BUILD_GEMM), ("bf16", hap.BUILD_BF16),
+                           ("bf16x3", hap.BUILD_BF16X3)):
+            hap.build_similarity(X, S, mode=mode)
+            torch.cuda.synchronize()
+            print(f"build {name}: {n} x {n} from d = {blobs.X.shape[1]}", flush=True)
+        return 0
+    if args.copy_gib > 0:
+        words = int(args.copy_gib * (1 << 30)) // 4
+        src = torch.ones(words, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"copy: {words * 4} bytes read, {words * 4} bytes written", flush=True)
+        del src, dst
+    if args.form == "batch-once":
+        problems, rp = synth.workload_batched()
+        iters = args.form_iters if args.form_iters else rp.max_iters
+        sizes = [b.X.shape[0] for b in problems]
+        X = torch.from_numpy(np.concatenate([b.X for b in problems])).to(dev)
+        bt = hap.HapBatch(sizes, problems[0].X.shape[1], rp.levels)
+        shape = tuple(int(v) for v in args.batch_launch.split(","))
+        bt.set_launch(*shape)
+        out = bt.outputs(dev)
+        torch.cuda.synchronize()
+        print(f"batch ready: {len(sizes)} problems, sum n^2 = {sum(k * k for k in sizes)}, launch {shape}", flush=True)
+        bt.run(X, rp.damping, iters, out=out)
+        torch.cuda.synchronize()
+        print(f"batch done: {iters} iterations", flush=True)
+        bt.close()
+        return 0
+    blobs, rp = synth.workload_plain_f32(n=args.n)
+    n = blobs.X.shape[0]
+    X = torch.from_numpy(blobs.X).to(dev)
+    S = torch.empty((n, n), dtype=torch.float32, device=dev)
+    hap.build_similarity(X, S)
+    h = hap.Hap(S, rp.levels, rp.damping)
+    if args.rows:
+        h.set_row_count(args.rows)
+    if args.rb:
+        h.set_launch(rows_per_block=args.rb)
+    if not args.read_s:
+        h.set_points(X)
+    torch.cuda.synchronize()
+    print(f"similarity and state ready: n={n} levels={rp.levels}", flush=True)
+    res = h.iterate(args.sweeps)
+    torch.cuda.synchronize()
+    print(f"sweeps done: {res.iters}; launch {h.get_launch()}; rows {h.get_row_count()}", flush=True)
+    h.close()
+    return 0
+
+
+def run_ceiling_form(args, torch, hap) -> dict:
+    """What the row pass's read/write mixes reach on this GPU: the library's bandwidth probe
+    (same access pattern as the row pass: 512-thread workgroups over blocks of 32 rows, 16-byte
+    accesses, non-temporal S and stores) over 8192 x 8192 FP32 arrays, for a pure read, a copy,
+    the points-mode mix (read and write rho and alpha) and the S-reading mix (read S, rho,
+    alpha; write rho, alpha).  HIP events on the probe's stream, --steps repetitions each after
+    two untimed ones."""
+    dev = torch.device("cuda:0")
+    n = 8192
+    arrs = [torch.full((n, n), 1.0 + k, dtype=torch.float32, device=dev) for k in range(5)]
+    sink = torch.zeros(1, dtype=torch.float32, device=dev)
+    reps = max(5, args.steps)
+    out = {"form": "ceiling", "arrays": f"{n} x {n} FP32", "peak_GBs": HBM_PEAK_GBS, "mixes": {}}
+    for name, r, w in (("read", 1, 0), ("copy", 1, 1), ("points_mix_2r2w", 2, 2), ("s_mix_3r2w", 3, 2)):
+        ins, outs = arrs[:r], arrs[r:r + w]
+        for _ in range(2):
+            hap.bandwidth_probe(ins, outs, sink=sink)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            hap.bandwidth_probe(ins, outs, sink=sink)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        gbs = (r + w) * n * n * 4 / (us * 1e-6) / 1e9
+        out["mixes"][name] = {"reads": r, "writes": w, "avg_us": us, "GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+        print(json.dumps({"mix": name, "avg_us": us, "GBs": gbs}), file=sys.stderr, flush=True)
+    return out
+
+
 def run_image_form(args, torch, hap, synth) -> dict:
     """Image-style form (Section 4): RGB pixels of the sizes of the paper's two images
     (103 x 103 and 120 x 100, from 16 colour blobs), negative Euclidean distances, random
@@ -424,10 +526,24 @@ def main() -> int:
     ap.add_argument("--cpu-sweeps", type=int, default=5, help="sweeps of the oracle timed for cpu_baseline (about 13 s)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration under rocprofv3)")
-    ap.add_argument("--form", choices=["plain", "precision", "batched", "warm", "image"], default="plain",
+    ap.add_argument("--form", choices=["plain", "precision", "batched", "warm", "image", "ceiling", "sweeps",
+                                       "builds", "batch-once"], default="plain",
                     help="plain: the headline line; precision: the similarity build forms; "
                          "batched: many problems in one launch; warm: the learned warm start; "
-                         "image: the paper's image-style workload (random preferences, Euclidean distance)")
+                         "image: the paper's image-style workload (random preferences, Euclidean distance); "
+                         "ceiling: bandwidth of the row pass's read/write mixes; "
+                         "sweeps, builds, batch-once: short runs for counter profiling")
+    ap.add_argument("--sweeps", type=int, default=4, help="--form sweeps: sweeps to run")
+    ap.add_argument("--n", type=int, default=8192, help="--form sweeps: points")
+    ap.add_argument("--rows", type=int, default=0, help="--form sweeps: update rows [0, rows) only (0: all)")
+    ap.add_argument("--rb", type=int, default=0, help="--form sweeps: rows per workgroup (0: the default launch)")
+    ap.add_argument("--copy-gib", type=float, default=1.0,
+                    help="--form sweeps / batch-once: GiB of the calibration copy run first (0: none)")
+    ap.add_argument("--batch-launch", default="1024,512,4",
+                    help="--form batch-once: threads,workgroups,row_groups of the persistent launch")
+    ap.add_argument("--read-s-steps", type=int, default=2,
+                    help="plain form: steps of the S-reading row pass timed after the headline steps "
+                         "(its own roofline entry; 0: skip)")
     ap.add_argument("--form-iters", type=int, default=0, help="iterations for a form run (0 = the workload's)")
     ap.add_argument("--read-s", action="store_true", help="plain form: the row pass reads S (no points mode)")
     ap.add_argument("--schedule", choices=["sequential", "mrhap"], default="sequential",
@@ -444,6 +560,7 @@ def main() -> int:
               "(the row-block sharding is described in the design notes)", file=sys.stderr)
         return 2
 
+    import numpy as np
     import torch
 
     from paper_1403_7394_amd import hap, metrics, synth
@@ -464,6 +581,11 @@ def main() -> int:
     if args.form == "image":
         print(json.dumps(run_image_form(args, torch, hap, synth)), flush=True)
         return 0
+    if args.form == "ceiling":
+        print(json.dumps(run_ceiling_form(args, torch, hap)), flush=True)
+        return 0
+    if args.form in ("sweeps", "builds", "batch-once"):
+        return run_profile_form(args, torch, hap, synth)
     dev = torch.device("cuda:0")
     blobs, rp = synth.workload_plain_f32()
     n = blobs.X.shape[0]
@@ -482,10 +604,10 @@ def main() -> int:
     points = not args.read_s and args.kappa == 0.0
     schedule = hap.SCHEDULE_MRHAP if args.schedule == "mrhap" else hap.SCHEDULE_SEQUENTIAL
 
-    def step(profile: bool):
+    def step(profile: bool, use_points: bool):
         hap.build_similarity(X, S)
         h = hap.Hap(S, L, rp.damping, workspace=ws, schedule=schedule, kappa=args.kappa)
-        if points:
+        if use_points:
             h.set_points(X)
         if profile:
             # event pairs around the launches of every PROF_EVERY-th sweep: enough launches for
@@ -500,39 +622,66 @@ def main() -> int:
         h.close()
         return res, counts, ns, prof, launch, labels
 
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sweeps = 0
-    row_ms = col_ms = 0.0
-    row_n = col_n = 0
-    first_sweeps = 0
-    for _ in range(args.steps):
-        res, counts, ns, prof, launch, labels = step(True)
-        # an early stop is detected one sweep after the stop iteration; a stop at the cap is not
-        sweeps += res.iters + 1 if (res.converged and res.iters < rp.max_iters) else res.iters
-        first_sweeps += 1
-        row_ms += prof[0]
-        row_n += prof[1]
-        col_ms += prof[2]
-        col_n += prof[3]
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    def timed(steps: int, use_points: bool):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        acc = dict(sweeps=0, row_ms=0.0, row_n=0, col_ms=0.0, col_n=0, first=0)
+        for _ in range(steps):
+            res, counts, ns, prof, launch, labels = step(True, use_points)
+            # an early stop is detected one sweep after the stop iteration; a stop at the cap is not
+            acc["sweeps"] += res.iters + 1 if (res.converged and res.iters < rp.max_iters) else res.iters
+            acc["first"] += 1
+            acc["row_ms"] += prof[0]
+            acc["row_n"] += prof[1]
+            acc["col_ms"] += prof[2]
+            acc["col_n"] += prof[3]
+        torch.cuda.synchronize()
+        acc["elapsed"] = time.perf_counter() - t0
+        acc["last"] = (res, counts, ns, launch, labels)
+        return acc
 
-    w = 4
-    # algorithmic bytes of all row-pass launches: 4 N^2 w in the first sweep, 5 N^2 w after
-    # (one word less per element in points mode, where S is not read)
-    first_w, steady_w = (3, 4) if points else (4, 5)
-    alg_bytes_total = (first_sweeps * L * first_w + (row_n - first_sweeps * L) * steady_w) * n * n * w
-    bytes_per_launch = alg_bytes_total / max(row_n, 1)
-    avg_launch_s = row_ms / max(row_n, 1) * 1e-3
-    achieved = bytes_per_launch / avg_launch_s / 1e9
-    # the counters were taken on the plain row pass; the Eq. 2.7 instance is another kernel
-    traffic = measured_traffic(points, first_sweeps * L, row_n - first_sweeps * L) if args.kappa == 0.0 else None
+    def roofline(acc, use_points: bool) -> dict:
+        w = 4
+        # algorithmic bytes of all row-pass launches: read S, R, A and write R, A = 5 N^2 w, or
+        # 4 N^2 w in the first sweep (no alpha to finish); one word less per element in points
+        # mode, where S is not read
+        first_w, steady_w = (3, 4) if use_points else (4, 5)
+        first_launches = acc["first"] * L
+        alg_total = (first_launches * first_w + (acc["row_n"] - first_launches) * steady_w) * n * n * w
+        per_launch = alg_total / max(acc["row_n"], 1)
+        avg_s = acc["row_ms"] / max(acc["row_n"], 1) * 1e-3
+        achieved = per_launch / avg_s / 1e9
+        # the counters were taken on the plain row pass; the Eq. 2.7 instance is another kernel
+        traffic = (measured_traffic(use_points, first_launches, acc["row_n"] - first_launches)
+                   if args.kappa == 0.0 else None)
+        return {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": ("row pass (sweep_kernel, points mode)" if use_points else
+                       "row pass (sweep_kernel, S read, Eq. 2.7 row offsets)" if args.kappa else
+                       "row pass (sweep_kernel, S read)"),
+            "words_per_element": {"first_sweep": first_w, "later_sweeps": steady_w},
+            "avg_launch_us": avg_s * 1e6,
+            "alg_bytes_per_launch": per_launch,
+            "launches_timed": acc["row_n"],
+            "launches": int(acc["sweeps"] * L),
+            "timed_every": PROF_EVERY,
+        }
+
+    for _ in range(args.warmup):
+        step(False, points)
+    main = timed(args.steps, points)
+    res, counts, ns, launch, labels = main["last"]
+    elapsed = main["elapsed"]
+    sweeps = main["sweeps"]
     ms_per_step = elapsed / args.steps * 1e3
     value = n * n * L * sweeps / elapsed
 
+    lab = labels.cpu().numpy()
     out = {
         "metric": METRIC,
         "value": value,
@@ -555,33 +704,44 @@ def main() -> int:
             "n": n, "levels": L, "damping": rp.damping, "max_iters": rp.max_iters,
             "stable_iters": rp.stable_iters, "seed": blobs.seed,
         },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "kernel": ("row pass (sweep_kernel, points mode)" if points else
-                       "row pass (sweep_kernel, S read, Eq. 2.7 row offsets)" if args.kappa else "row pass (sweep_kernel)"),
-            "avg_launch_us": avg_launch_s * 1e6,
-            "alg_bytes_per_launch": bytes_per_launch,
-            "launches_timed": row_n,
-            "launches": int(sweeps * L),
-            "timed_every": PROF_EVERY,
-        },
+        "roofline": roofline(main, points),
         "sweeps_per_step": sweeps / args.steps,
         "converged": bool(res.converged),
-        "time_to_converge_ms": ms_per_step,
+        # the run meets the stop rule only if it converged; otherwise the step ran to the cap
+        "time_to_converge_ms": ms_per_step if res.converged else None,
+        "time_to_cap_ms": None if res.converged else ms_per_step,
         # the timed sweeps' kernel time only (row passes and column sums, no host work)
-        "sweep_updates_per_s": n * n * row_n / ((row_ms + col_ms) * 1e-3) if row_ms > 0 else None,
-        "colsum_avg_us": col_ms / max(col_n, 1) * 1e3,
+        "sweep_updates_per_s": (n * n * main["row_n"] / ((main["row_ms"] + main["col_ms"]) * 1e-3)
+                                if main["row_ms"] > 0 else None),
+        "colsum_avg_us": main["col_ms"] / max(main["col_n"], 1) * 1e3,
         "exemplars_per_level": counts,
         "net_similarity": ns,
-        "purity_per_level": [metrics.purity(lab, blobs.truth) for lab in labels.cpu().numpy()],
+        "purity_per_level": [metrics.purity(x, blobs.truth) for x in lab],
         "launch": {"threads": launch[0], "chunks": launch[1], "rows_per_block": launch[2],
                    "streaming": launch[3]},
     }
+    # how the step's labels compare with the stored oracle runs of the same workload (written by
+    # tests/golden/full_run_plain8192.py from the oracle alone); the row-ordered launch
+    # (one row per workgroup) equals the FP32 oracle run at every checkpoint, which the GPU tests
+    # check; the default launch sums the column partials in blocks of rows
+    if (args.schedule == "sequential" and args.kappa == 0.0 and not res.converged
+            and res.iters == rp.max_iters):
+        gold = {}
+        for dt in ("float32", "float64"):
+            try:
+                with np.load(os.path.join(ROOT, "tests", "golden", f"full_run_plain8192_oracle_{dt}.npz")) as z:
+                    gold[dt] = z["final_labels"]
+            except (OSError, KeyError):
+                pass
+        out["oracle_label_agreement_at_cap"] = {dt: [float(np.mean(lab[l] == g[l])) for l in range(L)]
+                                                for dt, g in gold.items()}
+    if points and args.read_s_steps > 0:
+        # the pass the workload's configuration names (dense S read every sweep), timed the same way
+        rs = timed(args.read_s_steps, False)
+        out["roofline_read_s"] = roofline(rs, False)
+        out["read_s"] = {"steps": args.read_s_steps, "ms_per_step": rs["elapsed"] / args.read_s_steps * 1e3,
+                         "value": n * n * L * rs["sweeps"] / rs["elapsed"],
+                         "labels_equal_points_mode": bool(torch.equal(rs["last"][4], labels))}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(blobs.X, rp, args.cpu_sweeps)
     print(json.dumps(out), flush=True)

@@ -140,10 +140,27 @@ HAP_API hap_status hap_build_similarity(const void *X, int64_t n, int64_t d, int
  * Median of the n(n-1) off-diagonal entries of S (device, n x lds, type dtype):
  * the mean of the two middle order statistics, formed in FP64 and rounded to
  * dtype, written to *out_host as a double.  Exact (radix select on the bit
- * patterns).  Synchronises the stream.
+ * patterns).  2 <= n <= 65536 (HAP_E_UNSUPPORTED above: the select counts keys in
+ * 32 bits).  Allocates and frees an 8 KB scratch on the stream.  Synchronises the stream.
  */
 HAP_API hap_status hap_median_offdiag(const void *S, int64_t n, int64_t lds, int32_t dtype,
                               double *out_host, void *stream);
+
+
+/*
+ * Bandwidth probe for the roofline: one kernel that reads `reads` arrays in[0..reads) and writes
+ * `writes` arrays out[0..writes) of rows x cols FP32 elements (device, row stride ld, 16-byte
+ * aligned; cols and ld multiples of 4, cols <= 8192), with the access pattern of the sweep's
+ * row pass (workgroups of 512 threads own rows_per_block consecutive rows, 16 bytes per thread access,
+ * the first input and every output non-temporal); each output element is the sum of the inputs.
+ * (reads, writes): (1, 0) pure read (out[0] must still point at one writable element, stored to
+ * only if the data hold a marker pair, so the loads cannot be dropped), (1, 1) copy, (2, 2) the
+ * points-mode row pass's mix (read and write rho and alpha), (3, 2) the row pass reading S.
+ * Measures what such a mix reaches on the device; not part of the method.  HAP_E_ARG for other
+ * mixes or bad sizes, HAP_E_UNSUPPORTED above 8192 columns.  Stream-ordered, no synchronisation.
+ */
+HAP_API hap_status hap_bandwidth_probe(int32_t reads, int32_t writes, const float *const *in, float *const *out,
+                                       int64_t rows, int64_t cols, int64_t ld, int64_t rows_per_block, void *stream);
 
 /* Bytes of device workspace hap_init needs for this problem. */
 HAP_API hap_status hap_workspace_size(int64_t n, int32_t levels, int32_t dtype, size_t *bytes);
@@ -186,7 +203,9 @@ HAP_API hap_status hap_exemplars(hap_ctx *ctx, int32_t level, int32_t *labels, i
 
 /*
  * Net similarity NS^l = sum_i s^l_{i, e^l_i} (s^l_ii = p^l_i), accumulated in
- * FP64 on the GPU; level = -1 gives the sum over levels.  X (device, n x d,
+ * FP64 on the GPU; level = -1 gives the sum over levels.  The paper defines no
+ * objective; this is the usual affinity-propagation one (the summed similarity of
+ * every point to its exemplar, an exemplar's own term being its preference).  X (device, n x d,
  * leading dimension ldx, type x_dtype) may be given to recompute the
  * similarities -||x_i - x_e||^2 in FP64 instead of reading S.  Synchronises.
  */
@@ -216,7 +235,11 @@ HAP_API hap_status hap_similarity_offsets(hap_ctx *ctx, int32_t level, void *del
  * Override the sweep launch shape: threads per row (64..1024, power of two),
  * 16-byte column chunks per thread (1, 2, 4 or 8; 4 needs <= 512 threads, 8 needs
  * <= 256) and rows per workgroup (>= 1; 1 sums the column partials in row
- * order).  threads * chunks * (16 / element size) must cover n.  0 keeps the
+ * order).  threads * chunks * (16 / element size) must cover n.  A shape with more
+ * than min(n, 2048) workgroups (for example one row per workgroup at n > 2048) makes the
+ * library allocate its own column-partial buffer of (workgroups x n) words (twice that
+ * under HAP_SCHEDULE_MRHAP; 268 MB for one row per workgroup at n = 8192, FP32), kept
+ * until hap_destroy; HAP_E_OOM if that allocation fails (nothing changes).  0 keeps the
  * library's choice for that field.  flags (a bit set; -1 keeps the current
  * choices): HAP_LAUNCH_STREAM selects the streaming row pass for long rows (1024
  * threads, 1 to 16 chunks; the row is read again from the caches in its second
@@ -234,16 +257,21 @@ HAP_API hap_status hap_get_launch(hap_ctx *ctx, int32_t *threads, int32_t *chunk
 
 /*
  * Points mode of the register-resident row pass.  The caller states that the context's S
- * was built from X (device FP32, n x d row-major, row stride ldx) by hap_build_similarity
- * with HAP_BUILD_DIRECT and no noise; the row pass then recomputes s_ij = -||x_i - x_j||^2
- * with the build's arithmetic (FP64 accumulation in coordinate order, rounded once), which
- * gives the same values as reading S and saves one N^2 read per level and iteration (about
- * a fifth of the sweep's traffic).  The one-off passes (median, labels, net similarity) and
- * the streaming row pass still read S, and so does every row pass of a context with
- * kappa > 0.  FP32 contexts, d = 2 or 3.  X must stay valid while the context iterates.
- * X = NULL switches the mode off.
+ * was built from X (device FP32, n x d row-major, row stride ldx; n must equal the context's
+ * point count) by hap_build_similarity with HAP_BUILD_DIRECT and no noise; the row pass then
+ * recomputes s_ij = -||x_i - x_j||^2 (Section 2) with the build's arithmetic (FP64
+ * accumulation in coordinate order, rounded once), which gives the same values as reading S
+ * and saves one N^2 read per level and iteration (about a fifth of the sweep's traffic).  The
+ * one-off passes (median, labels, net similarity) and the streaming row pass still read S,
+ * and so does every row pass of a context with kappa > 0.  FP32 contexts, d = 2 or 3.  X must
+ * stay valid while the context iterates.  X = NULL switches the mode off.
+ * Checks: n different from the context's, or a type, d or ldx that does not fit, gives
+ * HAP_E_ARG / HAP_E_DTYPE / HAP_E_UNSUPPORTED before anything is launched.  Otherwise 64
+ * off-diagonal entries (two corners and 62 pseudo-random pairs) are recomputed from X on the
+ * device and compared bit for bit with S; any difference gives HAP_E_ARG and leaves the mode
+ * as it was.  Synchronises the stream.
  */
-HAP_API hap_status hap_set_points(hap_ctx *ctx, const void *X, int64_t d, int64_t ldx, int32_t x_dtype);
+HAP_API hap_status hap_set_points(hap_ctx *ctx, const void *X, int64_t n, int64_t d, int64_t ldx, int32_t x_dtype);
 
 /*
  * One block of a run split by rows (the per-node message updates of Section 3, with each
@@ -252,7 +280,8 @@ HAP_API hap_status hap_set_points(hap_ctx *ctx, const void *X, int64_t d, int64_
  * tau then hold that block's contribution alone, which is what one device of a row-split
  * run computes before a collective adds the other blocks' sums.  The other rows keep
  * their messages (the initial ones, in a fresh context) and add nothing to the sums; their
- * labels and messages are not meaningful while a block is set.  rows = n (the default)
+ * labels and messages are not meaningful while a block is set, and the stop rule and the
+ * exemplar count of hap_exemplars take rows [0, rows) only.  rows = n (the default)
  * is the whole problem.  The launch shape (rows per workgroup) applies to the block; a
  * shape that does not fit is rejected (HAP_E_ARG).  Needs the sequential schedule and
  * kappa = 0 when rows < n (HAP_E_UNSUPPORTED otherwise); HAP_E_ARG unless 1 <= rows <= n.
@@ -310,7 +339,7 @@ HAP_API hap_status hap_batch_run(hap_batch *batch, const void *X, double damping
  * its problem at once (each group owning NT/G threads); the rows' column-sum contributions
  * are still added in row order, so every shape computes the same values bit for bit.
  * (threads, row_groups) is one of (256, 1), (512, 1), (512, 2), (512, 4), (1024, 4); any
- * other pair is rejected with HAP_ERR_ARG and changes nothing.  0 keeps the current value.
+ * other pair is rejected with HAP_E_ARG and changes nothing.  0 keeps the current value.
  * For the autotuner. */
 HAP_API hap_status hap_batch_set_launch(hap_batch *batch, int32_t threads, int32_t workgroups, int32_t row_groups);
 HAP_API hap_status hap_batch_get_launch(hap_batch *batch, int32_t *threads, int32_t *workgroups,

@@ -50,7 +50,11 @@ struct hap_ctx {
          *B = nullptr, *delta = nullptr;
     double kappa = 0.0;           // Eq. 2.7 weight (0: the update is off)
     int32_t *E = nullptr, *Efinal = nullptr, *mark = nullptr, *count = nullptr;
-    char *Qpart = nullptr;
+    char *Qpart = nullptr;        // column partials of up to nb_cap workgroups (in the workspace)
+    // column partials of launches with more than nb_cap workgroups (for example one row per
+    // workgroup at n > 2048): allocated by the library when such a launch is set
+    char *Qbig = nullptr;
+    size_t qbig_bytes = 0;
     DevState *ds = nullptr;
     double *dbl = nullptr;        // [0] median, [1..] net similarity per level + total
     void *select_scratch = nullptr;
@@ -200,7 +204,7 @@ Launch default_launch(int64_t n, size_t esz) {
     return lc;
 }
 
-bool launch_fits(const Launch &lc, int64_t n, int64_t rows, size_t esz, int nb_cap) {
+bool launch_fits(const Launch &lc, int64_t n, int64_t rows, size_t esz) {
     const int64_t vw = (int64_t)(16 / esz);
     if (lc.streaming) {
         if (lc.threads != 1024) return false;
@@ -209,10 +213,10 @@ bool launch_fits(const Launch &lc, int64_t n, int64_t rows, size_t esz, int nb_c
         return false;
     }
     if ((int64_t)lc.threads * lc.chunks * vw < n) return false;
-    if (lc.rows_per_block < 1) return false;
-    const int64_t nb = (rows + lc.rows_per_block - 1) / lc.rows_per_block;
-    return nb <= nb_cap;
+    return lc.rows_per_block >= 1;
 }
+
+int64_t launch_blocks(const Launch &lc, int64_t rows) { return (rows + lc.rows_per_block - 1) / lc.rows_per_block; }
 
 bool dtype_ok(int32_t dt) { return dt == HAP_F32 || dt == HAP_F64; }
 size_t dtype_size(int32_t dt) { return dt == HAP_F64 ? 8 : 4; }
@@ -258,8 +262,12 @@ hipError_t prof_collect(hap_ctx *c) {
 template <typename T>
 hap_status run_sweeps(hap_ctx *c, int count, int K) {
     const int L = c->L;
-    const int nb = (int)((c->rows + c->lc.rows_per_block - 1) / c->lc.rows_per_block);
-    T *Qpart[2] = {(T *)c->Qpart, (T *)c->Qpart + (size_t)c->nb_cap * c->ldw};
+    const int nb = (int)launch_blocks(c->lc, c->rows);
+    // the workspace's partial buffers, or the library's own when the launch has more workgroups
+    const bool big = nb > c->nb_cap;
+    T *qbase = big ? (T *)c->Qbig : (T *)c->Qpart;
+    const size_t qstride = (size_t)(big ? nb : c->nb_cap) * c->ldw;
+    T *Qpart[2] = {qbase, qbase + qstride};
     hap::SweepExtra<T> ex;
     ex.X = (const T *)c->X;
     ex.ldx = c->ldx;
@@ -398,9 +406,33 @@ hap_status finalize_labels(hap_ctx *c) {
     for (int l = 0; l < c->L; ++l) {
         LevelPtrs<T> lv = level_ptrs<T>(c, l);
         HIP_TRY(hap::launch_finalize<T>((const T *)c->S, c->lds, lv, (int)c->n, c->ldw, c->lam, c->t_host, lv.Efinal,
-                                        nullptr, 0, nullptr, nullptr, c->ds, c->stream),
+                                        nullptr, 0, nullptr, nullptr, c->ds, c->stream, nullptr, (int)c->rows),
                 c);
     }
+    return HAP_OK;
+}
+
+// Column partials for a launch with more workgroups than the workspace holds: one row of ldw
+// words per workgroup (two sets under the MapReduce schedule, whose passes alternate).  The
+// library allocates them when such a launch is set and frees them in hap_destroy.
+hap_status ensure_partials(hap_ctx *c, const Launch &lc, int64_t rows) {
+    const int64_t nb = launch_blocks(lc, rows);
+    if (nb <= c->nb_cap) return HAP_OK;
+    const size_t sets = c->schedule == HAP_SCHEDULE_MRHAP ? 2 : 1;
+    const size_t need = sets * (size_t)nb * (size_t)c->ldw * c->esz;
+    if (c->Qbig && c->qbig_bytes >= need) return HAP_OK;
+    HIP_TRY(hipStreamSynchronize(c->stream), c);
+    if (c->Qbig) {
+        HIP_TRY(hipFree(c->Qbig), c);
+        c->Qbig = nullptr;
+        c->qbig_bytes = 0;
+    }
+    if (hipMalloc(&c->Qbig, need) != hipSuccess) {
+        (void)hipGetLastError();
+        c->Qbig = nullptr;
+        return fail_arg("column partials of this launch: hipMalloc failed", HAP_E_OOM);
+    }
+    c->qbig_bytes = need;
     return HAP_OK;
 }
 
@@ -452,7 +484,9 @@ hap_status hap_median_offdiag(const void *S, int64_t n, int64_t lds, int32_t dty
     if (!S || !out_host) return fail_arg("hap_median_offdiag: null pointer");
     if (!dtype_ok(dtype)) return fail_arg("hap_median_offdiag: dtype", HAP_E_DTYPE);
     if (n < 2 || !ld_ok(n, lds, dtype)) return fail_arg("hap_median_offdiag: bad sizes");
-    if (n > (int64_t)1 << 20) return fail_arg("hap_median_offdiag: n too large", HAP_E_UNSUPPORTED);
+    if (n > hap::kMaxSelectN)
+        return fail_arg("hap_median_offdiag: n too large (at most 65536: the select counts n(n-1) keys in 32 bits)",
+                        HAP_E_UNSUPPORTED);
     hipStream_t st = (hipStream_t)stream;
     void *scratch = nullptr;
     const size_t bytes = hap::select_scratch_bytes() + 256;
@@ -466,6 +500,38 @@ hap_status hap_median_offdiag(const void *S, int64_t n, int64_t lds, int32_t dty
     if (e == hipSuccess) e = e2;
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail_hip(e, "hap_median_offdiag");
+    return HAP_OK;
+}
+
+hap_status hap_bandwidth_probe(int32_t reads, int32_t writes, const float *const *in, float *const *out, int64_t rows,
+                               int64_t cols, int64_t ld, int64_t rows_per_block, void *stream) {
+    const bool mix_ok = (reads == 1 && writes == 0) || (reads == 1 && writes == 1) || (reads == 2 && writes == 2) ||
+                        (reads == 3 && writes == 2);
+    if (!mix_ok) return fail_arg("hap_bandwidth_probe: (reads, writes) must be (1,0), (1,1), (2,2) or (3,2)");
+    if (!in || (writes > 0 && !out)) return fail_arg("hap_bandwidth_probe: null pointer");
+    if (rows < 1 || cols < 1 || ld < cols || ld % 4 != 0 || cols % 4 != 0 || rows_per_block < 1)
+        return fail_arg("hap_bandwidth_probe: bad sizes (cols and ld multiples of 4, ld >= cols)");
+    if (cols > 8192) return fail_arg("hap_bandwidth_probe: at most 8192 columns", HAP_E_UNSUPPORTED);
+    if (reads == 1 && writes == 0 && (!out || !out[0]))
+        return fail_arg("hap_bandwidth_probe: the pure-read probe needs out[0] (one element, written only if the "
+                        "data hold a marker pair)");
+    hap::ProbeArgs a{};
+    for (int r = 0; r < reads; ++r) {
+        if (!in[r] || ((uintptr_t)in[r] & 15u)) return fail_arg("hap_bandwidth_probe: input null or not 16-byte aligned");
+        a.in[r] = in[r];
+    }
+    for (int w = 0; w < writes; ++w) {
+        if (!out[w] || ((uintptr_t)out[w] & 15u))
+            return fail_arg("hap_bandwidth_probe: output null or not 16-byte aligned");
+        a.out[w] = out[w];
+    }
+    if (writes == 0) a.out[0] = out[0];   // the pure-read mix's one-element sink
+    a.rows = rows;
+    a.cols = cols;
+    a.ld = ld;
+    a.rows_per_block = rows_per_block;
+    hipError_t e = hap::launch_probe(reads, writes, a, (hipStream_t)stream);
+    if (e != hipSuccess) return fail_hip(e, "hap_bandwidth_probe");
     return HAP_OK;
 }
 
@@ -504,7 +570,7 @@ hap_status hap_init(hap_ctx **out, const void *S, int64_t n, int64_t lds, int32_
     const size_t esz = dtype_size(dtype);
     Layout lo = make_layout(n, p->levels, esz);
     Launch lc = default_launch(n, esz);
-    if (lc.threads == 0 || !launch_fits(lc, n, n, esz, lo.nb_cap))
+    if (lc.threads == 0 || !launch_fits(lc, n, n, esz) || launch_blocks(lc, n) > lo.nb_cap)
         return fail_arg("hap_init: n too large (at most 65536 points in FP32, 32768 in FP64)", HAP_E_UNSUPPORTED);
     if (workspace) {
         if (workspace_bytes < lo.total) return fail_arg("hap_init: workspace too small");
@@ -674,7 +740,7 @@ hap_status hap_exemplars(hap_ctx *c, int32_t level, int32_t *labels, int32_t *n_
     const int32_t *src = c->Efinal + (size_t)c->ldw * level;
     if (labels) HIP_TRY(hipMemcpyAsync(labels, src, (size_t)c->n * 4, hipMemcpyDeviceToDevice, c->stream), c);
     if (n_exemplars) {
-        HIP_TRY(hap::launch_count_distinct(src, (int)c->n, c->mark, c->count, c->stream), c);
+        HIP_TRY(hap::launch_count_distinct(src, (int)c->rows, (int)c->n, c->mark, c->count, c->stream), c);
         HIP_TRY(hipMemcpyAsync(n_exemplars, c->count, 4, hipMemcpyDeviceToHost, c->stream), c);
         HIP_TRY(hipStreamSynchronize(c->stream), c);
     }
@@ -828,8 +894,10 @@ hap_status hap_set_launch(hap_ctx *c, int32_t threads, int32_t chunks, int32_t r
     if (rows_per_block) lc.rows_per_block = rows_per_block;
     if (flags >= 0) lc.streaming = (flags & HAP_LAUNCH_STREAM) != 0;
     lc.ordered = (lc.rows_per_block == 1);
-    if (!launch_fits(lc, c->n, c->rows, c->esz, c->nb_cap))
+    if (!launch_fits(lc, c->n, c->rows, c->esz))
         return fail_arg("hap_set_launch: shape does not fit this problem");
+    const hap_status ps = ensure_partials(c, lc, c->rows);
+    if (ps != HAP_OK) return ps;
     c->lc = lc;
     if (flags >= 0) c->use_graphs = (flags & HAP_LAUNCH_EAGER) == 0;
     drop_graphs(c);
@@ -842,8 +910,10 @@ hap_status hap_set_row_count(hap_ctx *c, int64_t rows) {
     if (rows < c->n && (c->schedule != HAP_SCHEDULE_SEQUENTIAL || c->kappa != 0.0))
         return fail_arg("hap_set_row_count: a row block needs the sequential schedule without kappa",
                         HAP_E_UNSUPPORTED);
-    if (!launch_fits(c->lc, c->n, rows, c->esz, c->nb_cap))
+    if (!launch_fits(c->lc, c->n, rows, c->esz))
         return fail_arg("hap_set_row_count: the launch shape does not fit this row count");
+    const hap_status ps = ensure_partials(c, c->lc, rows);
+    if (ps != HAP_OK) return ps;
     c->rows = rows;
     drop_graphs(c);
     return HAP_OK;
@@ -855,7 +925,7 @@ hap_status hap_get_row_count(hap_ctx *c, int64_t *rows) {
     return HAP_OK;
 }
 
-hap_status hap_set_points(hap_ctx *c, const void *X, int64_t d, int64_t ldx, int32_t x_dtype) {
+hap_status hap_set_points(hap_ctx *c, const void *X, int64_t n, int64_t d, int64_t ldx, int32_t x_dtype) {
     if (!c) return fail_arg("hap_set_points: null context");
     if (!X) {
         c->X = nullptr;
@@ -864,10 +934,42 @@ hap_status hap_set_points(hap_ctx *c, const void *X, int64_t d, int64_t ldx, int
         drop_graphs(c);
         return HAP_OK;
     }
+    if (c->failed) return fail_arg("hap_set_points: context failed earlier", HAP_E_STATE);
+    if (n != c->n) return fail_arg("hap_set_points: the point count differs from the context's n");
     if (c->dtype != HAP_F32 || x_dtype != HAP_F32)
         return fail_arg("hap_set_points: points mode needs FP32 similarities and FP32 points", HAP_E_DTYPE);
     if (d != 2 && d != 3) return fail_arg("hap_set_points: points mode supports d = 2 or 3", HAP_E_UNSUPPORTED);
     if (ldx < d) return fail_arg("hap_set_points: ldx < d");
+    // S must be the direct build of these points: recompute sampled entries and compare bits
+    hap::PairSample ps{};
+    uint64_t z = 0x9e3779b97f4a7c15ull ^ (uint64_t)n;
+    auto next = [&]() {
+        z += 0x9e3779b97f4a7c15ull;
+        uint64_t x = z;
+        x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+        x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+        return x ^ (x >> 31);
+    };
+    ps.count = 64;
+    ps.i[0] = 0;
+    ps.j[0] = (int32_t)(n - 1);
+    ps.i[1] = (int32_t)(n - 1);
+    ps.j[1] = 0;
+    for (int k = 2; k < 64; ++k) {
+        const int32_t i = (int32_t)(next() % (uint64_t)n);
+        int32_t j = (int32_t)(next() % (uint64_t)n);
+        if (j == i) j = (int32_t)((i + 1) % n);
+        ps.i[k] = i;
+        ps.j[k] = j;
+    }
+    HIP_TRY(hap::launch_points_check((const float *)c->S, c->lds, (const float *)X, ldx, (int)d, ps, c->count,
+                                     c->stream),
+            c);
+    int32_t bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, c->count, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream), c);
+    HIP_TRY(hipStreamSynchronize(c->stream), c);
+    if (bad != 0)
+        return fail_arg("hap_set_points: S is not the direct build of these points (sampled entries differ)");
     c->X = X;
     c->ldx = ldx;
     c->d = (int)d;
@@ -924,6 +1026,10 @@ hap_status hap_destroy(hap_ctx *c) {
     for (hipEvent_t ev : c->ev) (void)hipEventDestroy(ev);
     if (c->own_ws) {
         e = hipFree(c->ws);
+        if (e != hipSuccess && s == HAP_OK) s = fail_hip(e, "hap_destroy: hipFree");
+    }
+    if (c->Qbig) {
+        e = hipFree(c->Qbig);
         if (e != hipSuccess && s == HAP_OK) s = fail_hip(e, "hap_destroy: hipFree");
     }
     delete c;

@@ -88,7 +88,7 @@ hipError_t launch_colsum(const T *Qpart, int64_t ldw, int nb, int n, const Level
 template <typename T>
 hipError_t launch_finalize(const T *S, int64_t lds, const LevelPtrs<T> &lv, int n, int64_t ldw, double lam, int t,
                            int32_t *labels_out, T *alpha_out, int64_t lda, T *c_out, T *phi_out, DevState *ds,
-                           hipStream_t st, const T *delta = nullptr);
+                           hipStream_t st, const T *delta = nullptr, int rows = 0);
 // Optional level-wise similarity update (Eq. 2.7), level-sequential schedule.  Run after the
 // column sums of level l in iteration t, before the row pass of level l+1:
 //   launch_level_phi:   phi^l = max_k(alpha^{l+1,t-1}_ik + s^{l+1,t-1}_ik), alpha^{l+1,t-1}
@@ -108,17 +108,39 @@ bool launch_supported(int threads, int chunks, int elem_size);
 template <typename T>
 hipError_t launch_alpha_pad(T *A, int64_t rows, int n, int64_t ldw, hipStream_t st);
 
-hipError_t launch_count_distinct(const int32_t *labels, int n, int32_t *mark, int32_t *out, hipStream_t st);
+// Number of distinct values among labels[0, rows), every value in [0, n) (mark: int32 [n]).
+hipError_t launch_count_distinct(const int32_t *labels, int rows, int n, int32_t *mark, int32_t *out, hipStream_t st);
 hipError_t launch_net_similarity(const void *S, int64_t lds, int dtype, const void *pref_base,
                                  int64_t ldw, const int32_t *Efinal_base, int n, int levels,
                                  const void *X, int64_t d, int64_t ldx, int x_dtype, double *out,
                                  hipStream_t st);
+// Bandwidth probe (hap_bandwidth_probe): reads/writes arrays of rows x cols floats (row
+// stride ld) with the row pass's access pattern.  (reads, writes) in {(1,0), (1,1), (2,2), (3,2)}.
+struct ProbeArgs {
+    const float *in[3];
+    float *out[2];
+    int64_t rows, cols, ld;
+    int64_t rows_per_block;
+};
+hipError_t launch_probe(int reads, int writes, const ProbeArgs &a, hipStream_t st);
+
+// Sampled off-diagonal pairs for the points-mode check (at most 64).
+struct PairSample {
+    int32_t i[64], j[64];
+    int32_t count;
+};
+// bad[0] = number of sampled pairs whose s_ij recomputed from X (FP32, d coordinates, row
+// stride ldx) by the direct build's arithmetic differs from S (FP32, row stride lds).
+hipError_t launch_points_check(const float *S, int64_t lds, const float *X, int64_t ldx, int d, const PairSample &ps,
+                               int32_t *bad, hipStream_t st);
 hipError_t launch_fill_pref(void *pref_base, int64_t ldw, int n, int levels, int dtype,
                             const double *value_dev, hipStream_t st);
 
 // Radix select of the two middle off-diagonal order statistics; writes their FP64 mean,
 // rounded to the working type, to *median_dev (as double).
 size_t select_scratch_bytes();
+// Largest n the radix select takes: its histograms count up to n(n-1) keys in 32 bits.
+constexpr int64_t kMaxSelectN = 65536;
 hipError_t launch_median_offdiag(const void *S, int64_t n, int64_t lds, int dtype, void *scratch,
                                  double *median_dev, hipStream_t st);
 

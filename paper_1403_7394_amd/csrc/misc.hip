@@ -20,8 +20,8 @@ __global__ void zero_i32(int32_t *p, int n) {
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) p[k] = 0;
 }
 
-__global__ void mark_labels(const int32_t *labels, int n, int32_t *mark) {
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+__global__ void mark_labels(const int32_t *labels, int rows, int n, int32_t *mark) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < rows; k += gridDim.x * blockDim.x) {
         const int e = labels[k];
         if (e >= 0 && e < n) mark[e] = 1;
     }
@@ -89,7 +89,91 @@ __global__ __launch_bounds__(1024) void net_similarity_kernel(const T *__restric
     if (threadIdx.x == 0) out[levels] = total;
 }
 
+// Points-mode check: every sampled off-diagonal pair (i, j) has s_ij recomputed from the FP32
+// points with the direct build's arithmetic (FP64 squared differences summed in coordinate
+// order, negated and rounded once) and compared bit for bit with S.  One wave, one pair per
+// lane; bad[0] receives the number of pairs that differ.
+__global__ __launch_bounds__(64) void points_check_kernel(const float *__restrict__ S, int64_t lds,
+                                                          const float *__restrict__ X, int64_t ldx, int d,
+                                                          PairSample ps, int32_t *bad) {
+#pragma clang fp contract(off)
+    const int k = threadIdx.x;
+    int diff = 0;
+    if (k < ps.count) {
+        const int i = ps.i[k], j = ps.j[k];
+        double acc = 0.0;
+        for (int q = 0; q < d; ++q) {
+            const double df = (double)X[(int64_t)i * ldx + q] - (double)X[(int64_t)j * ldx + q];
+            const double sq = df * df;
+            acc = acc + sq;
+        }
+        const float want = (float)(-acc);
+        diff = __float_as_uint(want) != __float_as_uint(S[(int64_t)i * lds + j]) ? 1 : 0;
+    }
+    const unsigned long long m = __ballot(diff);
+    if (k == 0) bad[0] = __popcll(m);
+}
+
+// Bandwidth probe with the row pass's access pattern: workgroups of 512 threads own blocks of
+// consecutive rows; a thread owns fixed 16-byte column chunks.  Per element it reads R arrays
+// (the first non-temporally, like S in the row pass) and writes W arrays (non-temporally, like
+// R and A); every output is the sum of the inputs, so no read can be dropped.
+template <int R, int W>
+__global__ __launch_bounds__(512) void probe_kernel(ProbeArgs a) {
+    typedef float V __attribute__((ext_vector_type(4)));
+    constexpr int NCH = 4;   // 16-byte chunks per thread and row: rows of up to 8192 columns
+    const int64_t row0 = (int64_t)blockIdx.x * a.rows_per_block;
+    const int64_t row1 = row0 + a.rows_per_block < a.rows ? row0 + a.rows_per_block : a.rows;
+    for (int64_t i = row0; i < row1; ++i) {
+        V acc[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int64_t j = (int64_t)c * 2048 + threadIdx.x * 4;
+            if (j < a.cols) {
+                const int64_t o = i * a.ld + j;
+                acc[c] = __builtin_nontemporal_load((const V *)(a.in[0] + o));
+#pragma unroll
+                for (int r = 1; r < R; ++r) acc[c] += *(const V *)(a.in[r] + o);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int64_t j = (int64_t)c * 2048 + threadIdx.x * 4;
+            if (j < a.cols) {
+                const int64_t o = i * a.ld + j;
+#pragma unroll
+                for (int w = 0; w < W; ++w) __builtin_nontemporal_store(acc[c], (V *)(a.out[w] + o));
+                if constexpr (W == 0) {
+                    // keep the loads: a value that is never the row's own is never stored
+                    if (acc[c][0] == 1.2345e-38f && acc[c][1] == -1.2345e-38f) a.out[0][0] = acc[c][2];
+                }
+            }
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_probe(int reads, int writes, const ProbeArgs &a, hipStream_t st) {
+    const int grid = (int)((a.rows + a.rows_per_block - 1) / a.rows_per_block);
+#define HAP_PROBE(RR, WW)                                                                 \
+    if (reads == RR && writes == WW) {                                                    \
+        hipLaunchKernelGGL((probe_kernel<RR, WW>), dim3(grid), dim3(512), 0, st, a);      \
+        return hipGetLastError();                                                         \
+    }
+    HAP_PROBE(1, 0)
+    HAP_PROBE(1, 1)
+    HAP_PROBE(2, 2)
+    HAP_PROBE(3, 2)
+#undef HAP_PROBE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_points_check(const float *S, int64_t lds, const float *X, int64_t ldx, int d, const PairSample &ps,
+                               int32_t *bad, hipStream_t st) {
+    hipLaunchKernelGGL(points_check_kernel, dim3(1), dim3(64), 0, st, S, lds, X, ldx, d, ps, bad);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_pref(void *pref_base, int64_t ldw, int n, int levels, int dtype, const double *value_dev,
                             hipStream_t st) {
@@ -104,10 +188,10 @@ hipError_t launch_fill_pref(void *pref_base, int64_t ldw, int n, int levels, int
     return hipGetLastError();
 }
 
-hipError_t launch_count_distinct(const int32_t *labels, int n, int32_t *mark, int32_t *out, hipStream_t st) {
+hipError_t launch_count_distinct(const int32_t *labels, int rows, int n, int32_t *mark, int32_t *out, hipStream_t st) {
     const int grid = (n + 255) / 256;
     hipLaunchKernelGGL(zero_i32, dim3(grid), dim3(256), 0, st, mark, n);
-    hipLaunchKernelGGL(mark_labels, dim3(grid), dim3(256), 0, st, labels, n, mark);
+    hipLaunchKernelGGL(mark_labels, dim3((rows + 255) / 256), dim3(256), 0, st, labels, rows, n, mark);
     hipLaunchKernelGGL(sum_marks, dim3(1), dim3(1024), 0, st, mark, n, out);
     return hipGetLastError();
 }

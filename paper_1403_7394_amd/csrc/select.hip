@@ -203,6 +203,7 @@ hipError_t median_impl(const T *S, int64_t n, int64_t lds, void *scratch, double
 
 size_t select_scratch_bytes() { return (sizeof(SelectState) + 255) & ~size_t(255); }
 
+
 hipError_t launch_median_offdiag(const void *S, int64_t n, int64_t lds, int dtype, void *scratch,
                                  double *median_dev, hipStream_t st) {
     if (dtype == HAP_F32) return median_impl<float>((const float *)S, n, lds, scratch, median_dev, st);

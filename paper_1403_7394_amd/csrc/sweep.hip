@@ -567,6 +567,7 @@ struct FinArgs {
     T *phi_out;
     const T *delta;      // Eq. 2.7 row offsets of this level's s, or nullptr
     int n, t;
+    int rows;            // rows [0, rows) are the updated ones (one block of a run split by rows)
     T lam, oml;
     DevState *ds;
 };
@@ -648,7 +649,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs<T> a) {
         if (a.labels) a.labels[i] = ck;
         if (a.c_out) a.c_out[i] = cv;
         if (a.phi_out) a.phi_out[i] = mx;
-        if (a.E && a.t >= 2 && a.E[i] != ck) atomicOr(&a.ds->final_changed, 1);
+        // only the updated rows take part in the stop rule (the others keep their initial labels)
+        if (a.E && a.t >= 2 && i < a.rows && a.E[i] != ck) atomicOr(&a.ds->final_changed, 1);
     }
 }
 
@@ -790,7 +792,7 @@ hipError_t launch_colsum(const T *Qpart, int64_t ldw, int nb, int n, const Level
 template <typename T>
 hipError_t launch_finalize(const T *S, int64_t lds, const LevelPtrs<T> &lv, int n, int64_t ldw, double lam, int t,
                            int32_t *labels_out, T *alpha_out, int64_t lda, T *c_out, T *phi_out, DevState *ds,
-                           hipStream_t st, const T *delta) {
+                           hipStream_t st, const T *delta, int rows) {
     FinArgs<T> a;
     a.S = S;
     a.lds = lds;
@@ -808,6 +810,7 @@ hipError_t launch_finalize(const T *S, int64_t lds, const LevelPtrs<T> &lv, int 
     a.delta = delta;
     a.n = n;
     a.t = t;
+    a.rows = rows > 0 ? rows : n;
     a.lam = (T)lam;
     a.oml = (T)(1.0 - lam);
     a.ds = ds;
@@ -832,7 +835,7 @@ hipError_t launch_alpha_pad(T *A, int64_t rows, int n, int64_t ldw, hipStream_t 
     template hipError_t launch_colsum<T>(const T *, int64_t, int, int, const LevelPtrs<T> &, const LevelPtrs<T> *, \
                                          T *, bool, bool, int, bool, DevState *, hipStream_t);                    \
     template hipError_t launch_finalize<T>(const T *, int64_t, const LevelPtrs<T> &, int, int64_t, double, int,   \
-                                           int32_t *, T *, int64_t, T *, T *, DevState *, hipStream_t, const T *);
+                                           int32_t *, T *, int64_t, T *, T *, DevState *, hipStream_t, const T *, int);
 HAP_INSTANTIATE(float)
 HAP_INSTANTIATE(double)
 #undef HAP_INSTANTIATE

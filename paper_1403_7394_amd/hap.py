@@ -25,7 +25,7 @@ SCHEDULE_SEQUENTIAL, SCHEDULE_MRHAP = 0, 1
 # every symbol include/hap.h declares
 EXPORTS = (
     "hap_version", "hap_status_string", "hap_last_error", "hap_build_similarity",
-    "hap_median_offdiag", "hap_workspace_size", "hap_init", "hap_iterate", "hap_exemplars",
+    "hap_median_offdiag", "hap_bandwidth_probe", "hap_workspace_size", "hap_init", "hap_iterate", "hap_exemplars",
     "hap_net_similarity", "hap_preference", "hap_read_messages", "hap_similarity_offsets", "hap_set_launch",
     "hap_set_points", "hap_set_row_count", "hap_get_row_count",
     "hap_get_launch", "hap_profile", "hap_profile_read", "hap_destroy",
@@ -72,6 +72,7 @@ def _declare(lib):
         "hap_last_error": (ctypes.c_char_p, []),
         "hap_build_similarity": (I32, [V, I64, I64, I64, I32, V, I64, I32, I32, D, U64, V]),
         "hap_median_offdiag": (I32, [V, I64, I64, I32, _c_dblp, V]),
+        "hap_bandwidth_probe": (I32, [I32, I32, ctypes.POINTER(V), ctypes.POINTER(V), I64, I64, I64, I64, V]),
         "hap_workspace_size": (I32, [I64, I32, I32, ctypes.POINTER(SZ)]),
         "hap_init": (I32, [ctypes.POINTER(V), V, I64, I64, I32, ctypes.POINTER(hap_params), V, SZ, V]),
         "hap_iterate": (I32, [V, I32, I32, _c_i32p, _c_i32p]),
@@ -80,7 +81,7 @@ def _declare(lib):
         "hap_preference": (I32, [V, _c_dblp]),
         "hap_read_messages": (I32, [V, I32, V, V, I64, V, V, V]),
         "hap_set_launch": (I32, [V, I32, I32, I32, I32]),
-        "hap_set_points": (I32, [V, V, I64, I64, I32]),
+        "hap_set_points": (I32, [V, V, I64, I64, I64, I32]),
         "hap_set_row_count": (I32, [V, I64]),
         "hap_get_row_count": (I32, [V, ctypes.POINTER(I64)]),
         "hap_get_launch": (I32, [V, _c_i32p, _c_i32p, _c_i32p, _c_i32p]),
@@ -174,6 +175,26 @@ def median_offdiag(S, stream=None) -> float:
     _check("hap_median_offdiag", lib.hap_median_offdiag(
         ctypes.c_void_p(S.data_ptr()), S.shape[0], _ld(S), _dtype_code(S), ctypes.byref(out), _stream(stream)))
     return out.value
+
+
+def bandwidth_probe(inputs, outputs, sink=None, rows_per_block: int = 32, stream=None) -> None:
+    """hap_bandwidth_probe: reads the 2-D FP32 device tensors `inputs` and writes `outputs`, all
+    of one shape and row stride.  With no outputs (the pure-read mix) `sink` is a one-element
+    FP32 device tensor the kernel may store to."""
+    import torch
+    lib = load()
+    rows, cols = inputs[0].shape
+    ld = _ld(inputs[0])
+    for t in list(inputs) + list(outputs):
+        if t.dtype != torch.float32 or tuple(t.shape) != (rows, cols) or _ld(t) != ld or not t.is_cuda:
+            raise ValueError("bandwidth_probe: every array must be an FP32 device tensor of the same shape and stride")
+    if not outputs and (sink is None or sink.dtype != torch.float32 or sink.numel() < 1 or not sink.is_cuda):
+        raise ValueError("bandwidth_probe: the pure-read mix needs a one-element FP32 device sink")
+    ins = (ctypes.c_void_p * 3)(*[ctypes.c_void_p(t.data_ptr()) for t in inputs])
+    targets = list(outputs) if outputs else [sink]
+    outs = (ctypes.c_void_p * 2)(*[ctypes.c_void_p(t.data_ptr()) for t in targets])
+    _check("hap_bandwidth_probe", lib.hap_bandwidth_probe(len(inputs), len(outputs), ins, outs, rows, cols,
+                                                          ld, rows_per_block, _stream(stream)))
 
 
 def workspace_size(n: int, levels: int, dtype_code: int) -> int:
@@ -330,13 +351,14 @@ class Hap:
 
     def set_points(self, X=None):
         """Points mode: the row pass recomputes s_ij from X (the FP32 points S was built from
-        with BUILD_DIRECT, no noise) instead of reading S.  None switches it off."""
+        with BUILD_DIRECT, no noise) instead of reading S.  None switches it off.  The library
+        refuses points whose count differs from n or whose sampled distances differ from S."""
         if X is None:
-            _check("hap_set_points", self._lib.hap_set_points(self._ctx, None, 0, 0, 0))
+            _check("hap_set_points", self._lib.hap_set_points(self._ctx, None, 0, 0, 0, 0))
             self._points_keep = None
             return
-        _check("hap_set_points", self._lib.hap_set_points(self._ctx, ctypes.c_void_p(X.data_ptr()), X.shape[1],
-                                                          _ld(X), _dtype_code(X)))
+        _check("hap_set_points", self._lib.hap_set_points(self._ctx, ctypes.c_void_p(X.data_ptr()), X.shape[0],
+                                                          X.shape[1], _ld(X), _dtype_code(X)))
         self._points_keep = X
 
     def profile(self, enable, every: int = 1):

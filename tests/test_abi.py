@@ -97,6 +97,10 @@ def test_null_context_calls_fail_cleanly(lib):
     assert lib.hap_destroy(None) == hap.HAP_OK
     d = ctypes.c_double()
     assert lib.hap_net_similarity(None, 0, None, 0, 0, 0, ctypes.byref(d)) == hap.HAP_E_ARG
+    fake = ctypes.c_void_p(4096)
+    assert lib.hap_set_points(None, fake, 100, 2, 2, hap.HAP_F32) == hap.HAP_E_ARG
+    assert lib.hap_set_row_count(None, 10) == hap.HAP_E_ARG
+    assert lib.hap_set_launch(None, 256, 1, 1, 0) == hap.HAP_E_ARG
 
 
 def test_build_and_median_check_arguments(lib):
@@ -161,3 +165,19 @@ def test_batch_planning_checks_arguments(lib):
     assert not out.value
     assert lib.hap_batch_set_launch(None, 512, 1, 4) == hap.HAP_E_ARG
     assert lib.hap_batch_destroy(None) == hap.HAP_OK
+
+
+def test_bandwidth_probe_checks_arguments(lib):
+    fake = (ctypes.c_void_p * 3)(4096, 8192, 12288)     # never dereferenced: every call fails its checks
+    outs = (ctypes.c_void_p * 2)(16384, 20480)
+    assert lib.hap_bandwidth_probe(2, 1, fake, outs, 64, 64, 64, 32, None) == hap.HAP_E_ARG     # mix
+    assert lib.hap_bandwidth_probe(1, 1, fake, outs, 64, 63, 64, 32, None) == hap.HAP_E_ARG     # cols % 4
+    assert lib.hap_bandwidth_probe(1, 1, fake, outs, 64, 64, 60, 32, None) == hap.HAP_E_ARG     # ld < cols
+    assert lib.hap_bandwidth_probe(1, 1, fake, outs, 64, 8196, 8196, 32, None) == hap.HAP_E_UNSUPPORTED
+    assert lib.hap_bandwidth_probe(1, 0, fake, None, 64, 64, 64, 32, None) == hap.HAP_E_ARG     # no sink
+    import torch
+    a = torch.zeros((8, 8))
+    with pytest.raises(ValueError):
+        hap.bandwidth_probe([a], [])                       # host tensors, no sink: refused before the call
+    with pytest.raises(ValueError):
+        hap.bandwidth_probe([a], [torch.zeros((8, 4))])    # shapes differ

@@ -78,3 +78,33 @@ def test_full_run_against_oracle_labels(hap_gpu):
         else:
             cnt = np.array([len(np.unique(g[l])) for l in range(L)])
             assert np.all(cnt >= lo / 2) and np.all(cnt <= hi * 2), (t, cnt, lo, hi)
+
+
+def test_full_run_row_ordered_launch_is_the_fp32_oracle(hap_gpu):
+    """The benchmark's run (points mode, 500 iterations) with one row per workgroup, which sums
+    every column in row order as the FP32 evaluation of the oracle does: labels identical to
+    the stored FP32 oracle labels at every checkpoint, net similarity within 1e-12."""
+    o32 = _oracle("float32")
+    ts = [int(t) for t in o32["checkpoints"]]
+    b, rp = synth.workload_plain_f32()
+    n, L = b.X.shape[0], rp.levels
+    X = torch.from_numpy(b.X).to(DEV)
+    S = torch.empty((n, n), dtype=torch.float32, device=DEV)
+    hap_gpu.build_similarity(X, S)
+    h = hap_gpu.Hap(S, L, rp.damping)
+    h.set_points(X)
+    h.set_launch(rows_per_block=1)
+    assert h.get_launch()[2] == 1
+    assert h.preference() == [float(o32["pref"])] * L
+    prev = 0
+    for k, t in enumerate(ts):
+        h.iterate(t - prev, 0)
+        prev = t
+        g = h.labels().cpu().numpy()
+        ns = np.array([h.net_similarity(l) for l in range(L)])
+        ref = o32["labels"][k]
+        print(f"t={t}: exemplars {[len(np.unique(g[l])) for l in range(L)]}, "
+              f"equal to the FP32 oracle: {[bool(np.array_equal(g[l], ref[l])) for l in range(L)]}", flush=True)
+        assert np.array_equal(g, ref), (t, _agree(g, ref))
+        assert np.all(np.abs(ns - o32["net_similarity"][k]) <= 1e-12 * np.abs(o32["net_similarity"][k])), t
+    h.close()

@@ -45,3 +45,34 @@ def test_image_style_run_bit_identical(hap_gpu, n, dt, T):
     for l in range(L):
         assert np.array_equal(msgs[l]["rho"], r.state.rho[l]), l
         assert np.array_equal(msgs[l]["alpha"], r.state.alpha[l]), l
+
+
+def test_image_style_run_at_the_papers_size_is_the_fp32_oracle(hap_gpu):
+    """The image-style run at the size of the paper's first image (10,609 pixels, L = 3,
+    damping 0.5, 30 iterations; Section 4), built on the GPU from the pixels with the negative
+    Euclidean build and run with row-ordered column sums: labels identical to the stored FP32
+    oracle run (`tests/golden/image_run_10609.py`) at every checkpoint, net similarity within
+    1e-12."""
+    from pathlib import Path
+    with np.load(Path(__file__).resolve().parent / "golden" / "image_run_10609_oracle_float32.npz") as z:
+        gold = {k: z[k] for k in z.files}
+    b, prefs, rp = synth.workload_image("mandrill")
+    n, L = b.X.shape[0], rp.levels
+    assert int(gold["n"]) == n
+    X = torch.from_numpy(b.X).to(DEV)
+    ld = n + (-n) % 4
+    S = torch.empty((n, ld), dtype=torch.float32, device=DEV)[:, :n]
+    hap_gpu.build_similarity(X, S, mode=hap_gpu.BUILD_DIRECT_L2)
+    h = hap_gpu.Hap(S, L, rp.damping, pref=torch.from_numpy(prefs.astype(np.float32)).to(DEV))
+    h.set_launch(rows_per_block=1)
+    prev = 0
+    for k, t in enumerate(int(t) for t in gold["checkpoints"]):
+        h.iterate(t - prev)
+        prev = t
+        g = h.labels().cpu().numpy()
+        ns = np.array([h.net_similarity(l) for l in range(L)])
+        print(f"t={t}: exemplars {[len(np.unique(g[l])) for l in range(L)]}", flush=True)
+        assert np.array_equal(g, gold["labels"][k]), t
+        ref = gold["net_similarity"][k]
+        assert np.all(np.abs(ns - ref) <= 1e-12 * np.abs(ref)), (t, ns, ref)
+    h.close()

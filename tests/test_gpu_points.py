@@ -76,3 +76,41 @@ def test_points_mode_rejects_unsupported_inputs(hap_gpu):
     with pytest.raises(hap_gpu.HapError):
         h.set_points(Xt[:, :2].contiguous())    # FP64 context
     h.close()
+
+
+def test_points_mode_refuses_points_that_did_not_build_s(hap_gpu):
+    """hap_set_points takes the point count and spot-checks S against X: a short X, another
+    point set and another build of the same points are refused, and the context keeps
+    reading S (its results equal a context that never had points set)."""
+    b = synth.small_blobs(1302, 700, d=2, k=5, dtype=np.float32)
+    n = b.X.shape[0]
+    Xt = torch.from_numpy(b.X).to(DEV)
+    S = torch.empty((n, n), dtype=torch.float32, device=DEV)
+    hap_gpu.build_similarity(Xt, S)
+    h = hap_gpu.Hap(S, 2, 0.9)
+    with pytest.raises(hap_gpu.HapError) as e:
+        h.set_points(Xt[: n - 1].contiguous())             # n - 1 points
+    assert e.value.status == hap_gpu.HAP_E_ARG
+    with pytest.raises(hap_gpu.HapError) as e:
+        h.set_points(torch.roll(Xt, 1, dims=0).contiguous())  # the same points in another order
+    assert e.value.status == hap_gpu.HAP_E_ARG
+    S_gemm = torch.empty_like(S)
+    hap_gpu.build_similarity(Xt, S_gemm, mode=hap_gpu.BUILD_GEMM)
+    h_gemm = hap_gpu.Hap(S_gemm, 2, 0.9)
+    with pytest.raises(hap_gpu.HapError) as e:
+        h_gemm.set_points(Xt)                               # S from the Gram-matrix build
+    assert e.value.status == hap_gpu.HAP_E_ARG
+    h_gemm.close()
+    h.iterate(40)
+    refused = h.labels().cpu().numpy()
+    h.close()
+    h = hap_gpu.Hap(S, 2, 0.9)
+    h.iterate(40)
+    plain = h.labels().cpu().numpy()
+    h.close()
+    h = hap_gpu.Hap(S, 2, 0.9)
+    h.set_points(Xt)                                        # the right points are accepted
+    h.iterate(40)
+    accepted = h.labels().cpu().numpy()
+    h.close()
+    assert np.array_equal(refused, plain) and np.array_equal(accepted, plain)

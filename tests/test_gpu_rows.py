@@ -117,3 +117,28 @@ def test_whole_row_count_is_the_plain_run_and_bad_counts_fail(hap_gpu):
         with pytest.raises(hap_gpu.HapError):
             h.set_row_count(100)
         h.close()
+
+
+def test_block_stop_rule_at_the_cap_and_exemplar_count(hap_gpu):
+    """The stop rule and the exemplar count take the block's rows only: a block run that meets
+    the stop rule exactly at the cap reports it (the rows outside the block, whose labels
+    the finished availabilities would change, do not count), one iteration less does not,
+    and the counts are those of the block's labels."""
+    b = synth.separated_blobs(96, k=3, m=4)
+    S = sim.add_noise(sim.similarity(b.X), 1e-12, 96)
+    p = sim.median_offdiag(S)
+    n = S.shape[0]
+    rows, L, K = n - 1, 2, 10
+    r = hap_ref.hap(S, p, L, 0.5, 400, stable_iters=K, rows=rows)
+    assert r.converged
+    for cap, want in ((r.iters, True), (r.iters - 1, False)):
+        h = hap_gpu.Hap(_device_S(S), L, 0.5)
+        h.set_launch(rows_per_block=1)
+        h.set_row_count(rows)
+        res = h.iterate(cap, K)
+        assert bool(res.converged) == want and res.iters == cap, (cap, res)
+        if want:
+            lab = h.labels().cpu().numpy()
+            assert np.array_equal(lab[:, :rows], r.labels[:, :rows])
+            assert [h.exemplars(l)[1] for l in range(L)] == [len(np.unique(r.labels[l][:rows])) for l in range(L)]
+        h.close()
