@@ -146,6 +146,21 @@ HAP_API hap_status hap_build_similarity(const void *X, int64_t n, int64_t d, int
 HAP_API hap_status hap_median_offdiag(const void *S, int64_t n, int64_t lds, int32_t dtype,
                               double *out_host, void *stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid allocation): hap_median_offdiag without any allocation.  The median
+ * (same value, same kernels) is written to *median_dev (device double, 8-byte aligned); the
+ * call only enqueues kernels on the stream and does not synchronise.  Its radix-select state
+ * lives in a static device array of 8448 bytes that the library holds on every GPU it runs on
+ * until the process ends (looked up with hipGetSymbolAddress on the first call on each device,
+ * so make that first call outside graph capture; the device is the current one, which must be
+ * the stream's).  Every call on a GPU shares that GPU's array and
+ * clears it with a kernel first, so calls that overlap on one GPU (on different streams or
+ * threads) race and must not be issued.  Limits: 2 <= n <= 65536 (HAP_E_UNSUPPORTED above,
+ * the array's counters are 32-bit), the layout rules of the other calls (HAP_E_ARG).
+ */
+HAP_API hap_status hap_median_offdiag_noalloc(const void *S, int64_t n, int64_t lds, int32_t dtype,
+                                              double *median_dev, void *stream);
 
 /*
  * Bandwidth probe for the roofline: one kernel that reads `reads` arrays in[0..reads) and writes

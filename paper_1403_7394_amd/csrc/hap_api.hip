@@ -503,6 +503,24 @@ hap_status hap_median_offdiag(const void *S, int64_t n, int64_t lds, int32_t dty
     return HAP_OK;
 }
 
+hap_status hap_median_offdiag_noalloc(const void *S, int64_t n, int64_t lds, int32_t dtype, double *median_dev,
+                                      void *stream) {
+    if (!S || !median_dev) return fail_arg("hap_median_offdiag_noalloc: null pointer");
+    if (!dtype_ok(dtype)) return fail_arg("hap_median_offdiag_noalloc: dtype", HAP_E_DTYPE);
+    if (n < 2 || !ld_ok(n, lds, dtype)) return fail_arg("hap_median_offdiag_noalloc: bad sizes");
+    if (n > hap::kMaxSelectN)
+        return fail_arg("hap_median_offdiag_noalloc: n too large (at most 65536: the static scratch counts n(n-1) "
+                        "keys in 32 bits)",
+                        HAP_E_UNSUPPORTED);
+    if (((uintptr_t)median_dev & 7u) != 0) return fail_arg("hap_median_offdiag_noalloc: median_dev not 8-byte aligned");
+    void *scratch = nullptr;
+    hipError_t e = hap::static_scratch(&scratch);
+    if (e != hipSuccess) return fail_hip(e, "hap_median_offdiag_noalloc: hipGetSymbolAddress");
+    e = hap::launch_median_offdiag(S, n, lds, dtype, scratch, median_dev, (hipStream_t)stream);
+    if (e != hipSuccess) return fail_hip(e, "hap_median_offdiag_noalloc");
+    return HAP_OK;
+}
+
 hap_status hap_bandwidth_probe(int32_t reads, int32_t writes, const float *const *in, float *const *out, int64_t rows,
                                int64_t cols, int64_t ld, int64_t rows_per_block, void *stream) {
     const bool mix_ok = (reads == 1 && writes == 0) || (reads == 1 && writes == 1) || (reads == 2 && writes == 2) ||

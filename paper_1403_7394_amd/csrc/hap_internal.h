@@ -139,6 +139,10 @@ hipError_t launch_fill_pref(void *pref_base, int64_t ldw, int n, int levels, int
 // Radix select of the two middle off-diagonal order statistics; writes their FP64 mean,
 // rounded to the working type, to *median_dev (as double).
 size_t select_scratch_bytes();
+// Device address (on the current device) of the library's static select scratch, looked up with
+// hipGetSymbolAddress on the first call per device; its size in bytes.
+hipError_t static_scratch(void **out);
+size_t static_scratch_bytes();
 // Largest n the radix select takes: its histograms count up to n(n-1) keys in 32 bits.
 constexpr int64_t kMaxSelectN = 65536;
 hipError_t launch_median_offdiag(const void *S, int64_t n, int64_t lds, int dtype, void *scratch,

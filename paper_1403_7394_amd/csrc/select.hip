@@ -14,6 +14,8 @@
 // locates the digit holding rank k.  v[M/2] is then either equal to v[M/2-1]
 // (if the equal keys extend past rank k) or the smallest key above it, found by
 // one min-reduction pass.  Everything stays on the device; no host round trip.
+#include <mutex>
+
 #include "hap_internal.h"
 
 namespace hap {
@@ -203,6 +205,37 @@ hipError_t median_impl(const T *S, int64_t n, int64_t lds, void *scratch, double
 
 size_t select_scratch_bytes() { return (sizeof(SelectState) + 255) & ~size_t(255); }
 
+// Scratch of the allocation-free median (hap_median_offdiag_noalloc): one select state in a
+// file-scope device array, one copy per GPU, held until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it only stands for the symbol); it uses
+// the device address hipGetSymbolAddress returns, looked up once per device.
+constexpr size_t kStaticScratchBytes = 8448;
+static_assert(sizeof(SelectState) <= kStaticScratchBytes, "select state does not fit the static scratch");
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[dev] = ptr;
+    }
+    *out = g_scratch_addr[dev];
+    return hipSuccess;
+}
+
+size_t static_scratch_bytes() { return kStaticScratchBytes; }
 
 hipError_t launch_median_offdiag(const void *S, int64_t n, int64_t lds, int dtype, void *scratch,
                                  double *median_dev, hipStream_t st) {

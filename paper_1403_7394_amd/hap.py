@@ -25,7 +25,8 @@ SCHEDULE_SEQUENTIAL, SCHEDULE_MRHAP = 0, 1
 # every symbol include/hap.h declares
 EXPORTS = (
     "hap_version", "hap_status_string", "hap_last_error", "hap_build_similarity",
-    "hap_median_offdiag", "hap_bandwidth_probe", "hap_workspace_size", "hap_init", "hap_iterate", "hap_exemplars",
+    "hap_median_offdiag", "hap_median_offdiag_noalloc", "hap_bandwidth_probe", "hap_workspace_size", "hap_init",
+    "hap_iterate", "hap_exemplars",
     "hap_net_similarity", "hap_preference", "hap_read_messages", "hap_similarity_offsets", "hap_set_launch",
     "hap_set_points", "hap_set_row_count", "hap_get_row_count",
     "hap_get_launch", "hap_profile", "hap_profile_read", "hap_destroy",
@@ -72,6 +73,7 @@ def _declare(lib):
         "hap_last_error": (ctypes.c_char_p, []),
         "hap_build_similarity": (I32, [V, I64, I64, I64, I32, V, I64, I32, I32, D, U64, V]),
         "hap_median_offdiag": (I32, [V, I64, I64, I32, _c_dblp, V]),
+        "hap_median_offdiag_noalloc": (I32, [V, I64, I64, I32, V, V]),
         "hap_bandwidth_probe": (I32, [I32, I32, ctypes.POINTER(V), ctypes.POINTER(V), I64, I64, I64, I64, V]),
         "hap_workspace_size": (I32, [I64, I32, I32, ctypes.POINTER(SZ)]),
         "hap_init": (I32, [ctypes.POINTER(V), V, I64, I64, I32, ctypes.POINTER(hap_params), V, SZ, V]),
@@ -175,6 +177,15 @@ def median_offdiag(S, stream=None) -> float:
     _check("hap_median_offdiag", lib.hap_median_offdiag(
         ctypes.c_void_p(S.data_ptr()), S.shape[0], _ld(S), _dtype_code(S), ctypes.byref(out), _stream(stream)))
     return out.value
+
+
+def median_offdiag_noalloc(S, out, stream=None) -> None:
+    """hap_median_offdiag_noalloc: the median into `out` (a float64 device tensor of one element),
+    enqueued on the stream without any allocation or synchronisation."""
+    lib = load()
+    _check("hap_median_offdiag_noalloc", lib.hap_median_offdiag_noalloc(
+        ctypes.c_void_p(S.data_ptr()), S.shape[0], _ld(S), _dtype_code(S), ctypes.c_void_p(out.data_ptr()),
+        _stream(stream)))
 
 
 def bandwidth_probe(inputs, outputs, sink=None, rows_per_block: int = 32, stream=None) -> None:
