@@ -79,21 +79,72 @@ __device__ __forceinline__ void argmax_merge(T &v, int &k, T ov, int ok) {
     k = take ? ok : k;
 }
 
-template <typename T, bool WITH_C>
-__device__ __forceinline__ void wave_reduce(T &m1, int &k1, T &m2, T &cv, int &ck) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const T om1 = __shfl_xor(m1, off, 64);
-        const int ok1 = __shfl_xor(k1, off, 64);
-        const T om2 = __shfl_xor(m2, off, 64);
-        top2_merge(m1, k1, m2, om1, ok1, om2);
-        if constexpr (WITH_C) {
-            const T ocv = __shfl_xor(cv, off, 64);
-            const int ock = __shfl_xor(ck, off, 64);
-            argmax_merge(cv, ck, ocv, ock);
-        }
+// One DPP lane move of a 32-bit value; lanes whose source row is masked off get `old`.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_i32(int old, int v) {
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROW_MASK, 0xf, false);
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_val(float old, float v) {
+    return __int_as_float(dpp_i32<CTRL, ROW_MASK>(__float_as_int(old), __float_as_int(v)));
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_val(double old, double v) {
+    const long long o = __double_as_longlong(old), x = __double_as_longlong(v);
+    const int lo = dpp_i32<CTRL, ROW_MASK>((int)(o & 0xffffffffll), (int)(x & 0xffffffffll));
+    const int hi = dpp_i32<CTRL, ROW_MASK>((int)(o >> 32), (int)(x >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One step of the wave reduction: merge every lane's triple with the lane DPP control CTRL names
+// (lanes of masked-off rows merge with the identity, which leaves them unchanged).
+template <typename T, bool WITH_C, int CTRL, int ROW_MASK>
+__device__ __forceinline__ void reduce_step(T &m1, int &k1, T &m2, T &cv, int &ck) {
+    const T ninf = neg_inf<T>();
+    const T om1 = dpp_val<CTRL, ROW_MASK>(ninf, m1);
+    const int ok1 = dpp_i32<CTRL, ROW_MASK>(INT_MAX, k1);
+    const T om2 = dpp_val<CTRL, ROW_MASK>(ninf, m2);
+    top2_merge(m1, k1, m2, om1, ok1, om2);
+    if constexpr (WITH_C) {
+        const T ocv = dpp_val<CTRL, ROW_MASK>(ninf, cv);
+        const int ock = dpp_i32<CTRL, ROW_MASK>(INT_MAX, ck);
+        argmax_merge(cv, ck, ocv, ock);
     }
 }
+
+// Wave-wide (max, lowest argmax, second max) and (max, lowest argmax) with DPP lane moves:
+// pairs, quads, 8-lane halves and 16-lane rows by quad permutes and mirrors, then the rows by
+// two row broadcasts, which leave the whole wave's result in lane 63; it is read back into
+// every lane.  The merges are exact and order-independent, so any tree gives the same bits.
+template <typename T, bool WITH_C>
+__device__ __forceinline__ void wave_reduce(T &m1, int &k1, T &m2, T &cv, int &ck) {
+    reduce_step<T, WITH_C, 0xb1, 0xf>(m1, k1, m2, cv, ck);    // quad_perm [1,0,3,2]
+    reduce_step<T, WITH_C, 0x4e, 0xf>(m1, k1, m2, cv, ck);    // quad_perm [2,3,0,1]
+    reduce_step<T, WITH_C, 0x141, 0xf>(m1, k1, m2, cv, ck);   // row_half_mirror
+    reduce_step<T, WITH_C, 0x140, 0xf>(m1, k1, m2, cv, ck);   // row_mirror
+    reduce_step<T, WITH_C, 0x142, 0xa>(m1, k1, m2, cv, ck);   // row_bcast:15 into rows 1, 3
+    reduce_step<T, WITH_C, 0x143, 0xc>(m1, k1, m2, cv, ck);   // row_bcast:31 into rows 2, 3
+    if constexpr (sizeof(T) == 4) {
+        m1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m1), 63));
+        m2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m2), 63));
+        if constexpr (WITH_C) cv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cv), 63));
+    } else {
+        auto rl = [](double v) {
+            const long long x = __double_as_longlong(v);
+            const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), 63);
+            const int hi = __builtin_amdgcn_readlane((int)(x >> 32), 63);
+            return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+        };
+        m1 = rl(m1);
+        m2 = rl(m2);
+        if constexpr (WITH_C) cv = rl(cv);
+    }
+    k1 = __builtin_amdgcn_readlane(k1, 63);
+    if constexpr (WITH_C) ck = __builtin_amdgcn_readlane(ck, 63);
+}
+
+// Rows whose per-row scalars are staged in LDS at a time.
+constexpr int kWin = 64;
 
 template <typename T, int NT, int NCH>
 struct RowRegs {
@@ -105,8 +156,8 @@ struct RowRegs {
 // from initialisation and stay -inf or NaN, which '>' and fmax ignore.  Padding columns of
 // R, A and the column partials are never read back as results.
 //
-// D < 0: the row offset a.delta[i] of the optional level-wise similarity update (Eq. 2.7)
-// is added to the S values read.  (D > 0, the points mode, has its own row pass below.)
+// (D < 0, the optional level-wise similarity update of Eq. 2.7, adds the row offset where the
+// row is used; D > 0, the points mode, has its own row pass below.)
 template <typename T, int NT, int NCH, bool TAIL, int D>
 __device__ __forceinline__ void load_row(const SweepArgs<T> &a, int i, RowRegs<T, NT, NCH> &x) {
     using V = typename Vec<T>::type;
@@ -120,7 +171,6 @@ __device__ __forceinline__ void load_row(const SweepArgs<T> &a, int i, RowRegs<T
         if (!TAIL || j0 < a.n) {
             // S streams through once per level: non-temporal, so it does not displace R/A lines
             x.s[c] = __builtin_nontemporal_load((const V *)(Srow + j0));
-            if constexpr (D < 0) x.s[c] = x.s[c] + a.delta[i];   // Eq. 2.7 row offset
             x.r[c] = *(const V *)(Rrow + j0);
             x.a[c] = *(const V *)(Arow + j0);
         } else {
@@ -149,14 +199,38 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, c
     const T lam = a.lam, oml = a.oml;
     const T zero = T(0), ninf = neg_inf<T>();
 
-    RowRegs<T, NT, NCH> x;
+    // The next row's S, rho and alpha are loaded into a second register set while a row is
+    // computed.  The per-row scalars (preference, tau, the Eq. 2.7 offset, the previous label)
+    // of up to kWin rows are staged in LDS at the start of each window, so that no global load
+    // issued after the prefetch has to be waited for inside a row (vector memory operations
+    // complete in issue order).
+    RowRegs<T, NT, NCH> x, y;
     int buf = 0;
     int chg = 0;   // a label of this workgroup's rows changed (thread 0; one atomic per workgroup)
+    __shared__ T st_p[kWin], st_tau[kWin], st_d[kWin];
+    __shared__ int st_e[kWin], st_has[kWin];
+    if (row0 < row1) load_row<T, NT, NCH, TAIL, D>(a, row0, y);
     for (int i = row0; i < row1; ++i, buf ^= 1) {
-        load_row<T, NT, NCH, TAIL, D>(a, i, x);
+        const int r = (i - row0) % kWin;
+        if (r == 0) {
+            __syncthreads();
+            const int k = i + tid;
+            if (tid < kWin && k < row1) {
+                st_p[tid] = a.pref[k];
+                T tv = zero;
+                st_has[tid] = row_tau(a, k, t, tv) ? 1 : 0;
+                st_tau[tid] = tv;
+                st_d[tid] = (D < 0) ? a.delta[k] : zero;
+                st_e[tid] = a.E[k];
+            }
+            __syncthreads();
+        }
+        x = y;
+        if (i + 1 < row1) load_row<T, NT, NCH, TAIL, D>(a, i + 1, y);
         T *Rrow = a.R + (int64_t)i * ldw;
         T *Arow = a.A + (int64_t)i * ldw;
-        const T p_i = a.pref[i];
+        const T p_i = st_p[r];
+        const T d_i = st_d[r];   // Eq. 2.7 row offset (D < 0)
         // Column indices are handled relative to this thread's base tid*VW: element (c, v) is
         // column base + c*NT*VW + v, so compares and selects use compile-time offsets.
         const int base = tid * VW;
@@ -171,7 +245,7 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, c
             for (int v = 0; v < VW; ++v) {
                 const int j = c * NT * VW + v;
                 const bool diag = dcol == j;
-                const T sj = diag ? p_i : x.s[c][v];
+                const T sj = diag ? p_i : ((D < 0) ? x.s[c][v] + d_i : x.s[c][v]);
                 x.s[c][v] = sj;
                 const T rj = x.r[c][v];
                 T al = x.a[c][v];
@@ -207,7 +281,13 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, c
                 sh_ck[buf][wid] = ck;
             }
         }
-        __syncthreads();
+        // LDS exchange of the wave results: wait for this wave's LDS writes only (not for the
+        // prefetch and the stores in flight, which __syncthreads would also wait for), then the
+        // barrier; the empty asm statements keep the LDS accesses on their side of it
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
         m1 = sh_m1[buf][0];
         k1 = sh_k1[buf][0];
         m2 = sh_m2[buf][0];
@@ -220,7 +300,7 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, c
                 for (int w = 1; w < NW; ++w) argmax_merge(cv, ck, sh_cv[buf][w], sh_ck[buf][w]);
                 a.C[i] = cv;
                 if (a.phi_down) a.phi_down[i] = m1;
-                const int old = a.E[i];
+                const int old = st_e[r];
                 a.E[i] = ck;
                 chg |= (t >= 3 && old != ck) ? 1 : 0;
             }
@@ -231,8 +311,8 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, c
         // recomputed here instead of being kept alive across the barrier.
         asm volatile("" : "+v"(dcol));
         const int k1r = k1 - base;
-        T tau_i = zero;
-        const bool has_tau = row_tau(a, i, t, tau_i);
+        const T tau_i = st_tau[r];
+        const bool has_tau = st_has[r] != 0;
         if (a.tau_store && tid == 0) a.tau_store[i] = has_tau ? tau_i : pos_inf<T>();
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
@@ -253,42 +333,18 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, c
     if (chg) atomicOr(&a.ds->changed, 1);
 }
 
-typedef __attribute__((address_space(3))) void lds_void_t;
-
-// Points mode with the rho and alpha rows prefetched one row ahead into LDS by DMA
-// (global_load_lds, 16 bytes per lane; lane l of a wave writes 16 bytes at the wave's LDS
-// base + 16 l, so each thread later reads back exactly the 16 bytes its lane fetched).  The
-// per-row scalars (preference, coordinates of point i, tau_i, the previous label) of up to
-// kWin rows are staged in LDS at the start of each window, so no global load sits inside a
-// row: the only wait at the top of a row is for its own prefetch, issued one row earlier.
-constexpr int kWin = 64;
-
+// Points mode: s_ij is recomputed from the coordinates (the thread's column coordinates stay
+// in registers), and the next row's rho and alpha are loaded into registers while a row is
+// computed.  The per-row scalars (preference, coordinates of point i, tau_i, the previous
+// label) of up to kWin rows are staged in LDS at the start of each window, so no global load
+// issued after the prefetch has to be waited for inside a row.
 template <typename T, int NT, int NCH, int D>
 struct PointsLds {
-    T row[2][2][NCH][NT * Vec<T>::N];   // [buffer][rho, alpha][chunk][column]
     T p[kWin];
     T tau[kWin];
     T x[kWin][D > 0 ? D : 1];
     int e[kWin];
 };
-
-template <typename T, int NT, int NCH, bool TAIL>
-__device__ __forceinline__ void prefetch_rows(const SweepArgs<T> &a, int i, T (*dst)[NCH][NT * Vec<T>::N]) {
-    constexpr int VW = Vec<T>::N;
-    const int tid = threadIdx.x, wave = tid >> 6;
-    const T *Rrow = a.R + (int64_t)i * a.ldw;
-    const T *Arow = a.A + (int64_t)i * a.ldw;
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-        const int j0 = c * NT * VW + tid * VW;
-        if (!TAIL || j0 < a.n) {
-            __builtin_amdgcn_global_load_lds((const void *)(Rrow + j0), (lds_void_t *)(&dst[0][c][wave * 64 * VW]), 16,
-                                             0, 0);
-            __builtin_amdgcn_global_load_lds((const void *)(Arow + j0), (lds_void_t *)(&dst[1][c][wave * 64 * VW]), 16,
-                                             0, 0);
-        }
-    }
-}
 
 template <typename T, int NT, int NCH, bool FIRST, bool TAIL, int D>
 __device__ __forceinline__ void sweep_rows_points(const SweepArgs<T> &a, const int t, const int row0, const int row1,
@@ -321,7 +377,24 @@ __device__ __forceinline__ void sweep_rows_points(const SweepArgs<T> &a, const i
         for (int v = 0; v < VW; ++v)
 #pragma unroll
             for (int d = 0; d < D; ++d) asm volatile("" ::"v"(cp.x[c][v][d]));
-    if (row0 < row1) prefetch_rows<T, NT, NCH, TAIL>(a, row0, L.row[0]);
+    // rho and alpha of the next row are loaded into registers while this row is computed
+    V yr[NCH], ya[NCH];
+    auto fetch = [&](int row) {
+        const T *Rr = a.R + (int64_t)row * ldw;
+        const T *Ar = a.A + (int64_t)row * ldw;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int j0 = c * NT * VW + tid * VW;
+            if (!TAIL || j0 < n) {
+                yr[c] = *(const V *)(Rr + j0);
+                ya[c] = *(const V *)(Ar + j0);
+            } else {
+                yr[c] = (V)(zero);
+                ya[c] = (V)(ninf);
+            }
+        }
+    };
+    if (row0 < row1) fetch(row0);
     for (int i = row0; i < row1; ++i, buf ^= 1) {
         const int r = (i - row0) % kWin;
         if (r == 0) {
@@ -337,23 +410,12 @@ __device__ __forceinline__ void sweep_rows_points(const SweepArgs<T> &a, const i
             }
             __syncthreads();
         }
-        // this row's rho and alpha from the prefetch buffer, then the next row's prefetch.  The
-        // compiler does not order LDS reads after an asynchronous LDS DMA, so the wait for it
-        // is explicit (it also covers the row's earlier stores; the prefetch had the whole
-        // previous row to land), and the memory clobber keeps the reads below it.
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            const int j0 = c * NT * VW + tid * VW;
-            if (!TAIL || j0 < n) {
-                x.r[c] = *(const V *)(&L.row[buf][0][c][tid * VW]);
-                x.a[c] = *(const V *)(&L.row[buf][1][c][tid * VW]);
-            } else {
-                x.r[c] = (V)(zero);
-                x.a[c] = (V)(ninf);
-            }
+            x.r[c] = yr[c];
+            x.a[c] = ya[c];
         }
-        if (i + 1 < row1) prefetch_rows<T, NT, NCH, TAIL>(a, i + 1, L.row[buf ^ 1]);
+        if (i + 1 < row1) fetch(i + 1);
         // s_ij from the coordinates, with the direct build's arithmetic
         double xi[D];
 #pragma unroll
