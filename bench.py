@@ -175,8 +175,10 @@ def run_precision_form(args, torch, hap, synth) -> dict:
 def run_batched_form(args, torch, hap, synth) -> dict:
     """Batched form: 512 independent problems (N ~ U{64..2048}, d=16, L=3, damping 0.8,
     200 iterations) in one persistent launch, against the plain single-problem path run
-    problem by problem on the same GPU (with its column sums in row order, the batch's
-    order, so the two compute the same trajectory)."""
+    problem by problem on the same GPU (with the column sums in the batch's order: row order
+    for a problem one workgroup runs, member order of row blocks for a problem a gang shares,
+    so the two compute the same trajectory).  The autotuner picks the launch shape and the
+    split of the large problems over gangs of workgroups."""
     import numpy as np
 
     from paper_1403_7394_amd import autotune
@@ -187,7 +189,15 @@ def run_batched_form(args, torch, hap, synth) -> dict:
     X = torch.from_numpy(np.concatenate([b.X for b in problems])).to(dev)
     L = rp.levels
     bt = hap.HapBatch(sizes, 16, L)
-    shape = autotune.tune_batch(bt, X, rp.damping)
+    if args.batch_split:
+        shape = tuple(int(v) for v in args.batch_launch.split(","))
+        bt.set_launch(*shape)
+        bt.set_split(*(int(v) for v in args.batch_split.split(",")))
+        shape = shape + bt.get_split()
+    else:
+        shape = autotune.tune_batch(bt, X, rp.damping)
+    members, rows = bt.members()
+    print(json.dumps({"form": "batched", "step": "tuned", "launch": shape}), file=sys.stderr, flush=True)
     out = bt.outputs(dev)
     bt.run(X, rp.damping, iters, out=out)          # warm-up
     torch.cuda.synchronize()
@@ -198,39 +208,94 @@ def run_batched_form(args, torch, hap, synth) -> dict:
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / reps
     labels_b, ns_b, iters_b = out
-    # the plain path, one problem after another, with one reused workspace and S buffer
+    print(json.dumps({"form": "batched", "step": "batch timed", "s": t_batch}), file=sys.stderr, flush=True)
+    # the plain path, one problem after another, with one reused workspace and S buffer: timed at its
+    # default launch (the speed baseline), and on a sample of problems run with the batch's
+    # column-sum order (row order for a problem one workgroup runs, member order of row blocks for
+    # a problem a gang shares), where the two must give identical labels
     nmax = max(sizes)
     S = torch.empty((nmax, nmax), dtype=torch.float32, device=dev)
     ws = torch.empty(hap.workspace_size(nmax, L, hap.HAP_F32), dtype=torch.uint8, device=dev)
-    agree, ns_rel = [], []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for bidx, prob in enumerate(problems):
+
+    def plain(bidx, rows_per_block=0):
         n = sizes[bidx]
         o = bt.offsets[bidx]
         Sv = S[:n, :n]
         hap.build_similarity(X[o:o + n], Sv)
         h = hap.Hap(Sv, L, rp.damping, workspace=ws)
-        h.set_launch(rows_per_block=1)     # column sums in row order, as inside the batch
+        if rows_per_block:
+            h.set_launch(rows_per_block=rows_per_block)
         h.iterate(iters, 0)
         lab = h.labels()
         ns = h.net_similarity(-1)
         h.close()
-        mism = int((lab != bt.labels_of(labels_b, bidx)).sum().item())
-        agree.append(1.0 - mism / lab.numel())
-        ns_rel.append(abs(ns - ns_b[bidx, L].item()) / abs(ns))
+        return lab, ns
+
+    agree_default = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for bidx in range(len(problems)):
+        lab, _ = plain(bidx)
+        agree_default.append(float((lab == bt.labels_of(labels_b, bidx)).float().mean().item()))
+        if bidx % 128 == 127:
+            print(json.dumps({"form": "batched", "step": f"plain path {bidx + 1}/{len(problems)}",
+                              "s": time.perf_counter() - t0}), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
+    split_ids = [b for b in range(len(sizes)) if members[b] > 1]
+    whole_ids = [b for b in range(len(sizes)) if members[b] == 1]
+    rng = np.random.default_rng(5)
+    check = sorted(rng.choice(whole_ids, size=min(48, len(whole_ids)), replace=False).tolist() +
+                   (rng.choice(split_ids, size=min(6, len(split_ids)), replace=False).tolist() if split_ids else []))
+    identical, ns_rel = 0, []
+    for bidx in check:
+        lab, ns = plain(bidx, rows[bidx] if members[bidx] > 1 else 1)
+        identical += int(torch.equal(lab, bt.labels_of(labels_b, bidx)))
+        ns_rel.append(abs(ns - ns_b[bidx, L].item()) / abs(ns))
+    print(json.dumps({"form": "batched", "step": "parity sample", "identical": identical, "checked": len(check)}),
+          file=sys.stderr, flush=True)
     upd = float(sum(n * n for n in sizes)) * L * iters
+    # algorithmic traffic of the sweeps: per element, level and iteration read S, R, A and write
+    # R, A (12 + 8 bytes)
+    alg_bytes = upd * 20.0
     bt.close()
+    # a batch of fewer, large problems (the 16 largest of the workload): one workgroup per problem
+    # leaves most of the device idle, gangs spread each problem over several workgroups
+    few = sorted(range(len(sizes)), key=lambda b: -sizes[b])[:16]
+    Xf = torch.cat([X[bt.offsets[b]:bt.offsets[b] + sizes[b]] for b in few])
+    few_sizes = [sizes[b] for b in few]
+    bf = hap.HapBatch(few_sizes, 16, L)
+    bf.set_launch(shape[0], shape[1], shape[2])
+    few_out = {}
+    for split in ((0, 1), (256, 16)):
+        bf.set_split(*split)
+        of = bf.outputs(dev)
+        bf.run(Xf, rp.damping, iters, out=of)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bf.run(Xf, rp.damping, iters, out=of)
+        torch.cuda.synchronize()
+        few_out["split_%d_%d" % split] = {"s": time.perf_counter() - t0, "workgroups_busy": int(sum(bf.members()[0])),
+                                          "iters_min": int(of[2].min().item())}
+    bf.close()
+    print(json.dumps({"form": "batched", "step": "few large problems", **few_out}), file=sys.stderr, flush=True)
     return {"form": "batched", "workload": f"{len(sizes)} problems, N ~ U{{64..2048}}, d=16, L={L}, "
             f"damping {rp.damping}, {iters} iterations", "sum_n2": int(sum(n * n for n in sizes)),
-            "launch": {"threads": shape[0], "workgroups": shape[1], "row_groups": shape[2]},
-            "batched_s": t_batch, "plain_s": t_plain, "speedup_vs_plain": t_plain / t_batch,
+            "launch": {"threads": shape[0], "workgroups": shape[1], "row_groups": shape[2],
+                       "split_n": shape[3], "max_members": shape[4]},
+            "problems_split": int(sum(k > 1 for k in members)), "gang_members_total": int(sum(members)),
+            "batched_s": t_batch, "plain_default_launch_s": t_plain, "speedup_vs_plain": t_plain / t_batch,
             "batched_updates_per_s": upd / t_batch, "plain_updates_per_s": upd / t_plain,
-            "label_agreement_min": min(agree), "label_agreement_mean": float(np.mean(agree)),
-            "problems_identical_labels": int(sum(a == 1.0 for a in agree)), "problems": len(sizes),
-            "net_similarity_rel_diff_max": max(ns_rel)}
+            "roofline": {"bound": "hbm", "achieved": alg_bytes / t_batch / 1e9, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": alg_bytes / t_batch / 1e9 / HBM_PEAK_GBS,
+                         "alg_bytes": alg_bytes, "kernel": "batch_kernel (whole run, wall time of the launch)"},
+            "iters_min": int(iters_b.min().item()),
+            "few_large_problems": {"problems": 16, "sizes": f"{min(few_sizes)}..{max(few_sizes)}", **few_out},
+            "label_agreement_vs_plain_default_min": min(agree_default),
+            "label_agreement_vs_plain_default_mean": float(np.mean(agree_default)),
+            "parity_sample": {"problems_checked": len(check), "split_problems_checked": sum(members[b] > 1 for b in check),
+                              "identical_labels": identical, "net_similarity_rel_diff_max": max(ns_rel)},
+            "problems": len(sizes)}
 
 
 def run_warm_form(args, torch, hap, synth) -> dict:
@@ -411,6 +476,8 @@ def run_profile_form(args, torch, hap, synth) -> int:
         bt = hap.HapBatch(sizes, problems[0].X.shape[1], rp.levels)
         shape = tuple(int(v) for v in args.batch_launch.split(","))
         bt.set_launch(*shape)
+        if args.batch_split:
+            bt.set_split(*(int(v) for v in args.batch_split.split(",")))
         out = bt.outputs(dev)
         torch.cuda.synchronize()
         print(f"batch ready: {len(sizes)} problems, sum n^2 = {sum(k * k for k in sizes)}, launch {shape}", flush=True)
@@ -540,7 +607,11 @@ def main() -> int:
     ap.add_argument("--copy-gib", type=float, default=1.0,
                     help="--form sweeps / batch-once: GiB of the calibration copy run first (0: none)")
     ap.add_argument("--batch-launch", default="1024,512,4",
-                    help="--form batch-once: threads,workgroups,row_groups of the persistent launch")
+                    help="--form batch-once (and --form batched with --batch-split): threads,workgroups,row_groups "
+                         "of the persistent launch")
+    ap.add_argument("--batch-split", default="",
+                    help="--form batch-once / batched: split_n,max_members of the gangs that share large problems "
+                         "(batched default: the autotuner's choice; batch-once default: no split)")
     ap.add_argument("--read-s-steps", type=int, default=2,
                     help="plain form: steps of the S-reading row pass timed after the headline steps "
                          "(its own roofline entry; 0: skip)")

@@ -320,14 +320,18 @@ HAP_API hap_status hap_profile_read(hap_ctx *ctx, double *row_pass_ms, int64_t *
 HAP_API hap_status hap_destroy(hap_ctx *ctx);
 
 /*
- * Batched form: many independent HAP problems of up to 2048 points each (FP32), run
- * by ONE persistent kernel launch in which every workgroup takes whole problems from
- * a queue (largest first) and performs the similarity build (as HAP_BUILD_DIRECT),
- * the median preference, the Algorithm 1 initial state, the sweeps, the final labels
- * (Eq. 2.8) and the FP64 net similarity.  Problem b is point rows
- * [off_b, off_b + n[b]) of the packed X (off_b = n[0] + ... + n[b-1]).
+ * Batched form: many independent HAP problems of up to 2048 points each (FP32), run by ONE
+ * persistent kernel launch (Section 2 / Algorithm 1 on every problem; the paper's task
+ * parallelism over nodes and levels, Section 3, becomes parallelism over problems and row
+ * blocks).  Workgroups take work items from a queue (largest problem first): a whole problem,
+ * which one workgroup runs completely (the similarity build (as HAP_BUILD_DIRECT), the median
+ * preference, the Algorithm 1 initial state, the sweeps, the final labels (Eq. 2.8) and the FP64
+ * net similarity), or, for problems above the split size (hap_batch_set_split), one member of
+ * the gang of K workgroups that share the problem: member m sweeps a block of rows, and the gang
+ * meets once per level to add the members' column sums in member order.  Problem b is point
+ * rows [off_b, off_b + n[b]) of the packed X (off_b = n[0] + ... + n[b-1]).
  *
- * hap_batch_create plans the batch (offsets, queue order) and copies the plan into
+ * hap_batch_create plans the batch (offsets, queue order; no split) and copies the plan into
  * the workspace (device, hap_batch_workspace_size bytes, 256-byte aligned, owned by the
  * caller; NULL = the library allocates); it synchronises the stream.  d <= 32.
  */
@@ -345,6 +349,13 @@ HAP_API hap_status hap_batch_create(hap_batch **out, int32_t count, const int32_
  * stop iteration after an early stop).  Launches two kernels and nothing else: no
  * allocation, no copy, no synchronisation, so the call can be captured in a graph.
  * A second run of the same batch starts again from the initial state.
+ * A problem run by one workgroup sums its columns in row order, so its trajectory is the
+ * single-problem path's with one row per workgroup (hap_set_launch rows_per_block = 1); a
+ * problem shared by a gang adds the members' row-ordered partials in member order, which is
+ * the single-problem path's with rows_per_block = the gang's rows per member.  The members of a
+ * gang wait for each other with a bounded wait (60 s per meeting, scaled up for runs of more
+ * than 200 iterations); a gang that does not meet gives up and reports iters[b] = -1 (its labels
+ * and net similarity are then not valid), and so do the gangs still running.
  */
 HAP_API hap_status hap_batch_run(hap_batch *batch, const void *X, double damping, int32_t max_iters,
                                  int32_t stable_iters, int32_t *labels, double *net_similarity, int32_t *iters,
@@ -355,10 +366,26 @@ HAP_API hap_status hap_batch_run(hap_batch *batch, const void *X, double damping
  * are still added in row order, so every shape computes the same values bit for bit.
  * (threads, row_groups) is one of (256, 1), (512, 1), (512, 2), (512, 4), (1024, 4); any
  * other pair is rejected with HAP_E_ARG and changes nothing.  0 keeps the current value.
- * For the autotuner. */
+ * While some problem is split, the launch uses at most as many workgroups as fit the device
+ * at once.  For the autotuner. */
 HAP_API hap_status hap_batch_set_launch(hap_batch *batch, int32_t threads, int32_t workgroups, int32_t row_groups);
 HAP_API hap_status hap_batch_get_launch(hap_batch *batch, int32_t *threads, int32_t *workgroups,
                                         int32_t *row_groups);
+/*
+ * Split large problems over gangs of workgroups: a problem of n > max(split_n, 256) points is
+ * shared by K = min(max_members, ceil(n^2 / split_n^2)) workgroups, each sweeping
+ * ceil(n / K) consecutive rows (K then recounted so that no member is empty).  split_n = 0
+ * switches splitting off (the default); otherwise split_n >= 256; 1 <= max_members <= 16.
+ * Re-plans the queue and copies it to the workspace; synchronises the stream.  Splitting
+ * shortens the batch's longest item (one workgroup running the largest problem) at the cost of
+ * one gang barrier per level and iteration.
+ */
+HAP_API hap_status hap_batch_set_split(hap_batch *batch, int32_t split_n, int32_t max_members, void *stream);
+HAP_API hap_status hap_batch_get_split(hap_batch *batch, int32_t *split_n, int32_t *max_members);
+/* The plan of every problem under the current split: members (host int32 [count], 1 = one
+ * workgroup) and rows per member (host int32 [count]; n for a problem that is not split).
+ * Either may be NULL. */
+HAP_API hap_status hap_batch_get_members(hap_batch *batch, int32_t *members, int32_t *rows_per_member);
 HAP_API hap_status hap_batch_destroy(hap_batch *batch);
 
 /*

@@ -128,33 +128,55 @@ def batch_candidates(cus: int, count: int):
     return out
 
 
+def split_candidates():
+    """(split_n, max_members) settings tried for the batch's large problems (0: no split)."""
+    return [(0, 1), (1448, 2), (1024, 2), (1024, 4), (724, 4), (724, 8)]
+
+
 def tune_batch(bt: "hap.HapBatch", X, damping: float, iters: int = 10, use_cache: bool = True):
-    """Pick threads, workgroup count and row groups of the persistent batched kernel for
-    this batch (every shape computes the same bits, so only time decides)."""
+    """Pick threads, workgroup count and row groups of the persistent batched kernel for this
+    batch (every shape computes the same bits, so only time decides), then the split of its
+    large problems over gangs of workgroups (a split changes the order of the column sums of the
+    split problems, so it is chosen with the shape fixed).  Returns (threads, workgroups,
+    row_groups, split_n, max_members)."""
     import torch
-    key = f"batch:{_arch()}:d{bt.d}:L{bt.levels}:{batch_signature(bt.sizes)}"
+    key = f"batch2:{_arch()}:d{bt.d}:L{bt.levels}:{batch_signature(bt.sizes)}"
     if use_cache:
         hit = _load_cache().get(key)
-        if hit and len(hit) == 4:
+        if hit and len(hit) == 6:
             try:
                 bt.set_launch(*hit[:3])
-                return tuple(hit[:3])
+                bt.set_split(*hit[3:5])
+                return tuple(hit[:5])
             except hap.HapError:
                 pass
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     out = bt.outputs(X.device)
-    best, best_ms = None, float("inf")
-    for shape in batch_candidates(cus, bt.count):
-        bt.set_launch(*shape)
+
+    def time_run():
         bt.run(X, damping, 1, out=out)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         bt.run(X, damping, iters, out=out)
         e1.record()
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
+        return e0.elapsed_time(e1)
+
+    bt.set_split(0, 1)
+    best, best_ms = None, float("inf")
+    for shape in batch_candidates(cus, bt.count):
+        bt.set_launch(*shape)
+        ms = time_run()
         if ms < best_ms:
             best, best_ms = shape, ms
     bt.set_launch(*best)
-    _store(key, list(best) + [best_ms])
-    return best
+    best_split = (0, 1)
+    for split in split_candidates()[1:]:
+        bt.set_split(*split)
+        ms = time_run()
+        if ms < best_ms:
+            best_split, best_ms = split, ms
+    bt.set_split(*best_split)
+    result = tuple(best) + tuple(best_split)
+    _store(key, list(result) + [best_ms])
+    return result

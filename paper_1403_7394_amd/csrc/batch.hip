@@ -1,14 +1,21 @@
 // Batched HAP: many independent instances of up to 2048 points in ONE persistent launch.
 //
-// Every workgroup pulls instances from an atomic queue (the host orders them by
-// decreasing size, so the largest start first) and runs each one completely: the
-// similarity build (FP64-accumulated, as HAP_BUILD_DIRECT), the median preference
-// (radix select in LDS), the Algorithm 1 initial state, the sweeps (the same fused row
-// pass as the single-problem path, over all rows of the instance, so the column partials
-// are complete column sums in row order), the labels of the final iteration (Eq. 2.8) and
-// the FP64 net similarity.  A workgroup never waits for another one, so there is no
-// inter-workgroup dependency and nothing to deadlock; every workgroup exits once the
-// queue is empty.
+// Workgroups pull work items from an atomic queue.  An item is either a whole instance, which
+// one workgroup runs from start to end (the similarity build (FP64-accumulated, as
+// HAP_BUILD_DIRECT), the median preference (radix select in LDS), the Algorithm 1 initial
+// state, the sweeps over all rows, whose column partials are then complete column sums in row
+// order, the labels of the final iteration (Eq. 2.8) and the FP64 net similarity), or one
+// member of a gang: the K workgroups that share a large instance, member m owning a block of
+// consecutive rows.  Members build their rows of S, compute the median themselves, sweep their
+// rows and meet once per level at a barrier of the gang, where every member adds the members'
+// column partials in member order (the order of the single-problem column sums with the same
+// rows per workgroup) and forms the same column vectors.  The host orders the queue largest
+// instance first with a gang's members consecutive, so only the gang being handed out can be
+// incomplete while every earlier item runs to its end; the barrier's wait is bounded and gives
+// up (raising an error flag and reporting the instance's iteration count as -1) rather than
+// spin forever.
+#include <algorithm>
+
 #include "rowpass.h"
 
 namespace hap {
@@ -17,17 +24,19 @@ struct BatchArgs {
     const float *X;
     int64_t d;
     const BatchDesc *desc;
-    const int *order;       // instances in the order they are handed out
+    const BatchItem *items; // queue order
+    int n_items;
     int count;
     int levels;
     float lam, oml;
     int max_iters, stable_iters;
     float *wsf;             // float workspace
     int32_t *wsi;           // int workspace
-    int32_t *queue;         // [0]: next index handed out
+    int32_t *queue;         // [0]: next item handed out, [1]: a gang's wait gave up
     int32_t *labels;        // output labels
     double *ns;             // [count][levels + 1]
     int32_t *iters;         // [count]
+    uint64_t wait_ticks;    // limit of one gang barrier wait, in wall-clock ticks
 };
 
 namespace {
@@ -45,13 +54,14 @@ __device__ __forceinline__ float fval(unsigned int k) {
 
 template <int NT>
 __device__ void build_instance(const float *__restrict__ X, int64_t d, int n, int ld, float *__restrict__ S,
-                               double *xs /* LDS [64 * d] */) {
+                               double *xs /* LDS [64 * d] */, int r0, int r1) {
 #pragma clang fp contract(off)
-    // thread t computes column j = t + NT*c; the rows come through LDS in blocks of 64
+    // rows [r0, r1) of S; thread t computes column j = t + NT*c, the rows come through LDS in
+    // blocks of 64
     for (int j0 = 0; j0 < n; j0 += NT) {
         const int j = j0 + threadIdx.x;
-        for (int i0 = 0; i0 < n; i0 += 64) {
-            const int rows = min(64, n - i0);
+        for (int i0 = r0; i0 < r1; i0 += 64) {
+            const int rows = min(64, r1 - i0);
             __syncthreads();
             for (int e = threadIdx.x; e < rows * d; e += NT) xs[e] = (double)X[(int64_t)(i0 + e / d) * d + e % d];
             __syncthreads();
@@ -71,6 +81,38 @@ __device__ void build_instance(const float *__restrict__ X, int64_t d, int n, in
         }
     }
     __syncthreads();
+}
+
+// Barrier of the K workgroups of a gang.  Every member arrives once per barrier, so barrier k
+// of an instance completes when its counter reaches k*K.  Thread 0 publishes the workgroup's
+// writes (agent-scope fence), arrives, and waits with a bounded spin: it gives up once another
+// gang has given up or after `limit` wall-clock ticks, raising the batch's flag.  Returns
+// whether the gang met (the same answer for every thread of the workgroup).
+__device__ __forceinline__ bool gang_barrier(int32_t *ctr, int32_t target, int32_t *flag, uint64_t limit,
+                                             int *sh_ok) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = 1;
+        const uint64_t t0 = wall_clock64();
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                ok = 0;
+                break;
+            }
+            if ((uint64_t)wall_clock64() - t0 > limit) {
+                __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();
+        *sh_ok = ok;
+    }
+    __syncthreads();
+    return *sh_ok != 0;
 }
 
 // Median of the off-diagonal entries: mean of the two middle order statistics (FP64),
@@ -149,7 +191,8 @@ __device__ __forceinline__ void sweep_rows_grouped(const SweepArgs<float> &a, co
                                                    const int row1, const float4v (&Bv)[NCH], float4v (&qv)[NCH],
                                                    float (*sh_m1)[G][NTG / 64], int (*sh_k1)[G][NTG / 64],
                                                    float (*sh_m2)[G][NTG / 64], float (*sh_cv)[G][NTG / 64],
-                                                   int (*sh_ck)[G][NTG / 64], float4v (*contrib)[G][NCH][G > 1 ? NTG : 1]) {
+                                                   int (*sh_ck)[G][NTG / 64], float4v (*contrib)[G][NCH][G > 1 ? NTG : 1],
+                                                   int32_t *changed) {
 #pragma clang fp contract(off)
     constexpr int VW = 4;
     constexpr int NWG = NTG / 64;
@@ -292,7 +335,7 @@ __device__ __forceinline__ void sweep_rows_grouped(const SweepArgs<float> &a, co
             }
         }
     }
-    if (chg) atomicOr(&a.ds->changed, 1);
+    if (chg) atomicOr(changed, 1);
     __syncthreads();
     // the last step's rows of groups 1..G-1
     if (grp == 0 && steps > 0) {
@@ -321,212 +364,319 @@ __global__ __launch_bounds__(NT) void batch_kernel(BatchArgs g) {
     __shared__ unsigned int hist[kBins];
     __shared__ double xs[64 * 32];
     __shared__ int sh[4];
+    __shared__ int sh_ok;
     __shared__ double shd[NW];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int ltid = tid % NTG;
     const int L = g.levels;
     for (;;) {
-        if (tid == 0) sh[3] = atomicAdd(g.queue, 1);
+        if (tid == 0) sh[3] = atomicAdd(&g.queue[0], 1);
         __syncthreads();
         const int q = sh[3];
         __syncthreads();
-        if (q >= g.count) break;
-        const int b = g.order[q];
+        if (q >= g.n_items) break;
+        const BatchItem item = g.items[q];
+        const int b = item.b, m = item.m;
         const BatchDesc D = g.desc[b];
-        const int n = D.n, ld = D.ld;
+        const int n = D.n, ld = D.ld, K = D.K;
+        // member m's rows (the whole instance when one workgroup runs it)
+        const int r0 = (K > 1) ? m * D.rbm : 0;
+        const int r1 = (K > 1) ? min(n, r0 + D.rbm) : n;
         float *S = g.wsf + D.w_off;
         float *RA = S + (int64_t)n * ld;                       // per level: R then A
         float *vec = RA + (int64_t)2 * L * n * ld;             // per level: pref, Q, phi, tau, C, B
         int32_t *E = g.wsi + D.i_off;
         DevState *ds = (DevState *)(E + (int64_t)L * ld);
+        int32_t *sync = (K > 1) ? g.wsi + D.s_off : nullptr;   // [0] barrier counter, [4 + 2m + p] flags
+        float *P = (K > 1) ? g.wsf + D.g_off : nullptr;        // column partials [2][K][ld]
         auto R = [&](int l) { return RA + (int64_t)(2 * l) * n * ld; };
         auto A = [&](int l) { return RA + (int64_t)(2 * l + 1) * n * ld; };
         auto vp = [&](int l, int k) { return vec + (int64_t)(6 * l + k) * ld; };
+        int met = 0;   // gang barriers passed
+        auto gang_sync = [&]() -> bool {
+            if (K == 1) {
+                __syncthreads();
+                return true;
+            }
+            ++met;
+            return gang_barrier(sync, met * K, &g.queue[1], g.wait_ticks, &sh_ok);
+        };
 
-        // 1. similarity and preference
-        build_instance<NT>(g.X + D.x_off * g.d, g.d, n, ld, S, xs);
-        const float p = median_instance<NT>(S, n, ld, hist, sh);
-        // 2. Algorithm 1 initial state (alpha = rho = 0, phi = c = 0; tau^1 is never read and
-        //    tau^l is written before it is read); padding columns of alpha hold -inf
-        for (int l = 0; l < L; ++l) {
-            float *Rl = R(l), *Al = A(l);
-            for (int64_t e = tid; e < (int64_t)n * ld; e += NT) {
-                Rl[e] = 0.f;
-                Al[e] = ((int)(e % ld) < n) ? 0.f : neg_inf<float>();
-            }
-            for (int j = tid; j < ld; j += NT) {
-                vp(l, 0)[j] = (j < n) ? p : 0.f;
-                for (int k = 1; k < 6; ++k) vp(l, k)[j] = 0.f;
-                E[(int64_t)l * ld + j] = 0;
-            }
-        }
-        if (tid == 0) {
-            ds->t = ds->stable = ds->done = ds->stop_iter = ds->changed = ds->final_changed = 0;
-        }
-        __syncthreads();
-        // 3. sweeps
-        int t = 0, stable = 0, stop_iter = -1;
-        for (int it = 0; it < g.max_iters; ++it) {
-            t += 1;
+        // 1. similarity rows, then the preference (every member computes the same median)
+        build_instance<NT>(g.X + D.x_off * g.d, g.d, n, ld, S, xs, r0, r1);
+        if (!gang_sync()) goto gave_up;
+        {
+            const float p = median_instance<NT>(S, n, ld, hist, sh);
+            // 2. Algorithm 1 initial state (alpha = rho = 0, phi = c = 0; tau^1 is never read and
+            //    tau^l is written before it is read); padding columns of alpha hold -inf.  Each
+            //    member clears its own rows; member 0 the vectors and labels.
             for (int l = 0; l < L; ++l) {
-                SweepArgs<float> a;
-                a.S = S;
-                a.lds = ld;
-                a.R = R(l);
-                a.A = A(l);
-                a.ldw = ld;
-                a.pref = vp(l, 0);
-                a.C = vp(l, 4);
-                a.phi_down = l > 0 ? vp(l - 1, 2) : nullptr;
-                a.B = vp(l, 5);
-                a.tau = l > 0 ? vp(l, 3) : nullptr;
-                a.E = E + (int64_t)l * ld;
-                a.Qpart = nullptr;
-                a.X = nullptr;
-                a.ldx = 0;
-                a.tau_c = nullptr;
-                a.tau_q = nullptr;
-                a.tau_store = nullptr;
-                a.mrhap = 0;
-                a.delta = nullptr;
-                a.n = n;
-                a.rb = n;
-                a.rows = n;
-                a.lam = g.lam;
-                a.oml = g.oml;
-                a.ds = ds;
-                const int ltid = tid % NTG;
-                V Bv[CH], qv[CH];
-#pragma unroll
-                for (int c = 0; c < CH; ++c) {
-                    const int j0 = c * NTG * VW + ltid * VW;
-                    Bv[c] = (t > 1 && j0 < n) ? *(const V *)(a.B + j0) : (V)(0.f);
-                    qv[c] = (V)(0.f);
+                float *Rl = R(l), *Al = A(l);
+                for (int64_t e = (int64_t)r0 * ld + tid; e < (int64_t)r1 * ld; e += NT) {
+                    Rl[e] = 0.f;
+                    Al[e] = ((int)(e % ld) < n) ? 0.f : neg_inf<float>();
                 }
-                if (t == 1)
-                    sweep_rows_grouped<NTG, CH, G, true>(a, t, 0, n, Bv, qv, gm1, gk1, gm2, gcv, gck, contrib);
-                else
-                    sweep_rows_grouped<NTG, CH, G, false>(a, t, 0, n, Bv, qv, gm1, gk1, gm2, gcv, gck, contrib);
-                __syncthreads();   // c^l, phi^{l-1}, labels of every row are written
-                // column sums (complete, in row order, held by row group 0), tau^{l+1}, B^{l-1}
-                // and B^l at the top
-#pragma unroll
-                for (int c = 0; c < CH; ++c) {
-                    const int j0 = c * NTG * VW + ltid * VW;
-                    if (tid >= NTG || j0 >= n) continue;
-                    *(V *)(vp(l, 1) + j0) = qv[c];
-                    if (l + 1 < L) *(V *)(vp(l + 1, 3) + j0) = *(const V *)(vp(l, 4) + j0) + qv[c];
-                    if (l == L - 1) *(V *)(vp(l, 5) + j0) = qv[c];
-                    if (l > 0)
-                        *(V *)(vp(l - 1, 5) + j0) =
-                            (*(const V *)(vp(l - 1, 4) + j0) + *(const V *)(vp(l - 1, 2) + j0)) +
-                            *(const V *)(vp(l - 1, 1) + j0);
-                }
-                __syncthreads();
-            }
-            // stop rule: the row pass of iteration t compared the labels of iteration t-1
-            if (t >= 2) {
-                const int lit = t - 1;
-                stable = (lit >= 2 && !ds->changed) ? stable + 1 : 0;
-            }
-            __syncthreads();
-            if (tid == 0) ds->changed = 0;
-            if (g.stable_iters > 0 && stable >= g.stable_iters) {
-                stop_iter = t - 1;
-                break;
-            }
-            __syncthreads();
-        }
-        __syncthreads();
-        // 4. labels: those recorded by the last row pass after an early stop, otherwise the
-        //    labels of iteration t from alpha^t finished on the fly (nothing written)
-        int32_t *out = g.labels + D.out_off;
-        for (int l = 0; l < L; ++l) {
-            if (stop_iter >= 0) {
-                for (int i = tid; i < n; i += NT) out[(int64_t)l * n + i] = E[(int64_t)l * ld + i];
-                continue;
-            }
-            const float *Rl = R(l), *Al = A(l), *Bl = vp(l, 5);
-            for (int i = 0; i < n; ++i) {
-                float cv = neg_inf<float>();
-                int ck = INT_MAX;
-                for (int j = tid; j < n; j += NT) {
-                    const float rj = Rl[(int64_t)i * ld + j];
-                    float al = Al[(int64_t)i * ld + j];
-                    if (t >= 1) {
-                        const float ah = (j == i) ? Bl[j] - rj : fminf(0.f, Bl[j] - fmaxf(0.f, rj));
-                        al = g.lam * al + g.oml * ah;
-                    }
-                    const float x = al + rj;
-                    if (x > cv) {
-                        cv = x;
-                        ck = j;
+                if (m == 0) {
+                    for (int j = tid; j < ld; j += NT) {
+                        vp(l, 0)[j] = (j < n) ? p : 0.f;
+                        for (int k = 1; k < 6; ++k) vp(l, k)[j] = 0.f;
+                        E[(int64_t)l * ld + j] = 0;
                     }
                 }
-#pragma unroll
-                for (int off = 32; off >= 1; off >>= 1) {
-                    const float ocv = __shfl_xor(cv, off, 64);
-                    const int ock = __shfl_xor(ck, off, 64);
-                    argmax_merge(cv, ck, ocv, ock);
-                }
-                if (lane == 0) {
-                    sh_cv[0][wid] = cv;
-                    sh_ck[0][wid] = ck;
-                }
-                __syncthreads();
-                if (tid == 0) {
-                    cv = sh_cv[0][0];
-                    ck = sh_ck[0][0];
-                    for (int w = 1; w < NW; ++w) argmax_merge(cv, ck, sh_cv[0][w], sh_ck[0][w]);
-                    out[(int64_t)l * n + i] = ck;
-                }
-                __syncthreads();
             }
-        }
-        __syncthreads();
-        // 5. net similarity per level and total, FP64, fixed-order reduction
-        double total = 0.0;
-        for (int l = 0; l < L; ++l) {
-            double acc = 0.0;
-            for (int i = tid; i < n; i += NT) {
-                const int e = out[(int64_t)l * n + i];
-                if (e < 0 || e >= n)
-                    acc += __builtin_nan("");   // no valid exemplar (non-finite messages)
-                else
-                    acc += (e == i) ? (double)p : (double)S[(int64_t)i * ld + e];
-            }
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
-            if (lane == 0) shd[wid] = acc;
-            __syncthreads();
             if (tid == 0) {
-                double s = 0.0;
-                for (int w = 0; w < NW; ++w) s += shd[w];
-                g.ns[(int64_t)b * (L + 1) + l] = s;
-                total += s;
+                ds->t = ds->stable = ds->done = ds->stop_iter = ds->changed = ds->final_changed = 0;
+                if (K > 1) sync[4 + 2 * m] = sync[5 + 2 * m] = 0;
+            }
+            if (!gang_sync()) goto gave_up;
+            // 3. sweeps
+            int t = 0, stable = 0, stop_iter = -1, par = 0;
+            for (int it = 0; it < g.max_iters; ++it) {
+                t += 1;
+                int32_t *chg_flag = (K > 1) ? &sync[4 + 2 * m + (t & 1)] : &ds->changed;
+                for (int l = 0; l < L; ++l) {
+                    SweepArgs<float> a;
+                    a.S = S;
+                    a.lds = ld;
+                    a.R = R(l);
+                    a.A = A(l);
+                    a.ldw = ld;
+                    a.pref = vp(l, 0);
+                    a.C = vp(l, 4);
+                    a.phi_down = l > 0 ? vp(l - 1, 2) : nullptr;
+                    a.B = vp(l, 5);
+                    a.tau = l > 0 ? vp(l, 3) : nullptr;
+                    a.E = E + (int64_t)l * ld;
+                    a.Qpart = nullptr;
+                    a.X = nullptr;
+                    a.ldx = 0;
+                    a.tau_c = nullptr;
+                    a.tau_q = nullptr;
+                    a.tau_store = nullptr;
+                    a.mrhap = 0;
+                    a.delta = nullptr;
+                    a.n = n;
+                    a.rb = n;
+                    a.rows = n;
+                    a.lam = g.lam;
+                    a.oml = g.oml;
+                    a.ds = ds;
+                    V Bv[CH], qv[CH];
+#pragma unroll
+                    for (int c = 0; c < CH; ++c) {
+                        const int j0 = c * NTG * VW + ltid * VW;
+                        Bv[c] = (t > 1 && j0 < n) ? *(const V *)(a.B + j0) : (V)(0.f);
+                        qv[c] = (V)(0.f);
+                    }
+                    if (t == 1)
+                        sweep_rows_grouped<NTG, CH, G, true>(a, t, r0, r1, Bv, qv, gm1, gk1, gm2, gcv, gck, contrib,
+                                                             chg_flag);
+                    else
+                        sweep_rows_grouped<NTG, CH, G, false>(a, t, r0, r1, Bv, qv, gm1, gk1, gm2, gcv, gck, contrib,
+                                                              chg_flag);
+                    __syncthreads();   // c^l, phi^{l-1}, labels of this workgroup's rows are written
+                    if (K > 1) {
+                        // publish this member's column partials, then meet the gang
+#pragma unroll
+                        for (int c = 0; c < CH; ++c) {
+                            const int j0 = c * NTG * VW + ltid * VW;
+                            if (tid < NTG && j0 < n) *(V *)(P + ((int64_t)par * K + m) * ld + j0) = qv[c];
+                        }
+                        if (!gang_sync()) goto gave_up;
+                    }
+                    // column sums (row group 0: its own in row order, or the members' partials added
+                    // in member order), tau^{l+1}, B^{l-1} and B^l at the top
+#pragma unroll
+                    for (int c = 0; c < CH; ++c) {
+                        const int j0 = c * NTG * VW + ltid * VW;
+                        if (tid >= NTG || j0 >= n) continue;
+                        V tot = qv[c];
+                        if (K > 1) {
+                            tot = *(const V *)(P + ((int64_t)par * K) * ld + j0);
+                            for (int k = 1; k < K; ++k) tot += *(const V *)(P + ((int64_t)par * K + k) * ld + j0);
+                        }
+                        *(V *)(vp(l, 1) + j0) = tot;
+                        if (l + 1 < L) *(V *)(vp(l + 1, 3) + j0) = *(const V *)(vp(l, 4) + j0) + tot;
+                        if (l == L - 1) *(V *)(vp(l, 5) + j0) = tot;
+                        if (l > 0)
+                            *(V *)(vp(l - 1, 5) + j0) =
+                                (*(const V *)(vp(l - 1, 4) + j0) + *(const V *)(vp(l - 1, 2) + j0)) +
+                                *(const V *)(vp(l - 1, 1) + j0);
+                    }
+                    par ^= 1;
+                    __syncthreads();
+                }
+                // With two levels no gang barrier separates the column sums of level 1 (which read
+                // c^0 of every row) from the next iteration's level-0 pass (which rewrites c^0 of its
+                // rows); with more levels one does.
+                if (K > 1 && L == 2 && !gang_sync()) goto gave_up;
+                // stop rule: the row passes of iteration t compared the labels of iteration t-1
+                int changed_any;
+                if (K > 1) {
+                    changed_any = 0;
+                    for (int k = 0; k < K; ++k)
+                        changed_any |= __hip_atomic_load(&sync[4 + 2 * k + (t & 1)], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                } else {
+                    changed_any = ds->changed;
+                }
+                if (t >= 2) {
+                    const int lit = t - 1;
+                    stable = (lit >= 2 && !changed_any) ? stable + 1 : 0;
+                }
+                __syncthreads();
+                // this member's flag for the next iteration (every member has read it for iteration
+                // t - 1 before the first barrier of iteration t)
+                if (tid == 0) {
+                    if (K > 1)
+                        __hip_atomic_store(&sync[4 + 2 * m + ((t + 1) & 1)], 0, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    else
+                        ds->changed = 0;
+                }
+                if (g.stable_iters > 0 && stable >= g.stable_iters) {
+                    stop_iter = t - 1;
+                    break;
+                }
+                __syncthreads();
             }
             __syncthreads();
+            // 4. labels of this workgroup's rows: those recorded by the last row pass after an early
+            //    stop, otherwise the labels of iteration t from alpha^t finished on the fly
+            int32_t *out = g.labels + D.out_off;
+            for (int l = 0; l < L; ++l) {
+                if (stop_iter >= 0) {
+                    for (int i = r0 + tid; i < r1; i += NT) out[(int64_t)l * n + i] = E[(int64_t)l * ld + i];
+                    continue;
+                }
+                const float *Rl = R(l), *Al = A(l), *Bl = vp(l, 5);
+                for (int i = r0; i < r1; ++i) {
+                    float cv = neg_inf<float>();
+                    int ck = INT_MAX;
+                    for (int j = tid; j < n; j += NT) {
+                        const float rj = Rl[(int64_t)i * ld + j];
+                        float al = Al[(int64_t)i * ld + j];
+                        if (t >= 1) {
+                            const float ah = (j == i) ? Bl[j] - rj : fminf(0.f, Bl[j] - fmaxf(0.f, rj));
+                            al = g.lam * al + g.oml * ah;
+                        }
+                        const float x = al + rj;
+                        if (x > cv) {
+                            cv = x;
+                            ck = j;
+                        }
+                    }
+#pragma unroll
+                    for (int off = 32; off >= 1; off >>= 1) {
+                        const float ocv = __shfl_xor(cv, off, 64);
+                        const int ock = __shfl_xor(ck, off, 64);
+                        argmax_merge(cv, ck, ocv, ock);
+                    }
+                    if (lane == 0) {
+                        sh_cv[0][wid] = cv;
+                        sh_ck[0][wid] = ck;
+                    }
+                    __syncthreads();
+                    if (tid == 0) {
+                        cv = sh_cv[0][0];
+                        ck = sh_ck[0][0];
+                        for (int w = 1; w < NW; ++w) argmax_merge(cv, ck, sh_cv[0][w], sh_ck[0][w]);
+                        out[(int64_t)l * n + i] = ck;
+                    }
+                    __syncthreads();
+                }
+            }
+            if (!gang_sync()) goto gave_up;
+            // 5. net similarity per level and total, FP64, fixed-order reduction (member 0)
+            if (m == 0) {
+                double total = 0.0;
+                for (int l = 0; l < L; ++l) {
+                    double acc = 0.0;
+                    for (int i = tid; i < n; i += NT) {
+                        const int e = out[(int64_t)l * n + i];
+                        if (e < 0 || e >= n)
+                            acc += __builtin_nan("");   // no valid exemplar (non-finite messages)
+                        else
+                            acc += (e == i) ? (double)p : (double)S[(int64_t)i * ld + e];
+                    }
+#pragma unroll
+                    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+                    if (lane == 0) shd[wid] = acc;
+                    __syncthreads();
+                    if (tid == 0) {
+                        double s2 = 0.0;
+                        for (int w = 0; w < NW; ++w) s2 += shd[w];
+                        g.ns[(int64_t)b * (L + 1) + l] = s2;
+                        total += s2;
+                    }
+                    __syncthreads();
+                }
+                if (tid == 0) {
+                    g.ns[(int64_t)b * (L + 1) + L] = total;
+                    g.iters[b] = stop_iter >= 0 ? stop_iter : t;
+                }
+            }
+            __syncthreads();
+            continue;
         }
-        if (tid == 0) {
-            g.ns[(int64_t)b * (L + 1) + L] = total;
-            g.iters[b] = stop_iter >= 0 ? stop_iter : t;
-        }
+    gave_up:
+        // the gang did not meet within the wait limit: the instance's results are not valid
+        if (tid == 0) g.iters[b] = -1;
         __syncthreads();
     }
 }
 
-__global__ void batch_reset(int32_t *queue) { queue[0] = 0; }
+// Start of a run: the queue, the flag and every gang's barrier counter back to 0.
+__global__ void batch_reset(int32_t *queue, const BatchDesc *desc, int count, int32_t *wsi) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0) {
+        queue[0] = 0;
+        queue[1] = 0;
+    }
+    if (k < count && desc[k].K > 1) wsi[desc[k].s_off] = 0;
+}
+
+
 
 }  // namespace
 
-hipError_t launch_batch(const float *X, int64_t d, const BatchDesc *desc, const int *order, int count, int levels,
-                        double lam, int max_iters, int stable_iters, float *wsf, int32_t *wsi, int32_t *queue,
-                        int32_t *labels, double *ns, int32_t *iters, int threads, int workgroups, int groups,
-                        hipStream_t st) {
+namespace {
+
+// Workgroups of one batch kernel instance that fit the device at once (all of them run from the
+// start, so every gang's members are handed out to running workgroups).
+template <int NT, int G, int CH>
+int resident_workgroups() {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<NT, G, CH>, NT, 0) != hipSuccess) return 0;
+    return per_cu * cus;
+}
+
+template <int NT, int G, int CH>
+hipError_t launch_shape(const BatchArgs &g, int workgroups, bool gangs, hipStream_t st) {
+    int grid = workgroups;
+    if (gangs) {
+        const int res = resident_workgroups<NT, G, CH>();
+        if (res < kMaxGang) return hipErrorInvalidConfiguration;
+        grid = std::min(grid, res);
+    }
+    hipLaunchKernelGGL((batch_kernel<NT, G, CH>), dim3(grid), dim3(NT), 0, st, g);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_batch(const float *X, int64_t d, const BatchDesc *desc, const BatchItem *items, int n_items,
+                        int count, int levels, double lam, int max_iters, int stable_iters, float *wsf, int32_t *wsi,
+                        int32_t *queue, int32_t *labels, double *ns, int32_t *iters, int threads, int workgroups,
+                        int groups, bool gangs, hipStream_t st) {
     BatchArgs g;
     g.X = X;
     g.d = d;
     g.desc = desc;
-    g.order = order;
+    g.items = items;
+    g.n_items = n_items;
     g.count = count;
     g.levels = levels;
     g.lam = (float)lam;
@@ -539,21 +689,22 @@ hipError_t launch_batch(const float *X, int64_t d, const BatchDesc *desc, const 
     g.labels = labels;
     g.ns = ns;
     g.iters = iters;
-    hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, st, queue);
+    // a gang waits at most 60 s per barrier, longer for very long runs (a member may wait for
+    // the other members to be handed out, which can take as long as one whole instance)
+    int dev = 0, khz = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess) return e;
+    const double seconds = 60.0 * std::max(1.0, max_iters / 200.0);
+    g.wait_ticks = (uint64_t)(seconds * 1000.0 * (double)(khz > 0 ? khz : 100000));
+    hipLaunchKernelGGL(batch_reset, dim3((count + 255) / 256), dim3(256), 0, st, queue, desc, count, wsi);
     // threads x row groups: every row group covers 2048 columns
-    if (threads == 256 && groups == 1)
-        hipLaunchKernelGGL((batch_kernel<256, 1, 2>), dim3(workgroups), dim3(256), 0, st, g);
-    else if (threads == 512 && groups == 1)
-        hipLaunchKernelGGL((batch_kernel<512, 1, 1>), dim3(workgroups), dim3(512), 0, st, g);
-    else if (threads == 512 && groups == 2)
-        hipLaunchKernelGGL((batch_kernel<512, 2, 2>), dim3(workgroups), dim3(512), 0, st, g);
-    else if (threads == 512 && groups == 4)
-        hipLaunchKernelGGL((batch_kernel<512, 4, 4>), dim3(workgroups), dim3(512), 0, st, g);
-    else if (threads == 1024 && groups == 4)
-        hipLaunchKernelGGL((batch_kernel<1024, 4, 2>), dim3(workgroups), dim3(1024), 0, st, g);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+    if (threads == 256 && groups == 1) return launch_shape<256, 1, 2>(g, workgroups, gangs, st);
+    if (threads == 512 && groups == 1) return launch_shape<512, 1, 1>(g, workgroups, gangs, st);
+    if (threads == 512 && groups == 2) return launch_shape<512, 2, 2>(g, workgroups, gangs, st);
+    if (threads == 512 && groups == 4) return launch_shape<512, 4, 4>(g, workgroups, gangs, st);
+    if (threads == 1024 && groups == 4) return launch_shape<1024, 4, 2>(g, workgroups, gangs, st);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace hap

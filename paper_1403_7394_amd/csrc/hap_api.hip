@@ -1062,26 +1062,48 @@ hap_status hap_destroy(hap_ctx *c) {
 struct hap_batch {
     int count = 0, levels = 0;
     int64_t d = 0;
+    std::vector<int32_t> sizes;      // host copy of the instance sizes (re-planning)
     void *ws = nullptr;
     size_t ws_bytes = 0;
     bool own_ws = false;
     hap::BatchDesc *desc = nullptr;  // device
-    int *order = nullptr;            // device
+    hap::BatchItem *items = nullptr; // device, queue order
+    int n_items = 0;
     int32_t *queue = nullptr;        // device
     float *wsf = nullptr;
     int32_t *wsi = nullptr;
     int threads = 512, workgroups = 512, row_groups = 4;
+    int split_n = 0, max_members = 4;   // instances above split_n points are shared by a gang
+    bool gangs = false;
 };
 
 namespace {
 
 struct BatchPlan {
     std::vector<hap::BatchDesc> desc;
-    std::vector<int> order;
-    size_t off_desc, off_order, off_queue, off_f, off_i, total;
+    std::vector<hap::BatchItem> items;
+    size_t off_desc, off_items, off_queue, off_f, off_i, total;
+    bool gangs = false;
 };
 
-bool plan_batch(int32_t count, const int32_t *n, int64_t d, int32_t levels, BatchPlan &pl, std::string &err) {
+// Gang of an instance: members K = min(max_members, ceil(n^2 / split_n^2)) for n > split_n
+// (split_n = 0: never), rows per member ceil(n / K), then K recounted so no member is empty.
+void gang_of(int n, int split_n, int max_members, int &K, int &rbm) {
+    K = 1;
+    rbm = n;
+    if (split_n <= 0 || n <= split_n || n <= hap::kGangMinN) return;
+    const int64_t want = ((int64_t)n * n + (int64_t)split_n * split_n - 1) / ((int64_t)split_n * split_n);
+    K = (int)std::min<int64_t>(want, max_members);
+    if (K < 2) {
+        K = 1;
+        return;
+    }
+    rbm = (n + K - 1) / K;
+    K = (n + rbm - 1) / rbm;
+}
+
+bool plan_batch(int32_t count, const int32_t *n, int64_t d, int32_t levels, int split_n, int max_members, BatchPlan &pl,
+                std::string &err) {
     if (count < 1 || !n || d < 1 || d > 32 || levels < 1 || levels > 64) {
         err = "hap_batch: need count >= 1, 1 <= d <= 32, 1 <= levels <= 64";
         return false;
@@ -1101,15 +1123,30 @@ bool plan_batch(int32_t count, const int32_t *n, int64_t d, int32_t levels, Batc
         D.w_off = fo;
         D.i_off = io;
         D.out_off = oo;
+        gang_of(n[b], split_n, max_members, D.K, D.rbm);
+        pl.gangs = pl.gangs || D.K > 1;
         xo += n[b];
         fo += (hap::batch_floats(n[b], ld, levels) + 63) / 64 * 64;
         io += (hap::batch_ints(ld, levels) + 63) / 64 * 64;
+        D.g_off = -1;
+        D.s_off = -1;
+        if (n[b] > hap::kGangMinN) {
+            // room for the largest gang, whatever the current split
+            D.g_off = fo;
+            fo += (int64_t)2 * hap::kMaxGang * ld;
+            D.s_off = io;
+            io += hap::kGangInts;
+        }
         oo += (int64_t)levels * n[b];
     }
-    pl.order.resize(count);
-    for (int b = 0; b < count; ++b) pl.order[b] = b;
-    // largest problems first (ties by index, so the order is deterministic)
-    std::sort(pl.order.begin(), pl.order.end(), [&](int a, int b) { return n[a] != n[b] ? n[a] > n[b] : a < b; });
+    std::vector<int> order(count);
+    for (int b = 0; b < count; ++b) order[b] = b;
+    // largest problems first (ties by index, so the order is deterministic); a gang's members
+    // are consecutive in the queue
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return n[a] != n[b] ? n[a] > n[b] : a < b; });
+    pl.items.clear();
+    for (int b : order)
+        for (int m = 0; m < pl.desc[b].K; ++m) pl.items.push_back({b, m});
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -1117,12 +1154,23 @@ bool plan_batch(int32_t count, const int32_t *n, int64_t d, int32_t levels, Batc
         return o;
     };
     pl.off_desc = take(sizeof(hap::BatchDesc) * count);
-    pl.off_order = take(sizeof(int) * count);
+    pl.off_items = take(sizeof(hap::BatchItem) * (size_t)count * hap::kMaxGang);
     pl.off_queue = take(64);
     pl.off_f = take((size_t)fo * 4);
     pl.off_i = take((size_t)io * 4);
     pl.total = off;
     return true;
+}
+
+hap_status upload_plan(hap_batch *b, const BatchPlan &pl, hipStream_t st) {
+    hipError_t e = hipMemcpyAsync(b->desc, pl.desc.data(), sizeof(hap::BatchDesc) * b->count, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->items, pl.items.data(), sizeof(hap::BatchItem) * pl.items.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail_hip(e, "hap_batch: upload of the plan");
+    b->n_items = (int)pl.items.size();
+    b->gangs = pl.gangs;
+    return HAP_OK;
 }
 
 }  // namespace
@@ -1133,7 +1181,7 @@ hap_status hap_batch_workspace_size(int32_t count, const int32_t *n, int64_t d, 
     if (!bytes) return fail_arg("hap_batch_workspace_size: null pointer");
     BatchPlan pl;
     std::string err;
-    if (!plan_batch(count, n, d, levels, pl, err)) return fail_arg(err.c_str());
+    if (!plan_batch(count, n, d, levels, 0, 1, pl, err)) return fail_arg(err.c_str());
     *bytes = pl.total;
     return HAP_OK;
 }
@@ -1144,7 +1192,7 @@ hap_status hap_batch_create(hap_batch **out, int32_t count, const int32_t *n, in
     *out = nullptr;
     BatchPlan pl;
     std::string err;
-    if (!plan_batch(count, n, d, levels, pl, err)) return fail_arg(err.c_str());
+    if (!plan_batch(count, n, d, levels, 0, 1, pl, err)) return fail_arg(err.c_str());
     if (workspace && (workspace_bytes < pl.total || ((uintptr_t)workspace & (kAlign - 1)) != 0))
         return fail_arg("hap_batch_create: workspace too small or not 256-byte aligned");
     hap_batch *b = new (std::nothrow) hap_batch();
@@ -1152,6 +1200,7 @@ hap_status hap_batch_create(hap_batch **out, int32_t count, const int32_t *n, in
     b->count = count;
     b->levels = levels;
     b->d = d;
+    b->sizes.assign(n, n + count);
     if (workspace) {
         b->ws = workspace;
         b->ws_bytes = workspace_bytes;
@@ -1166,16 +1215,12 @@ hap_status hap_batch_create(hap_batch **out, int32_t count, const int32_t *n, in
     }
     char *base = (char *)b->ws;
     b->desc = (hap::BatchDesc *)(base + pl.off_desc);
-    b->order = (int *)(base + pl.off_order);
+    b->items = (hap::BatchItem *)(base + pl.off_items);
     b->queue = (int32_t *)(base + pl.off_queue);
     b->wsf = (float *)(base + pl.off_f);
     b->wsi = (int32_t *)(base + pl.off_i);
-    hipStream_t st = (hipStream_t)stream;
-    hipError_t e = hipMemcpyAsync(b->desc, pl.desc.data(), sizeof(hap::BatchDesc) * count, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(b->order, pl.order.data(), sizeof(int) * count, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) {
-        hap_status s = fail_hip(e, "hap_batch_create");
+    const hap_status s = upload_plan(b, pl, (hipStream_t)stream);
+    if (s != HAP_OK) {
         if (b->own_ws) (void)hipFree(b->ws);
         delete b;
         return s;
@@ -1189,9 +1234,9 @@ hap_status hap_batch_run(hap_batch *b, const void *X, double damping, int32_t ma
     if (!b || !X || !labels || !net_similarity || !iters) return fail_arg("hap_batch_run: null pointer");
     if (!(damping >= 0.0 && damping < 1.0)) return fail_arg("hap_batch_run: damping must be in [0, 1)");
     if (max_iters < 0 || stable_iters < 0) return fail_arg("hap_batch_run: negative count");
-    hipError_t e = hap::launch_batch((const float *)X, b->d, b->desc, b->order, b->count, b->levels, damping, max_iters,
-                                     stable_iters, b->wsf, b->wsi, b->queue, labels, net_similarity, iters, b->threads,
-                                     b->workgroups, b->row_groups, (hipStream_t)stream);
+    hipError_t e = hap::launch_batch((const float *)X, b->d, b->desc, b->items, b->n_items, b->count, b->levels, damping,
+                                     max_iters, stable_iters, b->wsf, b->wsi, b->queue, labels, net_similarity, iters,
+                                     b->threads, b->workgroups, b->row_groups, b->gangs, (hipStream_t)stream);
     if (e != hipSuccess) return fail_hip(e, "hap_batch_run");
     return HAP_OK;
 }
@@ -1216,6 +1261,41 @@ hap_status hap_batch_get_launch(hap_batch *b, int32_t *threads, int32_t *workgro
     if (threads) *threads = b->threads;
     if (workgroups) *workgroups = b->workgroups;
     if (row_groups) *row_groups = b->row_groups;
+    return HAP_OK;
+}
+
+hap_status hap_batch_set_split(hap_batch *b, int32_t split_n, int32_t max_members, void *stream) {
+    if (!b) return fail_arg("hap_batch_set_split: null pointer");
+    if (split_n < 0 || (split_n > 0 && split_n < hap::kGangMinN))
+        return fail_arg("hap_batch_set_split: split_n must be 0 (off) or at least 256");
+    if (max_members < 1 || max_members > hap::kMaxGang)
+        return fail_arg("hap_batch_set_split: max_members must lie in [1, 16]");
+    BatchPlan pl;
+    std::string err;
+    if (!plan_batch(b->count, b->sizes.data(), b->d, b->levels, split_n, max_members, pl, err))
+        return fail_arg(err.c_str());
+    const hap_status s = upload_plan(b, pl, (hipStream_t)stream);
+    if (s != HAP_OK) return s;
+    b->split_n = split_n;
+    b->max_members = max_members;
+    return HAP_OK;
+}
+
+hap_status hap_batch_get_split(hap_batch *b, int32_t *split_n, int32_t *max_members) {
+    if (!b) return fail_arg("hap_batch_get_split: null pointer");
+    if (split_n) *split_n = b->split_n;
+    if (max_members) *max_members = b->max_members;
+    return HAP_OK;
+}
+
+hap_status hap_batch_get_members(hap_batch *b, int32_t *members, int32_t *rows_per_member) {
+    if (!b) return fail_arg("hap_batch_get_members: null pointer");
+    for (int i = 0; i < b->count; ++i) {
+        int K, rbm;
+        gang_of(b->sizes[i], b->split_n, b->max_members, K, rbm);
+        if (members) members[i] = K;
+        if (rows_per_member) rows_per_member[i] = rbm;
+    }
     return HAP_OK;
 }
 

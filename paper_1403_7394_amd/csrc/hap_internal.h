@@ -160,7 +160,21 @@ struct BatchDesc {
     int64_t out_off; // first label of the instance in the output (levels x n, level-major)
     int n;
     int ld;          // padded row length (multiple of 64) of S, R, A
+    int K;           // workgroups sharing the instance (its gang); 1: one workgroup runs it alone
+    int rbm;         // rows per member when K > 1: member m sweeps rows [m*rbm, min(n, (m+1)*rbm))
+    int64_t g_off;   // first float of the gang's column partials P[2][K][ld] (instances that may be split)
+    int64_t s_off;   // first int of the gang's sync words (instances that may be split; kGangInts ints)
 };
+// One unit of work handed out by the batch queue: member m of instance b.
+struct BatchItem {
+    int b, m;
+};
+// Instances above kGangMinN points may be split over up to kMaxGang workgroups; each such
+// instance holds room for the largest gang.  Sync words: [0] barrier counter, [4 + 2m + p]
+// label-changed flag of member m for iterations of parity p.
+constexpr int kGangMinN = 256;
+constexpr int kMaxGang = 16;
+constexpr int kGangInts = 64;
 
 // Per-instance workspace (floats): S, then per level R, A, then per level the vectors
 // pref, Q, phi, tau, C, B.  Ints: per level E, then a DevState.
@@ -171,10 +185,11 @@ __host__ __device__ inline int64_t batch_ints(int ld, int levels) {
     return (int64_t)levels * ld + (int64_t)(sizeof(DevState) / sizeof(int32_t));
 }
 
-hipError_t launch_batch(const float *X, int64_t d, const BatchDesc *desc, const int *order, int count, int levels,
-                        double lam, int max_iters, int stable_iters, float *wsf, int32_t *wsi, int32_t *queue,
-                        int32_t *labels, double *ns, int32_t *iters, int threads, int workgroups, int groups,
-                        hipStream_t st);
+// queue[0]: next item handed out; queue[1]: set when a gang could not meet within the wait limit
+hipError_t launch_batch(const float *X, int64_t d, const BatchDesc *desc, const BatchItem *items, int n_items,
+                        int count, int levels, double lam, int max_iters, int stable_iters, float *wsf, int32_t *wsi,
+                        int32_t *queue, int32_t *labels, double *ns, int32_t *iters, int threads, int workgroups,
+                        int groups, bool gangs, hipStream_t st);
 
 // Warm-start perceptron (mlp.hip).  Offsets of the flat parameter vector (floats) and of the
 // workspace regions (bytes) for `rows` rows.

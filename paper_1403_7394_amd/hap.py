@@ -31,7 +31,7 @@ EXPORTS = (
     "hap_set_points", "hap_set_row_count", "hap_get_row_count",
     "hap_get_launch", "hap_profile", "hap_profile_read", "hap_destroy",
     "hap_batch_workspace_size", "hap_batch_create", "hap_batch_run", "hap_batch_set_launch",
-    "hap_batch_get_launch", "hap_batch_destroy",
+    "hap_batch_get_launch", "hap_batch_set_split", "hap_batch_get_split", "hap_batch_get_members", "hap_batch_destroy",
     "hap_warm_features", "hap_warm_targets", "hap_set_warm_start", "hap_iterate_warm",
     "hap_mlp_param_count", "hap_mlp_workspace_size", "hap_mlp_forward", "hap_mlp_loss_grad", "hap_mlp_adam",
     "hap_mlp_train",
@@ -95,6 +95,9 @@ def _declare(lib):
         "hap_batch_run": (I32, [V, V, D, I32, I32, V, V, V, V]),
         "hap_batch_set_launch": (I32, [V, I32, I32, I32]),
         "hap_batch_get_launch": (I32, [V, _c_i32p, _c_i32p, _c_i32p]),
+        "hap_batch_set_split": (I32, [V, I32, I32, V]),
+        "hap_batch_get_split": (I32, [V, _c_i32p, _c_i32p]),
+        "hap_batch_get_members": (I32, [V, _c_i32p, _c_i32p]),
         "hap_batch_destroy": (I32, [V]),
         "hap_similarity_offsets": (I32, [V, I32, V]),
         "hap_warm_features": (I32, [V, V, I64]),
@@ -490,6 +493,25 @@ class HapBatch:
         _check("hap_batch_get_launch", self._lib.hap_batch_get_launch(self._h, ctypes.byref(a), ctypes.byref(b),
                                                                       ctypes.byref(c)))
         return a.value, b.value, c.value
+
+    def set_split(self, split_n: int, max_members: int = 4):
+        """Share problems of more than split_n points among gangs of up to max_members
+        workgroups (split_n = 0: no split)."""
+        _check("hap_batch_set_split", self._lib.hap_batch_set_split(self._h, int(split_n), int(max_members),
+                                                                      ctypes.c_void_p(self._stream.cuda_stream)))
+
+    def get_split(self):
+        """(split_n, max_members)"""
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check("hap_batch_get_split", self._lib.hap_batch_get_split(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def members(self):
+        """(members, rows per member) of every problem under the current split."""
+        k = (ctypes.c_int32 * self.count)()
+        r = (ctypes.c_int32 * self.count)()
+        _check("hap_batch_get_members", self._lib.hap_batch_get_members(self._h, k, r))
+        return list(k), list(r)
 
     def close(self):
         if getattr(self, "_h", None):

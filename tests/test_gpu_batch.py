@@ -167,3 +167,121 @@ def test_full_size_batch_on_sampled_problems(hap_gpu):
         for l in range(rp.levels):
             assert abs(ns[b, l].item() - ns_ref[l]) <= 1e-12 * abs(ns_ref[l]), (b, l)
     bt.close()
+
+
+# ---------------------------------------------------------------------------
+# Problems shared by gangs of workgroups (hap_batch_set_split)
+# ---------------------------------------------------------------------------
+
+def _run_batch_split(hap, Xs, L, lam, T, split_n, max_members, K=0, launch=None, reps=1):
+    sizes = [x.shape[0] for x in Xs]
+    X = torch.from_numpy(np.concatenate(Xs)).to(DEV)
+    bt = hap.HapBatch(sizes, Xs[0].shape[1], L)
+    if launch:
+        bt.set_launch(*launch)
+    bt.set_split(split_n, max_members)
+    members, rows = bt.members()
+    outs = []
+    for _ in range(reps):
+        labels, ns, iters = bt.run(X, lam, T, K)
+        torch.cuda.synchronize()
+        outs.append(([bt.labels_of(labels, b).cpu().numpy().copy() for b in range(len(sizes))],
+                     ns.cpu().numpy().copy(), iters.cpu().numpy().copy()))
+    bt.close()
+    return outs, members, rows
+
+
+def _plain(hap, X, L, lam, T, rows_per_block, K=0):
+    """The single-problem path on the same points with the given rows per workgroup."""
+    n = X.shape[0]
+    Xt = torch.from_numpy(X).to(DEV)
+    S = torch.empty((n, n + (-n) % 4), dtype=torch.float32, device=DEV)[:, :n]
+    hap.build_similarity(Xt, S)
+    h = hap.Hap(S, L, lam)
+    h.set_launch(rows_per_block=rows_per_block)
+    res = h.iterate(T, K)
+    labels = h.labels().cpu().numpy()
+    ns = [h.net_similarity(l) for l in range(L)]
+    h.close()
+    return labels, ns, res
+
+
+@pytest.mark.parametrize("L,launch", [(3, (1024, 0, 4)), (2, (512, 0, 4)), (1, (512, 0, 2))])
+def test_split_problems_equal_the_plain_path_with_the_same_row_blocks(hap_gpu, L, launch):
+    """A problem shared by K workgroups equals the single-problem path with rows_per_block = the
+    gang's rows per member (the members' partials added in member order); problems run by one
+    workgroup still equal the path with one row per workgroup.  Two levels exercise the extra
+    gang barrier of that case, one level the top-level-only case."""
+    sizes = [1500, 700, 300, 2048, 90, 1029]
+    Xs = _problems(sizes, seed=900 + L)
+    lam, T = 0.8, 25
+    outs, members, rows = _run_batch_split(hap_gpu, Xs, L, lam, T, split_n=600, max_members=4,
+                                           launch=(launch[0], 64, launch[2]), reps=2)
+    (labels, ns, iters), (labels2, ns2, iters2) = outs
+    assert members == [4, 2, 1, 4, 1, 3], members
+    for b, X in enumerate(Xs):
+        rb = rows[b] if members[b] > 1 else 1
+        lab, ns_ref, res = _plain(hap_gpu, X, L, lam, T, rb)
+        assert iters[b] == T, (b, iters[b])
+        assert np.array_equal(labels[b], lab), (b, members[b])
+        for l in range(L):
+            assert abs(ns[b, l] - ns_ref[l]) <= 1e-12 * abs(ns_ref[l]) + 1e-300, (b, l)
+        # deterministic: a second run gives the same bits
+        assert np.array_equal(labels2[b], labels[b]) and np.array_equal(ns2[b], ns[b]) and iters2[b] == iters[b]
+
+
+def test_split_problems_stop_rule(hap_gpu):
+    """Early stops inside gangs: every member sees the OR of the members' label-change flags, so
+    the stop iteration equals the single-problem path's with the same row blocks."""
+    sizes = [1200, 900, 400]
+    Xs = _problems(sizes, seed=950)
+    L, lam, T, K = 1, 0.8, 400, 10
+    outs, members, rows = _run_batch_split(hap_gpu, Xs, L, lam, T, split_n=300, max_members=8, K=K,
+                                           launch=(512, 16, 4))
+    labels, ns, iters = outs[0]
+    assert all(k > 1 for k in members), members
+    for b, X in enumerate(Xs):
+        lab, ns_ref, res = _plain(hap_gpu, X, L, lam, T, rows[b], K=K)
+        assert res.converged and iters[b] == res.iters, (b, iters[b], res.iters)
+        assert np.array_equal(labels[b], lab), b
+
+
+def test_split_plan_and_arguments(hap_gpu):
+    sizes = [2048, 1024, 257, 256, 100]
+    bt = hap_gpu.HapBatch(sizes, 16, 3)
+    assert bt.get_split() == (0, 4) and bt.members() == ([1] * 5, sizes)
+    bt.set_split(512, 8)
+    k, r = bt.members()
+    # K = min(8, ceil(n^2 / 512^2)) rows per member ceil(n / K); 256 points and fewer never split
+    assert k == [8, 4, 1, 1, 1] and r == [256, 256, 257, 256, 100]
+    for bad in ((100, 4), (512, 0), (512, 17), (-1, 4)):
+        with pytest.raises(hap_gpu.HapError):
+            bt.set_split(*bad)
+    assert bt.get_split() == (512, 8)
+    bt.set_split(0, 4)
+    assert bt.members() == ([1] * 5, sizes)
+    bt.close()
+
+
+def test_split_full_batched_workload_sampled_problems(hap_gpu):
+    """The full batched workload (512 problems, N ~ U{64..2048}, d = 16, L = 3, damping 0.8) in
+    the launch the autotuner picks, with the benchmark's split: the smallest, a middle and the
+    largest problem (split) equal the single-problem path with the same row blocks over 8
+    iterations."""
+    from paper_1403_7394_amd import autotune
+    problems, rp = synth.workload_batched()
+    sizes = [b.X.shape[0] for b in problems]
+    X = torch.from_numpy(np.concatenate([b.X for b in problems])).to(DEV)
+    bt = hap_gpu.HapBatch(sizes, 16, rp.levels)
+    autotune.tune_batch(bt, X, rp.damping)
+    members, rows = bt.members()
+    labels, ns, iters = bt.run(X, rp.damping, 8)
+    torch.cuda.synchronize()
+    order = np.argsort(sizes)
+    picks = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
+    for b in picks:
+        lab, ns_ref, res = _plain(hap_gpu, problems[b].X, rp.levels, rp.damping, 8,
+                                  rows[b] if members[b] > 1 else 1)
+        assert int(iters[b].item()) == 8
+        assert np.array_equal(bt.labels_of(labels, b).cpu().numpy(), lab), (b, sizes[b], members[b])
+    bt.close()
