@@ -441,8 +441,8 @@ def run_profile_form(args, torch, hap, synth) -> int:
     sweeps: the FP32 similarity of the 2-D 64-blob workload (--n points, default 8192), then
       --sweeps full sweeps (L = 3, damping 0.9, no stop rule; points mode unless --read-s;
       --rows R updates rows [0, R) only, one device's block of a run split by rows; --rb B sets
-      the rows per workgroup), after one device copy of --copy-gib GiB whose counter readings
-      calibrate the HBM byte counters.
+      the rows per workgroup, --sweep-launch the whole row-pass shape), after one device copy
+      of --copy-gib GiB whose counter readings calibrate the HBM byte counters.
     builds: the similarity of the 32768-point, 64-dimensional workload built once in each mode
       (direct, FP32 GEMM, BF16, BF16x3).
     batch-once: the batched workload run once for --form-iters iterations (default 200) in the
@@ -496,6 +496,9 @@ def run_profile_form(args, torch, hap, synth) -> int:
         h.set_row_count(args.rows)
     if args.rb:
         h.set_launch(rows_per_block=args.rb)
+    if args.sweep_launch:
+        t_, c_, rb_, st_ = (int(v) for v in args.sweep_launch.split(","))
+        h.set_launch(t_, c_, rb_, streaming=bool(st_))
     if not args.read_s:
         h.set_points(X)
     torch.cuda.synchronize()
@@ -604,6 +607,8 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=8192, help="--form sweeps: points")
     ap.add_argument("--rows", type=int, default=0, help="--form sweeps: update rows [0, rows) only (0: all)")
     ap.add_argument("--rb", type=int, default=0, help="--form sweeps: rows per workgroup (0: the default launch)")
+    ap.add_argument("--sweep-launch", default="",
+                    help="--form sweeps: row-pass shape threads,chunks,rows_per_block,streaming (empty: the default)")
     ap.add_argument("--copy-gib", type=float, default=1.0,
                     help="--form sweeps / batch-once: GiB of the calibration copy run first (0: none)")
     ap.add_argument("--batch-launch", default="1024,512,4",

@@ -256,9 +256,11 @@ HAP_API hap_status hap_similarity_offsets(hap_ctx *ctx, int32_t level, void *del
  * under HAP_SCHEDULE_MRHAP; 268 MB for one row per workgroup at n = 8192, FP32), kept
  * until hap_destroy; HAP_E_OOM if that allocation fails (nothing changes).  0 keeps the
  * library's choice for that field.  flags (a bit set; -1 keeps the current
- * choices): HAP_LAUNCH_STREAM selects the streaming row pass for long rows (1024
- * threads, 1 to 16 chunks; the row is read again from the caches in its second
- * phase), otherwise the register-resident row pass; HAP_LAUNCH_EAGER issues every
+ * choices): HAP_LAUNCH_STREAM selects a row pass for long rows: with 1024 threads and 1
+ * to 16 chunks the streaming pass (the row is read again from the caches in its second
+ * phase), with 512 threads and 16 chunks (FP32 only, n <= 32768, the default for
+ * 16384 < n <= 32768) the held-row pass (the row's s and rho stay in registers between
+ * the phases); without the flag the register-resident row pass; HAP_LAUNCH_EAGER issues every
  * launch from the host instead of replaying captured graphs of sweep chunks (the
  * default captures each chunk of up to 16 sweeps once on a private stream and
  * replays it on the context's stream).  Returns HAP_E_ARG (and changes nothing)

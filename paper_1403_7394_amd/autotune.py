@@ -73,6 +73,9 @@ def sweep_candidates(n: int, elem_size: int):
         if chunks <= 16:
             for rb in sorted({max(1, n // 256), max(1, n // 512)}):
                 out.append((1024, chunks, rb, True))
+        if elem_size == 4 and 16384 < n <= 512 * 16 * 4:
+            for rb in sorted({max(1, n // 256), max(1, n // 512)}):
+                out.append((512, 16, rb, True))   # the held-row pass
     return out
 
 

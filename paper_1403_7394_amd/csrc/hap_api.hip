@@ -183,6 +183,14 @@ Launch default_launch(int64_t n, size_t esz) {
             found = true;
         }
     }
+    if (!found && esz == 4 && n > 512 * 8 * 4 && n <= 512 * 16 * 4) {
+        // FP32 rows of up to 32768 columns: the held-row pass (512 threads x 16 chunks keep the
+        // row's s and rho in registers between the two phases)
+        lc.threads = 512;
+        lc.chunks = 16;
+        lc.streaming = true;
+        found = true;
+    }
     if (!found) {
         // rows too long for registers: stream them with 1024 threads and 2..16 chunks
         lc.threads = 1024;
@@ -207,7 +215,8 @@ Launch default_launch(int64_t n, size_t esz) {
 bool launch_fits(const Launch &lc, int64_t n, int64_t rows, size_t esz) {
     const int64_t vw = (int64_t)(16 / esz);
     if (lc.streaming) {
-        if (lc.threads != 1024) return false;
+        const bool held = lc.threads == 512 && lc.chunks == 16 && esz == 4;
+        if (lc.threads != 1024 && !held) return false;
         if (lc.chunks < 1 || lc.chunks > 16) return false;
     } else if (!hap::launch_supported(lc.threads, lc.chunks, (int)esz)) {
         return false;

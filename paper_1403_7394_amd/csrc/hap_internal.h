@@ -44,7 +44,8 @@ struct Launch {
     int chunks;         // 16-byte column chunks per thread
     int rows_per_block; // rows handled by one workgroup (column partials are per workgroup)
     bool ordered;       // column partials summed strictly in workgroup order
-    bool streaming;     // large rows: 1024 threads, phase 2 re-reads S and R (chunks 2..16)
+    bool streaming;     // large rows: 1024 threads, phase 2 re-reads S and R (chunks 2..16); or, FP32
+                        // with 512 threads x 16 chunks, the held-row pass (phase 2 reads nothing)
 };
 
 // Pointers of one level inside the workspace.

@@ -414,6 +414,215 @@ __device__ __forceinline__ void stream_rows_unpipelined(const SweepArgs<T> &a, c
     if (chg) atomicOr(&a.ds->changed, 1);
 }
 
+// Row pass for rows of up to NT*NCH*4 FP32 columns that do not fit the register-resident pass
+// (16384 < n <= 32768 at 512 threads and 16 chunks): the row's S and rho are held in registers
+// from phase 1 to phase 2 (128 registers), so phase 2 reads nothing from memory; alpha is
+// finished and stored in phase 1, the column bases B are read per chunk, and the column
+// partials live in LDS.  Phase 1's loads run one chunk ahead of the arithmetic, and the next
+// row's first chunk is loaded during phase 2's last.  The per-row scalars are staged in LDS per
+// window of kWin rows, so that no global load issued after those loads is waited for in a row.
+template <int NT, int NCH, bool FIRST, bool TAIL>
+__device__ __forceinline__ void held_rows(const SweepArgs<float> &a, const int t, const int row0, const int row1,
+                                          Vec<float>::type (*qs)[NT], float (*sh_m1)[NT / 64], int (*sh_k1)[NT / 64],
+                                          float (*sh_m2)[NT / 64], float (*sh_cv)[NT / 64],
+                                          int (*sh_ck)[NT / 64]) {
+#pragma clang fp contract(off)
+    using T = float;
+    using V = Vec<float>::type;
+    constexpr int VW = 4;
+    constexpr int NW = NT / 64;
+    // the wave index is wave-uniform: as a scalar it keeps the LDS slots' addresses out of vector registers
+    const int tid = threadIdx.x, lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int n = a.n;
+    const int64_t ldw = a.ldw;
+    const T lam = a.lam, oml = a.oml;
+    const T zero = T(0), ninf = neg_inf<T>();
+    const int base = tid * VW;
+    __shared__ T st_p[kWin], st_tau[kWin], st_d[kWin];
+    __shared__ int st_e[kWin], st_has[kWin];
+    V hs[NCH], hr[NCH];            // this row's s (with the diagonal and the Eq. 2.7 offset) and rho^{t-1}
+    V sv = (V)(zero), rv = (V)(zero), av = (V)(zero), bv = (V)(zero);   // the next chunk's operands
+    // buffer-resource accesses: a resource per row, the lane's byte offset in one register and the
+    // chunk's offset as a scalar, so the chunks cost no address registers (loads past the row's
+    // resource return 0, which the ragged tail overrides)
+    constexpr int CB = NT * VW * (int)sizeof(T);
+    const int voff = tid * 16;
+    const __amdgpu_buffer_rsrc_t rB = row_rsrc(a.B, ldw * (int64_t)sizeof(T));
+    auto load1 = [&](int row, int c) {
+        const __amdgpu_buffer_rsrc_t rS = row_rsrc(a.S + (int64_t)row * a.lds, a.lds * (int64_t)sizeof(T));
+        const __amdgpu_buffer_rsrc_t rR = row_rsrc(a.R + (int64_t)row * ldw, ldw * (int64_t)sizeof(T));
+        const __amdgpu_buffer_rsrc_t rA = row_rsrc(a.A + (int64_t)row * ldw, ldw * (int64_t)sizeof(T));
+        sv = buf_load<V, kNT>(rS, voff, c * CB);
+        rv = buf_load<V, 0>(rR, voff, c * CB);
+        av = buf_load<V, 0>(rA, voff, c * CB);
+        if constexpr (!FIRST) bv = buf_load<V, 0>(rB, voff, c * CB);
+        if constexpr (TAIL) {
+            if (c * NT * VW + base >= n) av = (V)(ninf);   // columns past n never win a maximum
+        }
+    };
+    int buf = 0;
+    int chg = 0;
+    if (row0 < row1) load1(row0, 0);
+    for (int i = row0; i < row1; ++i, buf ^= 1) {
+        const int r = (i - row0) % kWin;
+        if (r == 0) {
+            __syncthreads();
+            const int k = i + tid;
+            if (tid < kWin && k < row1) {
+                st_p[tid] = a.pref[k];
+                T tv = zero;
+                st_has[tid] = row_tau(a, k, t, tv) ? 1 : 0;
+                st_tau[tid] = tv;
+                st_d[tid] = a.delta != nullptr ? a.delta[k] : zero;
+                st_e[tid] = a.E[k];
+            }
+            __syncthreads();
+        }
+        const T p_i = st_p[r];
+        const T d_i = st_d[r];
+        const bool has_d = a.delta != nullptr;
+        const __amdgpu_buffer_rsrc_t rA = row_rsrc(a.A + (int64_t)i * ldw, ldw * (int64_t)sizeof(T));
+        const __amdgpu_buffer_rsrc_t rR = row_rsrc(a.R + (int64_t)i * ldw, ldw * (int64_t)sizeof(T));
+        int dcol = i - base;
+        T m1 = ninf, m2 = ninf, cv = ninf;
+        int k1 = INT_MAX, ck = INT_MAX;
+        // phase 1: finish alpha^{t-1} (stored), reduce c/e over alpha + rho and the top two of alpha + s
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int j0 = c * NT * VW + base;
+            V sc = sv, ac = av;
+            hr[c] = rv;
+            const V bc = bv;
+            if (c + 1 < NCH) load1(i, c + 1);
+            // dcol is made opaque per chunk, so the diagonal masks are formed where they are used
+            // rather than all at once and held in scalar registers
+            asm volatile("" : "+v"(dcol));
+            if (has_d) sc = sc + d_i;
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                const int j = c * NT * VW + v;
+                const bool diag = dcol == j;
+                const T sj = diag ? p_i : sc[v];
+                sc[v] = sj;
+                const T rj = hr[c][v];
+                T al = ac[v];
+                if constexpr (!FIRST) {
+                    // two selects rather than one over two expressions, which the compiler
+                    // turns into a branch
+                    const T u = bc[v] - (diag ? rj : fmax(zero, rj));
+                    const T ah = diag ? u : fmin(zero, u);
+                    al = lam * al + oml * ah;
+                    ac[v] = al;
+                    const T cx = al + rj;
+                    const bool g = cx > cv;
+                    cv = g ? cx : cv;
+                    ck = g ? j : ck;
+                }
+                const T y = al + sj;
+                const bool g1 = y > m1;
+                m2 = g1 ? m1 : fmax(m2, y);
+                k1 = g1 ? j : k1;
+                m1 = g1 ? y : m1;
+            }
+            hs[c] = sc;
+            if constexpr (!FIRST) buf_store<V, kNT>(ac, rA, voff, c * CB);
+            // keep each chunk's memory accesses with its arithmetic (the compiler would otherwise
+            // hoist later chunks' accesses and run out of registers)
+            asm volatile("" ::: "memory");
+        }
+        k1 = (k1 == INT_MAX) ? INT_MAX : k1 + base;
+        ck = (ck == INT_MAX) ? INT_MAX : ck + base;
+        wave_reduce<T, !FIRST>(m1, k1, m2, cv, ck);
+        if (lane == 0) {
+            sh_m1[buf][wid] = m1;
+            sh_k1[buf][wid] = k1;
+            sh_m2[buf][wid] = m2;
+            if constexpr (!FIRST) {
+                sh_cv[buf][wid] = cv;
+                sh_ck[buf][wid] = ck;
+            }
+        }
+        // LDS exchange of the wave results (waits for LDS writes only, not for the stores in flight)
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        m1 = sh_m1[buf][0];
+        k1 = sh_k1[buf][0];
+        m2 = sh_m2[buf][0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) top2_merge(m1, k1, m2, sh_m1[buf][w], sh_k1[buf][w], sh_m2[buf][w]);
+        if constexpr (!FIRST) {
+            if (tid == 0) {
+                cv = sh_cv[buf][0];
+                ck = sh_ck[buf][0];
+                for (int w = 1; w < NW; ++w) argmax_merge(cv, ck, sh_cv[buf][w], sh_ck[buf][w]);
+                a.C[i] = cv;
+                if (a.phi_down) a.phi_down[i] = m1;
+                a.E[i] = ck;
+                chg |= (t >= 3 && st_e[r] != ck) ? 1 : 0;
+            }
+        } else {
+            if (a.mrhap && tid == 0 && a.phi_down) a.phi_down[i] = m1;
+        }
+        // phase 2: rho^t from the held row, column partials in LDS
+        asm volatile("" : "+v"(dcol));
+        const int k1r = k1 - base;
+        const T tau_i = st_tau[r];
+        const bool has_tau = st_has[r] != 0;
+        if (a.tau_store && tid == 0) a.tau_store[i] = has_tau ? tau_i : pos_inf<T>();
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int j0 = c * NT * VW + base;
+            if (c + 1 == NCH && i + 1 < row1) load1(i + 1, 0);
+            asm volatile("" : "+v"(dcol));
+            V out;
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                const int j = c * NT * VW + v;
+                const T m = (j == k1r) ? m2 : m1;
+                const T rh = has_tau ? hs[c][v] + fmin(tau_i, -m) : hs[c][v] - m;
+                out[v] = lam * hr[c][v] + oml * rh;
+            }
+            buf_store<V, kNT>(out, rR, voff, c * CB);
+            V q = qs[c][tid];
+#pragma unroll
+            for (int v = 0; v < VW; ++v) q[v] += (dcol == c * NT * VW + v) ? out[v] : fmax(zero, out[v]);
+            qs[c][tid] = q;
+            asm volatile("" ::: "memory");
+        }
+    }
+    if (chg) atomicOr(&a.ds->changed, 1);
+}
+
+template <int NT, int NCH, bool TAIL>
+__global__ __launch_bounds__(NT) void sweep_held_kernel(SweepArgs<float> a) {
+#pragma clang fp contract(off)
+    using V = Vec<float>::type;
+    constexpr int VW = 4;
+    constexpr int NW = NT / 64;
+    __shared__ float sh_m1[2][NW], sh_m2[2][NW], sh_cv[2][NW];
+    __shared__ int sh_k1[2][NW], sh_ck[2][NW];
+    __shared__ V qs[NCH][NT];
+    const DevState *ds = a.ds;
+    if (ds->done) return;
+    const int t = ds->t + 1;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) qs[c][threadIdx.x] = (V)(0.f);
+    const int row0 = blockIdx.x * a.rb;
+    const int row1 = min(a.rows, row0 + a.rb);
+    if (t == 1)
+        held_rows<NT, NCH, true, TAIL>(a, t, row0, row1, qs, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
+    else
+        held_rows<NT, NCH, false, TAIL>(a, t, row0, row1, qs, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
+    float *qrow = a.Qpart + (int64_t)blockIdx.x * a.ldw;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const int j0 = c * NT * VW + threadIdx.x * VW;
+        if (!TAIL || j0 < a.n) *(V *)(qrow + j0) = qs[c][threadIdx.x];
+    }
+}
+
 template <typename T, int NT, bool TAIL>
 __global__ __launch_bounds__(NT) void sweep_stream_kernel(SweepArgs<T> a, int nch) {
 #pragma clang fp contract(off)
@@ -743,6 +952,18 @@ hipError_t launch_sweep_level(const T *S, int64_t lds, const LevelPtrs<T> &lv, T
     a.delta = ex.delta;
     const int nb = (a.rows + lc.rows_per_block - 1) / lc.rows_per_block;
     const bool tail = (int64_t)lc.threads * lc.chunks * Vec<T>::N != n;
+    if (lc.streaming && lc.threads == 512) {
+        // the held-row pass: FP32, 512 threads x 16 chunks (n <= 32768)
+        if constexpr (sizeof(T) == 4) {
+            if (lc.chunks != 16 || n > 512 * 16 * 4) return hipErrorInvalidValue;
+            if (tail)
+                hipLaunchKernelGGL((sweep_held_kernel<512, 16, true>), dim3(nb), dim3(512), 0, st, a);
+            else
+                hipLaunchKernelGGL((sweep_held_kernel<512, 16, false>), dim3(nb), dim3(512), 0, st, a);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     if (lc.streaming) {
         if (lc.threads != 1024 || lc.chunks < 1 || lc.chunks > 16) return hipErrorInvalidValue;
         if (tail)

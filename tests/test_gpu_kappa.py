@@ -83,11 +83,13 @@ def test_fp32_bit_identical(hap_gpu, n, lam, kappa, T):
     same_as_oracle(g, hap_ref.hap(S32, p, 3, lam, T, dtype=np.float32, kappa=kappa), 3)
 
 
-def test_fp32_streaming_bit_identical(hap_gpu):
+@pytest.mark.parametrize("launch", [(1024, 3, 1), (512, 16, 1)])
+def test_fp32_streaming_bit_identical(hap_gpu, launch):
+    """The streaming and the held-row passes, forced, with the Eq. 2.7 offsets."""
     b, _ = synth.workload_plain_f32(n=1500)
     S32 = sim.similarity(b.X).astype(np.float32)
     p = sim.median_offdiag(S32, np.float32)
-    g = run(hap_gpu, S32, 3, 0.7, 30, 0.5, launch=(1024, 3, 1), streaming=True)
+    g = run(hap_gpu, S32, 3, 0.7, 30, 0.5, launch=launch, streaming=True)
     same_as_oracle(g, hap_ref.hap(S32, p, 3, 0.7, 30, dtype=np.float32, kappa=0.5), 3)
 
 

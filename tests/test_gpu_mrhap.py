@@ -58,13 +58,13 @@ def test_fp64_bit_identical(hap_gpu):
     same_as_oracle(g, hap_ref.hap(S, p, 3, 0.5, 60, schedule="mrhap"), 3)
 
 
-@pytest.mark.parametrize("n,T,streaming", [(1000, 40, None), (257, 80, None), (1000, 30, True)])
+@pytest.mark.parametrize("n,T,streaming", [(1000, 40, None), (257, 80, None), (1000, 30, True), (700, 30, "held")])
 def test_fp32_bit_identical(hap_gpu, n, T, streaming):
     b = synth.small_blobs(1400 + n, n, d=2, k=6, dtype=np.float32)
     S = sim.similarity(b.X).astype(np.float32)
     p = sim.median_offdiag(S, np.float32)
-    launch = (1024, 1, 1) if streaming else (0, 0, 1)
-    g = run(hap_gpu, S, 3, 0.9, T, launch=launch, streaming=streaming)
+    launch = (512, 16, 1) if streaming == "held" else (1024, 1, 1) if streaming else (0, 0, 1)
+    g = run(hap_gpu, S, 3, 0.9, T, launch=launch, streaming=bool(streaming) or None)
     same_as_oracle(g, hap_ref.hap(S, p, 3, 0.9, T, dtype=np.float32, schedule="mrhap"), 3)
 
 

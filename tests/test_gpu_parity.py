@@ -337,6 +337,52 @@ def test_streaming_matches_resident_exact_fit(hap_gpu):
     assert torch.equal(out[0][3], out[1][3])
 
 
+@pytest.mark.parametrize("n,lam,T", [(1000, 0.9, 60), (300, 0.5, 40), (2051, 0.7, 30)])
+def test_held_row_pass_bit_identical_to_fp32_oracle(hap_gpu, n, lam, T):
+    """The held-row pass (512 threads x 16 chunks, the row's s and rho kept in registers
+    between the two phases, column partials in LDS) forced on small problems with one row
+    per workgroup: bit-identical to the FP32 oracle."""
+    b, _ = synth.workload_plain_f32(n=n)
+    S32 = oracle_S(b.X, np.float32)
+    p = sim.median_offdiag(S32, np.float32)
+    r = hap_ref.hap(S32, p, 3, lam, T, dtype=np.float32)
+    h = hap_gpu.Hap(to_device(S32), 3, lam)
+    h.set_launch(512, 16, 1, streaming=True)
+    assert h.get_launch() == (512, 16, 1, True)
+    h.iterate(T)
+    assert np.array_equal(h.labels().cpu().numpy(), r.labels)
+    for l in range(3):
+        m = h.messages(l)
+        assert np.array_equal(m["rho"].cpu().numpy(), r.state.rho[l])
+        assert np.array_equal(m["alpha"].cpu().numpy(), r.state.alpha[l])
+        assert np.array_equal(m["c"].cpu().numpy(), r.state.c[l])
+    h.close()
+
+
+def test_held_matches_streaming_exact_fit(hap_gpu):
+    """n = 32768 = 512 x 16 x 4 = 1024 x 8 x 4 (no tail): the held-row pass and the streaming
+    pass sum the same rows per workgroup in the same order, so they agree bit for bit."""
+    n = 32768
+    b, _ = synth.workload_plain_f32(n=n)
+    X = torch.from_numpy(b.X.astype(np.float32)).to(DEV)
+    S = torch.empty((n, n), dtype=torch.float32, device=DEV)
+    hap_gpu.build_similarity(X, S)
+    h0 = hap_gpu.Hap(S, 2, 0.9, pref=-10.0)
+    assert h0.get_launch() == (512, 16, 128, True)    # the default for FP32 16384 < n <= 32768
+    h0.iterate(6)
+    h1 = hap_gpu.Hap(S, 2, 0.9, pref=-10.0)
+    h1.set_launch(1024, 8, 128, streaming=True)
+    h1.iterate(6)
+    for l in range(2):
+        m0, m1 = h0.messages(l), h1.messages(l)
+        for k in ("rho", "alpha", "c", "phi"):
+            assert torch.equal(m0[k], m1[k]), (l, k)
+        del m0, m1
+    assert torch.equal(h0.labels(), h1.labels())
+    h0.close()
+    h1.close()
+
+
 def test_streaming_row_pass_f64(hap_gpu):
     b = synth.small_blobs(77, 700, k=5)
     S = oracle_S(b.X, np.float64, 1e-12, 77)
@@ -359,6 +405,18 @@ def test_default_launch_for_long_rows_streams(hap_gpu):
     h = hap_gpu.Hap(S, 1, 0.5, pref=-1.0)
     threads, chunks, rb, streaming = h.get_launch()
     assert streaming and threads == 1024 and chunks == 3
+    h.close()
+    # FP32 rows of 16384 < n <= 32768 columns take the held-row pass, FP64 rows stream
+    n = 20000
+    S = torch.zeros((n, n), dtype=torch.float32, device=DEV)
+    h = hap_gpu.Hap(S, 1, 0.5, pref=-1.0)
+    assert h.get_launch() == (512, 16, (n + 255) // 256, True)
+    h.close()
+    del S
+    S = torch.zeros((n, n), dtype=torch.float64, device=DEV)
+    h = hap_gpu.Hap(S, 1, 0.5, pref=-1.0)
+    threads, chunks, rb, streaming = h.get_launch()
+    assert streaming and threads == 1024 and chunks == 10
     h.close()
 
 
