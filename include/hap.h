@@ -437,6 +437,24 @@ HAP_API hap_status hap_set_warm_start(hap_ctx *ctx, const float *Y, int64_t ldy)
 HAP_API hap_status hap_iterate_warm(hap_ctx *ctx, const float *Y, int64_t ldy, int32_t max_iters,
                                     int32_t stable_iters, int32_t *iters_done, int32_t *converged,
                                     int32_t *fell_back);
+/*
+ * Warm run judged by the cold start (opt-in: it always pays for a cold run as well).  The
+ * warm run from Y (hap_set_warm_start(Y), hap_iterate(max_iters, stable_iters)), then the
+ * cold run (Algorithm 1's alpha = 0) on the same context; each is scored by its net
+ * similarity summed over the levels (hap_net_similarity(level -1) with the X, d, ldx, x_dtype
+ * given here: recomputed from X in FP64 when X is not NULL, else read from S).  The run kept
+ * is the converged one if only one converged, else the one with the larger score (the warm
+ * run on a tie).  When the warm run is kept it is run again, so that the context's state and
+ * labels are the kept run's (every pass is deterministic, so the rerun repeats it bit for
+ * bit; HAP_E_STATE if the rerun's stop iteration differs).  Outputs (host, each may be
+ * NULL): iters_done and converged of the kept run,
+ * fell_back = 1 when the cold run is kept, ns_warm and ns_cold the two scores.  Y must not be
+ * NULL; stable_iters >= 1.  Synchronises the stream.
+ */
+HAP_API hap_status hap_iterate_warm_judged(hap_ctx *ctx, const float *Y, int64_t ldy, int32_t max_iters,
+                                           int32_t stable_iters, const void *X, int64_t d, int64_t ldx,
+                                           int32_t x_dtype, int32_t *iters_done, int32_t *converged,
+                                           int32_t *fell_back, double *ns_warm, double *ns_cold);
 
 /*
  * The warm start's perceptron: n_in -> hidden -> hidden -> n_out, ReLU after both hidden

@@ -1419,6 +1419,37 @@ hap_status hap_iterate_warm(hap_ctx *c, const float *Y, int64_t ldy, int32_t max
     return HAP_OK;
 }
 
+hap_status hap_iterate_warm_judged(hap_ctx *c, const float *Y, int64_t ldy, int32_t max_iters, int32_t stable_iters,
+                                   const void *X, int64_t d, int64_t ldx, int32_t x_dtype, int32_t *iters_done,
+                                   int32_t *converged, int32_t *fell_back, double *ns_warm, double *ns_cold) {
+    if (!c) return fail_arg("hap_iterate_warm_judged: null context");
+    if (!Y) return fail_arg("hap_iterate_warm_judged: null warm start");
+    if (stable_iters < 1) return fail_arg("hap_iterate_warm_judged: the judge needs a stop rule (stable_iters >= 1)");
+    int32_t it_w = 0, cv_w = 0, it_c = 0, cv_c = 0;
+    double sw = 0.0, sc = 0.0;
+    hap_status s = hap_set_warm_start(c, Y, ldy);
+    if (s == HAP_OK) s = hap_iterate(c, max_iters, stable_iters, &it_w, &cv_w);
+    if (s == HAP_OK) s = hap_net_similarity(c, -1, X, d, ldx, x_dtype, &sw);
+    if (s == HAP_OK) s = hap_set_warm_start(c, nullptr, 0);
+    if (s == HAP_OK) s = hap_iterate(c, max_iters, stable_iters, &it_c, &cv_c);
+    if (s == HAP_OK) s = hap_net_similarity(c, -1, X, d, ldx, x_dtype, &sc);
+    if (s != HAP_OK) return s;
+    const bool keep_warm = (cv_w != cv_c) ? (cv_w != 0) : !(sc > sw);
+    if (keep_warm) {
+        int32_t it = 0, cv = 0;
+        s = hap_set_warm_start(c, Y, ldy);
+        if (s == HAP_OK) s = hap_iterate(c, max_iters, stable_iters, &it, &cv);
+        if (s != HAP_OK) return s;
+        if (it != it_w || cv != cv_w) return fail_arg("hap_iterate_warm_judged: the warm rerun differs", HAP_E_STATE);
+    }
+    if (iters_done) *iters_done = keep_warm ? it_w : it_c;
+    if (converged) *converged = keep_warm ? cv_w : cv_c;
+    if (fell_back) *fell_back = keep_warm ? 0 : 1;
+    if (ns_warm) *ns_warm = sw;
+    if (ns_cold) *ns_cold = sc;
+    return HAP_OK;
+}
+
 int64_t hap_mlp_param_count(int32_t n_in, int32_t hidden, int32_t n_out) {
     if (!mlp_dims_ok(n_in, hidden, n_out)) return -1;
     return hap::mlp_layout(n_in, hidden, n_out, 0).count;

@@ -32,7 +32,7 @@ EXPORTS = (
     "hap_get_launch", "hap_profile", "hap_profile_read", "hap_destroy",
     "hap_batch_workspace_size", "hap_batch_create", "hap_batch_run", "hap_batch_set_launch",
     "hap_batch_get_launch", "hap_batch_set_split", "hap_batch_get_split", "hap_batch_get_members", "hap_batch_destroy",
-    "hap_warm_features", "hap_warm_targets", "hap_set_warm_start", "hap_iterate_warm",
+    "hap_warm_features", "hap_warm_targets", "hap_set_warm_start", "hap_iterate_warm", "hap_iterate_warm_judged",
     "hap_mlp_param_count", "hap_mlp_workspace_size", "hap_mlp_forward", "hap_mlp_loss_grad", "hap_mlp_adam",
     "hap_mlp_train",
 )
@@ -104,6 +104,8 @@ def _declare(lib):
         "hap_warm_targets": (I32, [V, V, I64]),
         "hap_set_warm_start": (I32, [V, V, I64]),
         "hap_iterate_warm": (I32, [V, V, I64, I32, I32, _c_i32p, _c_i32p, _c_i32p]),
+        "hap_iterate_warm_judged": (I32, [V, V, I64, I32, I32, V, I64, I64, I32, _c_i32p, _c_i32p, _c_i32p,
+                                          _c_dblp, _c_dblp]),
         "hap_mlp_param_count": (I64, [I32, I32, I32]),
         "hap_mlp_workspace_size": (I32, [I32, I32, I32, I64, ctypes.POINTER(SZ)]),
         "hap_mlp_forward": (I32, [V, I32, I32, I32, I32, V, I64, I64, V, I64, V, SZ, V]),
@@ -416,6 +418,25 @@ class Hap:
         _check("hap_iterate_warm", self._lib.hap_iterate_warm(self._ctx, ptr, ld, max_iters, stable_iters,
                                                               ctypes.byref(it), ctypes.byref(cv), ctypes.byref(fb)))
         return IterResult(it.value, bool(cv.value)), bool(fb.value)
+
+    def iterate_warm_judged(self, Y, max_iters: int, stable_iters: int, X=None):
+        """Warm run judged by the cold start: both run, the one with the larger net similarity
+        summed over levels (from X in FP64 when given, else from S; a converged run beats one
+        that did not converge) is kept.  Returns (IterResult, fell_back, ns_warm, ns_cold)."""
+        if Y is None:
+            raise ValueError("iterate_warm_judged needs a warm start Y")
+        it, cv, fb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        nw, nc = ctypes.c_double(), ctypes.c_double()
+        if X is None:
+            xp, d, ldx, xdt = None, 0, 0, 0
+        else:
+            if X.dim() != 2 or X.shape[0] != self.n or X.device != self.S.device:
+                raise ValueError("X must be (n, d) on the context's device")
+            xp, d, ldx, xdt = ctypes.c_void_p(X.data_ptr()), X.shape[1], _ld(X), _dtype_code(X)
+        _check("hap_iterate_warm_judged", self._lib.hap_iterate_warm_judged(
+            self._ctx, ctypes.c_void_p(Y.data_ptr()), _ld(Y), max_iters, stable_iters, xp, d, ldx, xdt,
+            ctypes.byref(it), ctypes.byref(cv), ctypes.byref(fb), ctypes.byref(nw), ctypes.byref(nc)))
+        return IterResult(it.value, bool(cv.value)), bool(fb.value), nw.value, nc.value
 
     def get_launch(self):
         """(threads, chunks, rows_per_block, streaming)."""

@@ -280,16 +280,37 @@ def test_end_to_end_warm_start_runs(hap_gpu):
     ex = np.unique(lab)
     assert np.array_equal(lab[ex], ex)
     h.close()
-    # what the network gains (or costs) against the cold start on the same problem; the cold
-    # start judges: a warm run that does not converge is replaced by the cold run's result
+    # the cold start on the same problem
     c = hap_gpu.Hap(to_device(S), 1, 0.9)
     cres = c.iterate(300, 30)
     clab = c.labels().cpu().numpy()[0]
+    cns = c.net_similarity(-1)
     c.close()
-    print(f"warm start: {res.iters} iterations (fell back: {fell}) against cold {cres.iters}; "
-          f"exemplar agreement {np.mean(lab == clab):.3f}")
     if fell:
         assert np.array_equal(lab, clab) and res.iters == cres.iters
+    # the judged form runs both starts and keeps the better net similarity: never worse than
+    # the cold start, and the kept run's labels and stop iteration are exactly that run's
+    j = hap_gpu.Hap(to_device(S), 1, 0.9)
+    jres, jfell, ns_w, ns_c = j.iterate_warm_judged(Y, 300, 30)
+    jlab = j.labels().cpu().numpy()[0]
+    jns = j.net_similarity(-1)
+    j.close()
+    assert ns_c == cns
+    if cres.converged:
+        assert jres.converged
+    assert jns == (ns_c if jfell else ns_w)
+    if jres.converged == cres.converged:
+        assert jns >= cns
+    if jfell:
+        assert np.array_equal(jlab, clab) and jres.iters == cres.iters
+    else:
+        assert np.array_equal(jlab, lab) and jres.iters == res.iters
+    # the form's own bar (fewer sweeps than the cold start, with the same exemplars): recorded
+    # as an expected failure with the measured figures when it is not met
+    agree = float(np.mean(lab == clab))
+    if fell or res.iters >= cres.iters or agree < 0.999:
+        pytest.xfail(f"warm start misses its bar: warm {res.iters} iterations (fell back: {fell}) "
+                     f"against cold {cres.iters}, exemplar agreement {agree:.3f}")
 
 
 def test_full_size_features_on_sampled_rows(hap_gpu):
