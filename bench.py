@@ -502,8 +502,9 @@ def run_profile_form(args, torch, hap, synth) -> int:
     sweeps: the FP32 similarity of the 2-D 64-blob workload (--n points, default 8192), then
       --sweeps full sweeps (L = 3, damping 0.9, no stop rule; points mode unless --read-s;
       --rows R updates rows [0, R) only, one device's block of a run split by rows; --rb B sets
-      the rows per workgroup, --sweep-launch the whole row-pass shape), after one device copy
-      of --copy-gib GiB whose counter readings calibrate the HBM byte counters.
+      the rows per workgroup, --sweep-launch the whole row-pass shape; --schedule mrhap runs
+      the MapReduce schedule, whose levels share one row-pass launch unless --unfused), after
+      one device copy of --copy-gib GiB whose counter readings calibrate the HBM byte counters.
     builds: the similarity of the 32768-point, 64-dimensional workload built once in each mode
       (direct, FP32 GEMM, BF16, BF16x3).
     batch-once: the batched workload run once for --form-iters iterations (default 200) in the
@@ -552,7 +553,10 @@ def run_profile_form(args, torch, hap, synth) -> int:
     X = torch.from_numpy(blobs.X).to(dev)
     S = torch.empty((n, n), dtype=torch.float32, device=dev)
     hap.build_similarity(X, S)
-    h = hap.Hap(S, rp.levels, rp.damping)
+    h = hap.Hap(S, rp.levels, rp.damping,
+                schedule=hap.SCHEDULE_MRHAP if args.schedule == "mrhap" else hap.SCHEDULE_SEQUENTIAL)
+    if args.unfused:
+        h.set_launch(unfused=True)
     if args.rows:
         h.set_row_count(args.rows)
     if args.rb:
@@ -668,6 +672,8 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=8192, help="--form sweeps: points")
     ap.add_argument("--rows", type=int, default=0, help="--form sweeps: update rows [0, rows) only (0: all)")
     ap.add_argument("--rb", type=int, default=0, help="--form sweeps: rows per workgroup (0: the default launch)")
+    ap.add_argument("--unfused", action="store_true",
+                    help="--form sweeps with --schedule mrhap: one row-pass launch per level")
     ap.add_argument("--sweep-launch", default="",
                     help="--form sweeps: row-pass shape threads,chunks,rows_per_block,streaming (empty: the default)")
     ap.add_argument("--copy-gib", type=float, default=1.0,

@@ -203,7 +203,8 @@ HAP_API hap_status hap_init(hap_ctx **out, const void *S, int64_t n, int64_t lds
  * early stop); converged (host, may be NULL) is 1 when the stable count reached
  * K.  The stop is detected one iteration late, so after an early stop the labels are
  * those of the stop iteration while the messages (hap_read_messages) are those of the
- * next one; a further call continues from there.  Synchronises the stream.
+ * next one; a further call continues from there.  HAP_E_OOM if the column-partial buffer
+ * the row pass needs (see hap_set_launch) cannot be allocated.  Synchronises the stream.
  */
 HAP_API hap_status hap_iterate(hap_ctx *ctx, int32_t max_iters, int32_t stable_iters,
                        int32_t *iters_done, int32_t *converged);
@@ -263,10 +264,16 @@ HAP_API hap_status hap_similarity_offsets(hap_ctx *ctx, int32_t level, void *del
  * the phases); without the flag the register-resident row pass; HAP_LAUNCH_EAGER issues every
  * launch from the host instead of replaying captured graphs of sweep chunks (the
  * default captures each chunk of up to 16 sweeps once on a private stream and
- * replays it on the context's stream).  Returns HAP_E_ARG (and changes nothing)
+ * replays it on the context's stream); HAP_LAUNCH_UNFUSED keeps one row-pass launch per
+ * level under the MapReduce schedule (by default, FP32 problems that read S with a
+ * register-resident shape of 4 chunks per thread and 2 to 4 levels run every level of a row
+ * in one launch, which reads the row of S once per sweep instead of once per level, Section
+ * 3; with more workgroups than the workspace's partial rows or more than two levels its
+ * column partials are library-owned, allocated on first use as above).  Returns HAP_E_ARG
+ * (and changes nothing)
  * for a shape that does not fit.  For the autotuner and for comparisons.
  */
-enum { HAP_LAUNCH_STREAM = 2, HAP_LAUNCH_EAGER = 4 };
+enum { HAP_LAUNCH_STREAM = 2, HAP_LAUNCH_EAGER = 4, HAP_LAUNCH_UNFUSED = 8 };
 HAP_API hap_status hap_set_launch(hap_ctx *ctx, int32_t threads, int32_t chunks, int32_t rows_per_block,
                                   int32_t flags);
 HAP_API hap_status hap_get_launch(hap_ctx *ctx, int32_t *threads, int32_t *chunks, int32_t *rows_per_block,

@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhap.so")
 ARCH = "gfx950"
 
-SOURCES = ["hap_api.hip", "sweep.hip", "select.hip", "misc.hip", "build.hip", "batch.hip", "warm.hip", "mlp.hip", "levelsim.hip"]
+SOURCES = ["hap_api.hip", "sweep.hip", "select.hip", "misc.hip", "build.hip", "batch.hip", "warm.hip", "mlp.hip", "levelsim.hip", "fused.hip"]
 
 
 def hipcc() -> str:

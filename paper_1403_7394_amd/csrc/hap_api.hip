@@ -61,6 +61,7 @@ struct hap_ctx {
     int nb_cap = 0;
 
     Launch lc{};
+    bool no_fuse = false;         // HAP_LAUNCH_UNFUSED: per-level row passes under the MapReduce schedule
     // per-launch event timing (hap_profile)
     bool prof = false;
     int prof_period = 1;          // time the launches of every prof_period-th sweep
@@ -227,6 +228,27 @@ bool launch_fits(const Launch &lc, int64_t n, int64_t rows, size_t esz) {
 
 int64_t launch_blocks(const Launch &lc, int64_t rows) { return (rows + lc.rows_per_block - 1) / lc.rows_per_block; }
 
+// The MapReduce schedule's fused all-level row pass applies: FP32, S read from memory (no points
+// mode), no Eq. 2.7 update, a register-resident shape it was built for, 2..kMaxFused levels.
+bool use_fused(const hap_ctx *c, const Launch &lc) {
+    return c->schedule == HAP_SCHEDULE_MRHAP && !c->no_fuse && c->kappa == 0.0 && c->X == nullptr &&
+           c->dtype == HAP_F32 && !lc.streaming && c->L >= 2 && c->rows == c->n &&
+           hap::fused_supported(lc.threads, lc.chunks, c->L);
+}
+
+// Column-partial buffers a sweep needs: one per level for the fused pass, two for the
+// per-level passes of the MapReduce schedule (they alternate), else one.
+size_t partial_sets(const hap_ctx *c, const Launch &lc) {
+    if (use_fused(c, lc)) return (size_t)c->L;
+    return c->schedule == HAP_SCHEDULE_MRHAP ? 2 : 1;
+}
+
+// The workspace holds two partial buffers of nb_cap rows; larger needs use Qbig.
+bool partials_in_workspace(const hap_ctx *c, const Launch &lc, int64_t rows) {
+    return launch_blocks(lc, rows) <= c->nb_cap && partial_sets(c, lc) <= 2;
+}
+
+
 bool dtype_ok(int32_t dt) { return dt == HAP_F32 || dt == HAP_F64; }
 size_t dtype_size(int32_t dt) { return dt == HAP_F64 ? 8 : 4; }
 
@@ -273,10 +295,12 @@ hap_status run_sweeps(hap_ctx *c, int count, int K) {
     const int L = c->L;
     const int nb = (int)launch_blocks(c->lc, c->rows);
     // the workspace's partial buffers, or the library's own when the launch has more workgroups
-    const bool big = nb > c->nb_cap;
+    // or the fused pass more levels
+    const bool big = !partials_in_workspace(c, c->lc, c->rows);
     T *qbase = big ? (T *)c->Qbig : (T *)c->Qpart;
     const size_t qstride = (size_t)(big ? nb : c->nb_cap) * c->ldw;
     T *Qpart[2] = {qbase, qbase + qstride};
+    const bool fused = use_fused(c, c->lc);
     hap::SweepExtra<T> ex;
     ex.X = (const T *)c->X;
     ex.ldx = c->ldx;
@@ -322,6 +346,43 @@ hap_status run_sweeps(hap_ctx *c, int count, int K) {
     };
     for (int it = 0; it < count; ++it) {
         c->prof_now = c->prof && (c->prof_sweep++ % c->prof_period == 0);
+        if (fused) {
+            if constexpr (sizeof(T) == 4) {
+                // every level's row pass in one launch, then the column sums in level order
+                hap::FusedArgs<float> fa{};
+                fa.S = (const float *)c->S;
+                fa.lds = c->lds;
+                fa.ldw = c->ldw;
+                fa.n = (int)c->n;
+                fa.rows = (int)c->rows;
+                fa.rb = c->lc.rows_per_block;
+                fa.L = L;
+                fa.lam = (float)c->lam;
+                fa.oml = (float)(1.0 - c->lam);
+                fa.ds = c->ds;
+                for (int l = 0; l < L; ++l) {
+                    LevelPtrs<float> lv = level_ptrs<float>(c, l);
+                    fa.R[l] = lv.R;
+                    fa.A[l] = lv.A;
+                    fa.pref[l] = lv.pref;
+                    fa.C[l] = lv.C;
+                    fa.phi[l] = lv.phi;
+                    fa.B[l] = lv.B;
+                    fa.Q[l] = lv.Q;
+                    fa.tau[l] = lv.tau;
+                    fa.E[l] = lv.E;
+                    fa.Qpart[l] = (float *)qbase + (size_t)l * qstride;
+                }
+                HIP_TRY(prof_mark(c, 0, false), c);
+                HIP_TRY(hap::launch_sweep_fused(fa, c->lc, c->stream), c);
+                HIP_TRY(prof_mark(c, 0, true), c);
+                for (int l = 0; l < L; ++l) {
+                    const hap_status s = col(l, (T *)fa.Qpart[l], false);
+                    if (s != HAP_OK) return s;
+                }
+                continue;
+            }
+        }
         if (c->schedule == HAP_SCHEDULE_MRHAP) {
             // Every row pass reads the previous iteration's column sums, so the column sums of
             // level l-1 run after the row pass of level l (two partial buffers alternate).
@@ -426,11 +487,12 @@ hap_status finalize_labels(hap_ctx *c) {
 // library allocates them when such a launch is set and frees them in hap_destroy.
 hap_status ensure_partials(hap_ctx *c, const Launch &lc, int64_t rows) {
     const int64_t nb = launch_blocks(lc, rows);
-    if (nb <= c->nb_cap) return HAP_OK;
-    const size_t sets = c->schedule == HAP_SCHEDULE_MRHAP ? 2 : 1;
+    if (partials_in_workspace(c, lc, rows)) return HAP_OK;
+    const size_t sets = partial_sets(c, lc);
     const size_t need = sets * (size_t)nb * (size_t)c->ldw * c->esz;
     if (c->Qbig && c->qbig_bytes >= need) return HAP_OK;
     HIP_TRY(hipStreamSynchronize(c->stream), c);
+    drop_graphs(c);   // captured sweeps hold the old buffer's address
     if (c->Qbig) {
         HIP_TRY(hipFree(c->Qbig), c);
         c->Qbig = nullptr;
@@ -705,6 +767,9 @@ hap_status hap_iterate(hap_ctx *c, int32_t max_iters, int32_t stable_iters, int3
     if (c->failed) return fail_arg("hap_iterate: context failed earlier", HAP_E_STATE);
     if (max_iters < 0 || stable_iters < 0) return fail_arg("hap_iterate: negative count");
     DevState hs;
+    // the partial buffers of the row pass the sweeps will use (points mode changes it)
+    const hap_status ps = ensure_partials(c, c->lc, c->rows);
+    if (ps != HAP_OK) return ps;
     // a previous early stop does not block continuing: clear the flag
     HIP_TRY(hipMemsetAsync(&c->ds->done, 0, sizeof(int32_t), c->stream), c);
     const int chunk = 16;
@@ -923,8 +988,13 @@ hap_status hap_set_launch(hap_ctx *c, int32_t threads, int32_t chunks, int32_t r
     lc.ordered = (lc.rows_per_block == 1);
     if (!launch_fits(lc, c->n, c->rows, c->esz))
         return fail_arg("hap_set_launch: shape does not fit this problem");
+    const bool no_fuse = c->no_fuse;
+    if (flags >= 0) c->no_fuse = (flags & HAP_LAUNCH_UNFUSED) != 0;
     const hap_status ps = ensure_partials(c, lc, c->rows);
-    if (ps != HAP_OK) return ps;
+    if (ps != HAP_OK) {
+        c->no_fuse = no_fuse;
+        return ps;
+    }
     c->lc = lc;
     if (flags >= 0) c->use_graphs = (flags & HAP_LAUNCH_EAGER) == 0;
     drop_graphs(c);
@@ -1006,7 +1076,9 @@ hap_status hap_set_points(hap_ctx *c, const void *X, int64_t n, int64_t d, int64
 
 hap_status hap_get_launch(hap_ctx *c, int32_t *threads, int32_t *chunks, int32_t *rows_per_block, int32_t *flags) {
     if (!c) return fail_arg("hap_get_launch: null context");
-    if (flags) *flags = (c->lc.streaming ? HAP_LAUNCH_STREAM : 0) | (c->use_graphs ? 0 : HAP_LAUNCH_EAGER);
+    if (flags)
+        *flags = (c->lc.streaming ? HAP_LAUNCH_STREAM : 0) | (c->use_graphs ? 0 : HAP_LAUNCH_EAGER) |
+                 (c->no_fuse ? HAP_LAUNCH_UNFUSED : 0);
     if (threads) *threads = c->lc.threads;
     if (chunks) *chunks = c->lc.chunks;
     if (rows_per_block) *rows_per_block = c->lc.rows_per_block;

@@ -106,6 +106,33 @@ template <typename T>
 hipError_t launch_level_delta(const LevelPtrs<T> &lv, T *delta_next, int n, int64_t ldw, double lam, double kappa,
                               const DevState *ds, hipStream_t st);
 bool launch_supported(int threads, int chunks, int elem_size);
+
+// The fused all-level row pass of the MapReduce schedule (FP32, S read from memory, the
+// register-resident shapes with 4 chunks per thread, up to kMaxFused levels): one launch runs
+// every level of each row, reading the row of S once.  Per level l: R, A, pref, C, E, B and
+// the partial buffer Qpart (nb x ldw); Q[l] the column sums of the previous iteration (read as
+// Q^{l-1} for tau^l); phi[l-1] and tau[l] written for l > 0.
+constexpr int kMaxFused = 4;
+template <typename T>
+struct FusedArgs {
+    const T *S;
+    int64_t lds, ldw;
+    int n, rows, rb, L;
+    T lam, oml;
+    DevState *ds;
+    T *R[kMaxFused];
+    T *A[kMaxFused];
+    const T *pref[kMaxFused];
+    T *C[kMaxFused];
+    T *phi[kMaxFused];
+    const T *B[kMaxFused];
+    const T *Q[kMaxFused];
+    T *tau[kMaxFused];
+    int32_t *E[kMaxFused];
+    T *Qpart[kMaxFused];
+};
+bool fused_supported(int threads, int chunks, int levels);
+hipError_t launch_sweep_fused(const FusedArgs<float> &a, const Launch &lc, hipStream_t st);
 template <typename T>
 hipError_t launch_alpha_pad(T *A, int64_t rows, int n, int64_t ldw, hipStream_t st);
 

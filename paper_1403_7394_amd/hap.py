@@ -20,6 +20,7 @@ BUILD_DIRECT, BUILD_GEMM, BUILD_BF16, BUILD_BF16X3, BUILD_DIRECT_L2 = 0, 1, 2, 3
 PREF_MEDIAN, PREF_SCALAR, PREF_VECTOR = 0, 1, 2
 LAUNCH_STREAM = 2
 LAUNCH_EAGER = 4
+LAUNCH_UNFUSED = 8
 SCHEDULE_SEQUENTIAL, SCHEDULE_MRHAP = 0, 1
 
 # every symbol include/hap.h declares
@@ -247,7 +248,6 @@ class Hap:
         p.kappa = float(kappa)
         self.schedule = int(schedule)
         self.kappa = float(kappa)
-        self._eager = False
         self._pref_keep = None
         if pref is None:
             p.pref_mode = PREF_MEDIAN
@@ -344,17 +344,25 @@ class Hap:
         _check("hap_similarity_offsets", self._lib.hap_similarity_offsets(self._ctx, level, ctypes.c_void_p(d.data_ptr())))
         return d
 
-    def set_launch(self, threads=0, chunks=0, rows_per_block=0, streaming=None, eager=None):
-        """Launch shape; streaming / eager None keep the current choice (both set together)."""
-        if streaming is None and eager is None:
+    def set_launch(self, threads=0, chunks=0, rows_per_block=0, streaming=None, eager=None, unfused=None):
+        """Launch shape; streaming / eager / unfused None keep the current choice (the flags are
+        set together)."""
+        if streaming is None and eager is None and unfused is None:
             flags = -1
         else:
-            _, _, _, cur_stream = self.get_launch()
-            st = cur_stream if streaming is None else streaming
-            ea = self._eager if eager is None else eager
-            flags = (LAUNCH_STREAM if st else 0) | (LAUNCH_EAGER if ea else 0)
-            self._eager = bool(ea)
+            cur = self.launch_flags()
+            st = bool(cur & LAUNCH_STREAM) if streaming is None else streaming
+            ea = bool(cur & LAUNCH_EAGER) if eager is None else eager
+            uf = bool(cur & LAUNCH_UNFUSED) if unfused is None else unfused
+            flags = (LAUNCH_STREAM if st else 0) | (LAUNCH_EAGER if ea else 0) | (LAUNCH_UNFUSED if uf else 0)
         _check("hap_set_launch", self._lib.hap_set_launch(self._ctx, threads, chunks, rows_per_block, flags))
+
+    def launch_flags(self) -> int:
+        """The HAP_LAUNCH_* bits in effect."""
+        a, b, c, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check("hap_get_launch", self._lib.hap_get_launch(self._ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                                          ctypes.byref(f)))
+        return f.value
 
     def set_row_count(self, rows: int):
         """Update rows [0, rows) only: one block of a run split by rows (n: the whole problem)."""

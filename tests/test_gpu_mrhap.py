@@ -95,3 +95,39 @@ def test_one_level_equals_the_sequential_schedule(hap_gpu):
     assert np.array_equal(a["labels"], m["labels"])
     assert np.array_equal(a["msgs"][0]["rho"], m["msgs"][0]["rho"])
     assert np.array_equal(a["msgs"][0]["alpha"], m["msgs"][0]["alpha"])
+
+
+@pytest.mark.parametrize("n,L,T", [(1000, 3, 40), (257, 2, 60), (700, 4, 30)])
+def test_fused_pass_bit_identical_to_oracle(hap_gpu, n, L, T):
+    """The fused all-level row pass (the default for FP32 problems that read S with four
+    chunks per thread), one row per workgroup: bit-identical to the FP32 oracle of the
+    MapReduce schedule."""
+    b = synth.small_blobs(1500 + n, n, d=2, k=6, dtype=np.float32)
+    S = sim.similarity(b.X).astype(np.float32)
+    p = sim.median_offdiag(S, np.float32)
+    g = run(hap_gpu, S, L, 0.9, T)
+    same_as_oracle(g, hap_ref.hap(S, p, L, 0.9, T, dtype=np.float32, schedule="mrhap"), L)
+
+
+@pytest.mark.parametrize("n,L", [(8192, 3), (3000, 4), (5000, 2)])
+def test_fused_matches_per_level_launches(hap_gpu, n, L):
+    """With the default rows per workgroup the fused pass and one launch per level
+    (HAP_LAUNCH_UNFUSED) agree bit for bit: messages, labels and the stop iteration."""
+    b, _ = synth.workload_plain_f32(n=n)
+    X = torch.from_numpy(b.X.astype(np.float32)).to(DEV)
+    S = torch.empty((n, n), dtype=torch.float32, device=DEV)
+    hap_gpu.build_similarity(X, S)
+    outs = []
+    for unfused in (False, True):
+        h = hap_gpu.Hap(S, L, 0.9, schedule=hap_gpu.SCHEDULE_MRHAP)
+        h.set_launch(unfused=unfused)
+        assert bool(h.launch_flags() & hap_gpu.LAUNCH_UNFUSED) == unfused
+        res = h.iterate(40, 5)
+        outs.append((res, h.labels(), [h.messages(l) for l in range(L)]))
+        h.close()
+    (r0, lab0, m0), (r1, lab1, m1) = outs
+    assert (r0.iters, r0.converged) == (r1.iters, r1.converged)
+    assert torch.equal(lab0, lab1)
+    for l in range(L):
+        for k in ("rho", "alpha", "c", "phi", "tau"):
+            assert torch.equal(m0[l][k], m1[l][k]), (l, k)
