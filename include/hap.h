@@ -261,7 +261,15 @@ HAP_API hap_status hap_similarity_offsets(hap_ctx *ctx, int32_t level, void *del
  * to 16 chunks the streaming pass (the row is read again from the caches in its second
  * phase), with 512 threads and 16 chunks (FP32 only, n <= 32768, the default for
  * 16384 < n <= 32768) the held-row pass (the row's s and rho stay in registers between
- * the phases); without the flag the register-resident row pass; HAP_LAUNCH_EAGER issues every
+ * the phases), with 512 (or 64) threads and 32 chunks the paired pass (FP32 only,
+ * threads*64 < n <= threads*128; the default for 32768 < n <= 65536 with 128 pairs): two
+ * workgroups share each block of rows_per_block rows, each holding half of every row as
+ * the held-row pass does, and exchange the row maxima once per row through device memory;
+ * every workgroup of the launch (2 per block, rounded up to 16) must be resident on the
+ * device at once, so a shape whose grid exceeds the device's capacity returns HAP_E_ARG,
+ * and if another kernel holds part of the device so that a partner never arrives, the
+ * waits give up after two seconds and hap_iterate returns HAP_E_HIP with the context
+ * failed; without the flag the register-resident row pass; HAP_LAUNCH_EAGER issues every
  * launch from the host instead of replaying captured graphs of sweep chunks (the
  * default captures each chunk of up to 16 sweeps once on a private stream and
  * replays it on the context's stream); HAP_LAUNCH_UNFUSED keeps one row-pass launch per

@@ -76,6 +76,9 @@ def sweep_candidates(n: int, elem_size: int):
         if elem_size == 4 and 16384 < n <= 512 * 16 * 4:
             for rb in sorted({max(1, n // 256), max(1, n // 512)}):
                 out.append((512, 16, rb, True))   # the held-row pass
+        if elem_size == 4 and 512 * 16 * 4 < n <= 512 * 32 * 4:
+            for pairs in (128, 64):
+                out.append((512, 32, -(-n // pairs), True))   # the paired pass
     return out
 
 

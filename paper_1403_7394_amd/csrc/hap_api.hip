@@ -62,6 +62,9 @@ struct hap_ctx {
 
     Launch lc{};
     bool no_fuse = false;         // HAP_LAUNCH_UNFUSED: per-level row passes under the MapReduce schedule
+    // the paired row pass's exchange slots (library-owned, allocated with its first launch shape)
+    uint64_t *pair_slots = nullptr;
+    uint64_t pair_wait = 0;       // wall-clock ticks one of its waits may take
     // per-launch event timing (hap_profile)
     bool prof = false;
     int prof_period = 1;          // time the launches of every prof_period-th sweep
@@ -91,6 +94,7 @@ struct hap_ctx {
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int64_t kMaxPairs = 2048;   // pairs of the paired row pass's largest launch
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
@@ -184,6 +188,16 @@ Launch default_launch(int64_t n, size_t esz) {
             found = true;
         }
     }
+    if (!found && esz == 4 && n > 512 * 16 * 4 && n <= 512 * 32 * 4) {
+        // FP32 rows of up to 65536 columns: the paired pass, two workgroups of 512 threads x 16
+        // chunks per block of rows, 128 pairs (256 workgroups, one per CU)
+        lc.threads = 512;
+        lc.chunks = 32;
+        lc.streaming = true;
+        lc.rows_per_block = (int)((n + 127) / 128);
+        lc.ordered = false;
+        return lc;
+    }
     if (!found && esz == 4 && n > 512 * 8 * 4 && n <= 512 * 16 * 4) {
         // FP32 rows of up to 32768 columns: the held-row pass (512 threads x 16 chunks keep the
         // row's s and rho in registers between the two phases)
@@ -215,6 +229,15 @@ Launch default_launch(int64_t n, size_t esz) {
 
 bool launch_fits(const Launch &lc, int64_t n, int64_t rows, size_t esz) {
     const int64_t vw = (int64_t)(16 / esz);
+    if (lc.streaming && lc.chunks == 32) {
+        // the paired pass: FP32, each half of a row within one workgroup's 16 chunks, and the
+        // whole grid resident at once
+        if (esz != 4 || (lc.threads != 512 && lc.threads != 64)) return false;
+        const int64_t h = (int64_t)lc.threads * 16 * 4;
+        if (n <= h || n > 2 * h || lc.rows_per_block < 1) return false;
+        const int64_t grid = hap::pair_grid(rows, lc.rows_per_block);
+        return grid / 2 <= kMaxPairs && grid <= hap::pair_capacity(lc.threads);
+    }
     if (lc.streaming) {
         const bool held = lc.threads == 512 && lc.chunks == 16 && esz == 4;
         if (lc.threads != 1024 && !held) return false;
@@ -314,6 +337,9 @@ hap_status run_sweeps(hap_ctx *c, int count, int K) {
         // previous iteration, the row pass applies this iteration's)
         T *phi_down = (l > 0 && !kappa) ? down.phi : nullptr;
         hap::SweepExtra<T> e = ex;
+        e.pair_slots = c->pair_slots;
+        e.pair_wait = c->pair_wait;
+        e.pair_level = l;
         if (kappa && l > 0) e.delta = lv.delta;
         const T *tau_l = nullptr;
         if (c->schedule == HAP_SCHEDULE_MRHAP) {
@@ -485,7 +511,27 @@ hap_status finalize_labels(hap_ctx *c) {
 // Column partials for a launch with more workgroups than the workspace holds: one row of ldw
 // words per workgroup (two sets under the MapReduce schedule, whose passes alternate).  The
 // library allocates them when such a launch is set and frees them in hap_destroy.
+// The paired pass's exchange slots: room for the most pairs any launch can hold, all ones.
+hap_status ensure_pair_slots(hap_ctx *c, const Launch &lc) {
+    if (!(lc.streaming && lc.chunks == 32) || c->pair_slots) return HAP_OK;
+    const size_t bytes = (size_t)hap::kPairSlotWords * kMaxPairs * sizeof(uint64_t);
+    HIP_TRY(hipStreamSynchronize(c->stream), c);
+    drop_graphs(c);
+    if (hipMalloc((void **)&c->pair_slots, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        c->pair_slots = nullptr;
+        return fail_arg("paired row pass: hipMalloc of its exchange slots failed", HAP_E_OOM);
+    }
+    HIP_TRY(hipMemsetAsync(c->pair_slots, 0xff, bytes, c->stream), c);
+    int khz = 0;
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device), c);
+    c->pair_wait = (uint64_t)khz * 2000;   // two seconds
+    return HAP_OK;
+}
+
 hap_status ensure_partials(hap_ctx *c, const Launch &lc, int64_t rows) {
+    const hap_status ss = ensure_pair_slots(c, lc);
+    if (ss != HAP_OK) return ss;
     const int64_t nb = launch_blocks(lc, rows);
     if (partials_in_workspace(c, lc, rows)) return HAP_OK;
     const size_t sets = partial_sets(c, lc);
@@ -659,6 +705,12 @@ hap_status hap_init(hap_ctx **out, const void *S, int64_t n, int64_t lds, int32_
     const size_t esz = dtype_size(dtype);
     Layout lo = make_layout(n, p->levels, esz);
     Launch lc = default_launch(n, esz);
+    if (lc.streaming && lc.chunks == 32 && !launch_fits(lc, n, n, esz)) {
+        // the device holds fewer workgroups at once than the paired pass needs: stream the rows
+        lc.threads = 1024;
+        lc.chunks = (int)((n + 4095) / 4096);
+        lc.rows_per_block = (int)((n + 255) / 256);
+    }
     if (lc.threads == 0 || !launch_fits(lc, n, n, esz) || launch_blocks(lc, n) > lo.nb_cap)
         return fail_arg("hap_init: n too large (at most 65536 points in FP32, 32768 in FP64)", HAP_E_UNSUPPORTED);
     if (workspace) {
@@ -796,6 +848,12 @@ hap_status hap_iterate(hap_ctx *c, int32_t max_iters, int32_t stable_iters, int3
     }
     HIP_TRY(hipMemcpyAsync(&hs, c->ds, sizeof(DevState), hipMemcpyDeviceToHost, c->stream), c);
     HIP_TRY(hipStreamSynchronize(c->stream), c);
+    if (hs.pair_abort) {
+        c->failed = true;
+        return fail_arg("hap_iterate: the paired row pass gave up waiting for a partner workgroup (part of the "
+                        "device was busy); the state is not valid",
+                        HAP_E_HIP);
+    }
     c->t_host = hs.t;
     int conv = 0, done_iter = hs.t;
     if (stopped || hs.done) {
@@ -1127,6 +1185,10 @@ hap_status hap_destroy(hap_ctx *c) {
         e = hipFree(c->ws);
         if (e != hipSuccess && s == HAP_OK) s = fail_hip(e, "hap_destroy: hipFree");
     }
+    if (c->pair_slots) {
+        e = hipFree(c->pair_slots);
+        if (e != hipSuccess && s == HAP_OK) s = fail_hip(e, "hap_destroy: hipFree");
+    }
     if (c->Qbig) {
         e = hipFree(c->Qbig);
         if (e != hipSuccess && s == HAP_OK) s = fail_hip(e, "hap_destroy: hipFree");
@@ -1406,6 +1468,9 @@ hap_status restart_state(hap_ctx *c, const float *Y, int64_t ldy) {
     HIP_TRY(hipMemsetAsync(base + lo.R, 0, lo.pref - lo.R, st), c);
     HIP_TRY(hipMemsetAsync(base + lo.Q, 0, lo.Qpart - lo.Q, st), c);
     HIP_TRY(hipMemsetAsync(c->ds, 0, sizeof(DevState), st), c);
+    if (c->pair_slots)
+        HIP_TRY(hipMemsetAsync(c->pair_slots, 0xff, (size_t)hap::kPairSlotWords * kMaxPairs * sizeof(uint64_t), st),
+                c);
     HIP_TRY(hap::launch_alpha_pad<T>((T *)c->A, (int64_t)c->L * c->n, (int)c->n, c->ldw, st), c);
     if (Y) {
         for (int l = 0; l < c->L; ++l) {

@@ -19,7 +19,8 @@ struct DevState {
     int32_t stop_iter;      // iteration at which the run stopped
     int32_t changed;        // set by the row pass when any label changed in the current sweep
     int32_t final_changed;  // set by the finalize pass when e^t differs from e^{t-1}
-    int32_t pad[2];
+    int32_t pair_abort;     // set when a paired row pass gave up waiting for a partner workgroup
+    int32_t pad;
 };
 
 // 16-byte vectors: 4 floats or 2 doubles per lane access.
@@ -77,7 +78,23 @@ struct SweepExtra {
     int mrhap = 0;
     const T *delta = nullptr;   // Eq. 2.7 row offsets of this level's similarity
     int rows = 0;               // rows [0, rows) only (one block of a run split by rows); 0: all
+    uint64_t *pair_slots = nullptr;   // the paired row pass's exchange slots (kPairSlotWords per pair)
+    uint64_t pair_wait = 0;           // wall-clock ticks one of its waits may take
+    int pair_level = 0;               // the level this launch updates (part of the exchange tags)
 };
+// The paired row pass (FP32 rows of 32768 < n <= 65536, two workgroups per block of rows):
+// exchange slots in device memory, 20 words per pair, initialised to all ones (a tag no row
+// carries).
+struct PairArgs {
+    uint64_t *slots;
+    uint64_t wait_ticks;
+    int level;
+};
+constexpr int kPairSlotWords = 20;
+// Workgroups of the paired pass's launch that the device holds at once (the grid must fit).
+int pair_capacity(int threads);
+// Workgroups the paired pass launches for a block of rb rows per pair.
+int64_t pair_grid(int64_t rows, int64_t rb);
 template <typename T>
 hipError_t launch_sweep_level(const T *S, int64_t lds, const LevelPtrs<T> &lv, T *phi_down,
                               const T *tau_l, int n, int64_t ldw, double lam, T *Qpart, const Launch &lc,

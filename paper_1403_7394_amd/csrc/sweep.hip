@@ -421,11 +421,82 @@ __device__ __forceinline__ void stream_rows_unpipelined(const SweepArgs<T> &a, c
 // partials live in LDS.  Phase 1's loads run one chunk ahead of the arithmetic, and the next
 // row's first chunk is loaded during phase 2's last.  The per-row scalars are staged in LDS per
 // window of kWin rows, so that no global load issued after those loads is waited for in a row.
-template <int NT, int NCH, bool FIRST, bool TAIL>
+//
+// PAIR: the paired pass for rows twice as long (32768 < n <= 65536 at 512 threads): two
+// workgroups share a block of rows, one holding columns [0, H) and the other [H, n) of every
+// row (H = NT*NCH*4), each exactly as above on its half.  Between the phases of a row each
+// workgroup publishes its half's (M1, k1, M2) and (c, e) and merges the partner's: thread 0
+// writes five 64-bit words, each a value with a tag naming the sweep and the row in its upper
+// half, with relaxed device-scope atomic stores, and polls the partner's five words until all
+// carry the tag of the row, level and sweep (per-word tags need no fences: each word is read whole), with a
+// wall-clock bound.  Two slots per side, by row parity, are enough: a workgroup can publish
+// row i + 2 only after it has read the partner's row i + 1, which the partner publishes after it
+// has read row i.  A wait that gives up sets a flag (sticky, checked by the host, which fails
+// the run) that ends every other wait at once, so the launch always drains.
+struct HeldPair {
+    uint64_t *mine, *theirs;   // this side's and the partner's slots: [2 row parities][5 words]
+    int32_t *abort;
+    uint64_t limit;            // wall-clock ticks one wait may take
+    int side;
+    int level;
+};
+
+__device__ __forceinline__ void pair_exchange(const HeldPair &hp, int row, int t, float &m1, int &k1, float &m2,
+                                              float &cv, int &ck) {
+    // the tag names the sweep, the level and the row: consecutive launches (the next level, or
+    // the next sweep's first) always differ in it, so a slot a pair left in its last launch
+    // never passes for the current one
+    const uint32_t tag = ((uint32_t)(t & 0x3ff) << 22) | ((uint32_t)(hp.level & 0x1f) << 17) | (uint32_t)row;
+    uint64_t *mine = hp.mine + (row & 1) * 5;
+    const uint64_t *theirs = hp.theirs + (row & 1) * 5;
+    const uint32_t out[5] = {__float_as_uint(m1), (uint32_t)k1, __float_as_uint(m2), __float_as_uint(cv),
+                             (uint32_t)ck};
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+        __hip_atomic_store(mine + k, ((uint64_t)tag << 32) | out[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t w[5];
+    bool ok = false;
+    const uint64_t t0 = wall_clock64();
+    for (;;) {
+        bool all = true;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            w[k] = __hip_atomic_load(theirs + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            all = all && (uint32_t)(w[k] >> 32) == tag;
+        }
+        if (all) {
+            ok = true;
+            break;
+        }
+        if (__hip_atomic_load(hp.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+        if ((uint64_t)wall_clock64() - t0 > hp.limit) {
+            __hip_atomic_store(hp.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    if (!ok) return;   // the run is failed; this half's values stand
+    const float om1 = __uint_as_float((uint32_t)w[0]), om2 = __uint_as_float((uint32_t)w[2]);
+    const float ocv = __uint_as_float((uint32_t)w[3]);
+    const int ok1 = (int)(uint32_t)w[1], ock = (int)(uint32_t)w[4];
+    // both sides merge the lower half first (the merges are exact, so this only fixes the form)
+    if (hp.side == 0) {
+        top2_merge(m1, k1, m2, om1, ok1, om2);
+        argmax_merge(cv, ck, ocv, ock);
+    } else {
+        float a1 = om1, a2 = om2, c1 = ocv;
+        int ak = ok1, cc = ock;
+        top2_merge(a1, ak, a2, m1, k1, m2);
+        argmax_merge(c1, cc, cv, ck);
+        m1 = a1, k1 = ak, m2 = a2, cv = c1, ck = cc;
+    }
+}
+
+template <int NT, int NCH, bool FIRST, bool TAIL, bool PAIR>
 __device__ __forceinline__ void held_rows(const SweepArgs<float> &a, const int t, const int row0, const int row1,
-                                          Vec<float>::type (*qs)[NT], float (*sh_m1)[NT / 64], int (*sh_k1)[NT / 64],
-                                          float (*sh_m2)[NT / 64], float (*sh_cv)[NT / 64],
-                                          int (*sh_ck)[NT / 64]) {
+                                          const int coff, const int ncols, Vec<float>::type (*qs)[NT],
+                                          float (*sh_m1)[NT / 64], int (*sh_k1)[NT / 64], float (*sh_m2)[NT / 64],
+                                          float (*sh_cv)[NT / 64], int (*sh_ck)[NT / 64], const HeldPair &hp) {
 #pragma clang fp contract(off)
     using T = float;
     using V = Vec<float>::type;
@@ -433,13 +504,16 @@ __device__ __forceinline__ void held_rows(const SweepArgs<float> &a, const int t
     constexpr int NW = NT / 64;
     // the wave index is wave-uniform: as a scalar it keeps the LDS slots' addresses out of vector registers
     const int tid = threadIdx.x, lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int n = a.n;
     const int64_t ldw = a.ldw;
     const T lam = a.lam, oml = a.oml;
     const T zero = T(0), ninf = neg_inf<T>();
     const int base = tid * VW;
+    // this workgroup's columns [coff, coff + ncols): the whole row, or one half of it (PAIR)
+    const bool owner = !PAIR || hp.side == 0;   // writes the row's scalars
     __shared__ T st_p[kWin], st_tau[kWin], st_d[kWin];
     __shared__ int st_e[kWin], st_has[kWin];
+    __shared__ T shx_m1[2], shx_m2[2];
+    __shared__ int shx_k1[2];
     V hs[NCH], hr[NCH];            // this row's s (with the diagonal and the Eq. 2.7 offset) and rho^{t-1}
     V sv = (V)(zero), rv = (V)(zero), av = (V)(zero), bv = (V)(zero);   // the next chunk's operands
     // buffer-resource accesses: a resource per row, the lane's byte offset in one register and the
@@ -447,17 +521,19 @@ __device__ __forceinline__ void held_rows(const SweepArgs<float> &a, const int t
     // resource return 0, which the ragged tail overrides)
     constexpr int CB = NT * VW * (int)sizeof(T);
     const int voff = tid * 16;
-    const __amdgpu_buffer_rsrc_t rB = row_rsrc(a.B, ldw * (int64_t)sizeof(T));
+    const int64_t lds_h = a.lds - coff, ldw_h = ldw - coff;   // the resources start at column coff
+    const __amdgpu_buffer_rsrc_t rB = row_rsrc(a.B + coff, ldw_h * (int64_t)sizeof(T));
     auto load1 = [&](int row, int c) {
-        const __amdgpu_buffer_rsrc_t rS = row_rsrc(a.S + (int64_t)row * a.lds, a.lds * (int64_t)sizeof(T));
-        const __amdgpu_buffer_rsrc_t rR = row_rsrc(a.R + (int64_t)row * ldw, ldw * (int64_t)sizeof(T));
-        const __amdgpu_buffer_rsrc_t rA = row_rsrc(a.A + (int64_t)row * ldw, ldw * (int64_t)sizeof(T));
+        const __amdgpu_buffer_rsrc_t rS =
+            row_rsrc(a.S + (int64_t)row * a.lds + coff, lds_h * (int64_t)sizeof(T));
+        const __amdgpu_buffer_rsrc_t rR = row_rsrc(a.R + (int64_t)row * ldw + coff, ldw_h * (int64_t)sizeof(T));
+        const __amdgpu_buffer_rsrc_t rA = row_rsrc(a.A + (int64_t)row * ldw + coff, ldw_h * (int64_t)sizeof(T));
         sv = buf_load<V, kNT>(rS, voff, c * CB);
         rv = buf_load<V, 0>(rR, voff, c * CB);
         av = buf_load<V, 0>(rA, voff, c * CB);
         if constexpr (!FIRST) bv = buf_load<V, 0>(rB, voff, c * CB);
         if constexpr (TAIL) {
-            if (c * NT * VW + base >= n) av = (V)(ninf);   // columns past n never win a maximum
+            if (c * NT * VW + base >= ncols) av = (V)(ninf);   // columns past n never win a maximum
         }
     };
     int buf = 0;
@@ -481,9 +557,9 @@ __device__ __forceinline__ void held_rows(const SweepArgs<float> &a, const int t
         const T p_i = st_p[r];
         const T d_i = st_d[r];
         const bool has_d = a.delta != nullptr;
-        const __amdgpu_buffer_rsrc_t rA = row_rsrc(a.A + (int64_t)i * ldw, ldw * (int64_t)sizeof(T));
-        const __amdgpu_buffer_rsrc_t rR = row_rsrc(a.R + (int64_t)i * ldw, ldw * (int64_t)sizeof(T));
-        int dcol = i - base;
+        const __amdgpu_buffer_rsrc_t rA = row_rsrc(a.A + (int64_t)i * ldw + coff, ldw_h * (int64_t)sizeof(T));
+        const __amdgpu_buffer_rsrc_t rR = row_rsrc(a.R + (int64_t)i * ldw + coff, ldw_h * (int64_t)sizeof(T));
+        int dcol = i - coff - base;
         T m1 = ninf, m2 = ninf, cv = ninf;
         int k1 = INT_MAX, ck = INT_MAX;
         // phase 1: finish alpha^{t-1} (stored), reduce c/e over alpha + rho and the top two of alpha + s
@@ -530,8 +606,8 @@ __device__ __forceinline__ void held_rows(const SweepArgs<float> &a, const int t
             // hoist later chunks' accesses and run out of registers)
             asm volatile("" ::: "memory");
         }
-        k1 = (k1 == INT_MAX) ? INT_MAX : k1 + base;
-        ck = (ck == INT_MAX) ? INT_MAX : ck + base;
+        k1 = (k1 == INT_MAX) ? INT_MAX : k1 + coff + base;
+        ck = (ck == INT_MAX) ? INT_MAX : ck + coff + base;
         wave_reduce<T, !FIRST>(m1, k1, m2, cv, ck);
         if (lane == 0) {
             sh_m1[buf][wid] = m1;
@@ -552,25 +628,45 @@ __device__ __forceinline__ void held_rows(const SweepArgs<float> &a, const int t
         m2 = sh_m2[buf][0];
 #pragma unroll
         for (int w = 1; w < NW; ++w) top2_merge(m1, k1, m2, sh_m1[buf][w], sh_k1[buf][w], sh_m2[buf][w]);
-        if constexpr (!FIRST) {
-            if (tid == 0) {
+        if (tid == 0) {
+            if constexpr (!FIRST) {
                 cv = sh_cv[buf][0];
                 ck = sh_ck[buf][0];
                 for (int w = 1; w < NW; ++w) argmax_merge(cv, ck, sh_cv[buf][w], sh_ck[buf][w]);
+            }
+            if constexpr (PAIR) {
+                // the whole row's values from the two halves, passed to every thread through LDS
+                pair_exchange(hp, i, t, m1, k1, m2, cv, ck);
+                shx_m1[buf] = m1;
+                shx_k1[buf] = k1;
+                shx_m2[buf] = m2;
+            }
+        }
+        if constexpr (PAIR) {
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_waitcnt(0xc07f);
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            m1 = shx_m1[buf];
+            k1 = shx_k1[buf];
+            m2 = shx_m2[buf];
+        }
+        if (owner && tid == 0) {
+            if constexpr (!FIRST) {
                 a.C[i] = cv;
                 if (a.phi_down) a.phi_down[i] = m1;
                 a.E[i] = ck;
                 chg |= (t >= 3 && st_e[r] != ck) ? 1 : 0;
+            } else {
+                if (a.mrhap && a.phi_down) a.phi_down[i] = m1;
             }
-        } else {
-            if (a.mrhap && tid == 0 && a.phi_down) a.phi_down[i] = m1;
         }
         // phase 2: rho^t from the held row, column partials in LDS
         asm volatile("" : "+v"(dcol));
-        const int k1r = k1 - base;
+        const int k1r = k1 - coff - base;
         const T tau_i = st_tau[r];
         const bool has_tau = st_has[r] != 0;
-        if (a.tau_store && tid == 0) a.tau_store[i] = has_tau ? tau_i : pos_inf<T>();
+        if (a.tau_store && owner && tid == 0) a.tau_store[i] = has_tau ? tau_i : pos_inf<T>();
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             const int j0 = c * NT * VW + base;
@@ -611,15 +707,61 @@ __global__ __launch_bounds__(NT) void sweep_held_kernel(SweepArgs<float> a) {
     for (int c = 0; c < NCH; ++c) qs[c][threadIdx.x] = (V)(0.f);
     const int row0 = blockIdx.x * a.rb;
     const int row1 = min(a.rows, row0 + a.rb);
+    const HeldPair none{};
     if (t == 1)
-        held_rows<NT, NCH, true, TAIL>(a, t, row0, row1, qs, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
+        held_rows<NT, NCH, true, TAIL, false>(a, t, row0, row1, 0, a.n, qs, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck, none);
     else
-        held_rows<NT, NCH, false, TAIL>(a, t, row0, row1, qs, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
+        held_rows<NT, NCH, false, TAIL, false>(a, t, row0, row1, 0, a.n, qs, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck, none);
     float *qrow = a.Qpart + (int64_t)blockIdx.x * a.ldw;
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         const int j0 = c * NT * VW + threadIdx.x * VW;
         if (!TAIL || j0 < a.n) *(V *)(qrow + j0) = qs[c][threadIdx.x];
+    }
+}
+
+// The paired pass: workgroups b and b + 8 of every 16 form a pair (on the same XCD when the
+// workgroups are dealt round-robin to the eight XCDs); the pair's rows are the block of its
+// index, side 0 holds columns [0, H) and side 1 columns [H, n).  Every workgroup of the launch
+// must be resident at once (the host sizes the grid to the device's capacity).
+template <int NT, int NCH, bool TAIL>
+__global__ __launch_bounds__(NT) void sweep_pair_kernel(SweepArgs<float> a, PairArgs p) {
+#pragma clang fp contract(off)
+    using V = Vec<float>::type;
+    constexpr int VW = 4;
+    constexpr int NW = NT / 64;
+    constexpr int H = NT * NCH * VW;
+    __shared__ float sh_m1[2][NW], sh_m2[2][NW], sh_cv[2][NW];
+    __shared__ int sh_k1[2][NW], sh_ck[2][NW];
+    __shared__ V qs[NCH][NT];
+    const DevState *ds = a.ds;
+    if (ds->done) return;
+    const int t = ds->t + 1;
+    const int b = blockIdx.x;
+    const int side = (b >> 3) & 1, pair = (b >> 4) * 8 + (b & 7);
+    const int coff = side * H;
+    const int ncols = min(H, a.n - coff);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) qs[c][threadIdx.x] = (V)(0.f);
+    const int row0 = pair * a.rb;
+    const int row1 = min(a.rows, row0 + a.rb);
+    HeldPair hp;
+    hp.mine = p.slots + ((size_t)pair * 2 + side) * 10;
+    hp.theirs = p.slots + ((size_t)pair * 2 + (side ^ 1)) * 10;
+    hp.abort = &a.ds->pair_abort;
+    hp.limit = p.wait_ticks;
+    hp.side = side;
+    hp.level = p.level;
+    if (t == 1)
+        held_rows<NT, NCH, true, TAIL, true>(a, t, row0, row1, coff, ncols, qs, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck, hp);
+    else
+        held_rows<NT, NCH, false, TAIL, true>(a, t, row0, row1, coff, ncols, qs, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck, hp);
+    if (row0 >= a.rows) return;
+    float *qrow = a.Qpart + (int64_t)pair * a.ldw + coff;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const int j0 = c * NT * VW + threadIdx.x * VW;
+        if (!TAIL || j0 < ncols) *(V *)(qrow + j0) = qs[c][threadIdx.x];
     }
 }
 
@@ -867,6 +1009,27 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs<T> a) {
 // Host launchers
 // ---------------------------------------------------------------------------
 
+int64_t pair_grid(int64_t rows, int64_t rb) {
+    const int64_t pairs = (rows + rb - 1) / rb;
+    return (pairs + 7) / 8 * 16;   // pairs in groups of eight: workgroups b and b + 8 of each 16
+}
+
+int pair_capacity(int threads) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    hipError_t e = hipErrorInvalidValue;
+    if (threads == 512)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sweep_pair_kernel<512, 16, true>, 512, 0);
+    else if (threads == 64)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sweep_pair_kernel<64, 16, true>, 64, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return per_cu * cus;
+}
+
 bool launch_supported(int threads, int chunks, int elem_size) {
     (void)elem_size;
     switch (chunks) {
@@ -952,6 +1115,30 @@ hipError_t launch_sweep_level(const T *S, int64_t lds, const LevelPtrs<T> &lv, T
     a.delta = ex.delta;
     const int nb = (a.rows + lc.rows_per_block - 1) / lc.rows_per_block;
     const bool tail = (int64_t)lc.threads * lc.chunks * Vec<T>::N != n;
+    if (lc.streaming && lc.chunks == 32) {
+        // the paired pass: FP32, two workgroups of 512 (or, for tests, 64) threads x 16 chunks
+        if constexpr (sizeof(T) == 4) {
+            if ((lc.threads != 512 && lc.threads != 64) || ex.pair_slots == nullptr) return hipErrorInvalidValue;
+            const int h = lc.threads * 16 * 4;
+            if (n <= h || n > 2 * h) return hipErrorInvalidValue;
+            const int64_t grid = pair_grid(a.rows, lc.rows_per_block);
+            if (grid > pair_capacity(lc.threads)) return hipErrorInvalidValue;
+            PairArgs pa{ex.pair_slots, ex.pair_wait, ex.pair_level};
+            if (lc.threads == 512) {
+                if (tail)
+                    hipLaunchKernelGGL((sweep_pair_kernel<512, 16, true>), dim3(grid), dim3(512), 0, st, a, pa);
+                else
+                    hipLaunchKernelGGL((sweep_pair_kernel<512, 16, false>), dim3(grid), dim3(512), 0, st, a, pa);
+            } else {
+                if (tail)
+                    hipLaunchKernelGGL((sweep_pair_kernel<64, 16, true>), dim3(grid), dim3(64), 0, st, a, pa);
+                else
+                    hipLaunchKernelGGL((sweep_pair_kernel<64, 16, false>), dim3(grid), dim3(64), 0, st, a, pa);
+            }
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     if (lc.streaming && lc.threads == 512) {
         // the held-row pass: FP32, 512 threads x 16 chunks (n <= 32768)
         if constexpr (sizeof(T) == 4) {

@@ -383,6 +383,69 @@ def test_held_matches_streaming_exact_fit(hap_gpu):
     h1.close()
 
 
+def _vectors(hap_gpu, h, l):
+    """c, phi, tau of level l without copying the n x n messages."""
+    import ctypes
+    n = h.n
+    c, phi, tau = (torch.empty(n, dtype=torch.float32, device=DEV) for _ in range(3))
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    assert h._lib.hap_read_messages(h._ctx, l, None, None, n, P(c), P(phi), P(tau)) == hap_gpu.HAP_OK
+    return c, phi, tau
+
+
+@pytest.mark.parametrize("n,rb,schedule,kappa", [(5001, 20, 0, 0.0), (8192, 32, 0, 0.0), (6001, 24, 1, 0.0),
+                                                 (7000, 28, 0, 0.5)])
+def test_paired_pass_matches_streaming(hap_gpu, n, rb, schedule, kappa):
+    """The paired pass (two workgroups per block of rows, each holding half of every row, the
+    row maxima exchanged once per row), here with 64-thread workgroups so that a row of a few
+    thousand points already spans two of them, against the streaming pass with the same rows
+    per block (the same column-sum order): bit-identical messages, labels and vectors over 20
+    sweeps, for the plain and the MapReduce schedule and with the Eq. 2.7 offsets; the last
+    block of 5001 and 6001 rows holds a single row, so its exchange slots carry the previous
+    level's values with the same sweep and row when the next level starts."""
+    b, _ = synth.workload_plain_f32(n=n)
+    S32 = oracle_S(b.X, np.float32)
+    St = to_device(S32)
+    out = []
+    for shape in [(64, 32, rb, True), (1024, -(-n // 4096), rb, True)]:
+        h = hap_gpu.Hap(St, 3, 0.9, schedule=schedule, kappa=kappa)
+        h.set_launch(*shape[:3], streaming=shape[3])
+        assert h.get_launch() == shape
+        h.iterate(20)
+        out.append([h.messages(l) for l in range(3)] + [h.labels()])
+        h.close()
+    for l in range(3):
+        for k in ("rho", "alpha", "c", "phi", "tau"):
+            assert torch.equal(out[0][l][k], out[1][l][k]), (l, k)
+    assert torch.equal(out[0][3], out[1][3])
+
+
+def test_paired_pass_at_full_size_matches_streaming(hap_gpu):
+    """65536 points (the default launch: 512-thread pairs, 128 blocks of 512 rows) against the
+    streaming pass with the same rows per block: labels and c, phi, tau of both levels
+    bit-identical after three sweeps."""
+    n = 65536
+    b, _ = synth.workload_plain_f32(n=n)
+    X = torch.from_numpy(b.X.astype(np.float32)).to(DEV)
+    S = torch.empty((n, n), dtype=torch.float32, device=DEV)
+    hap_gpu.build_similarity(X, S)
+    got = []
+    for shape in [None, (1024, 16, 512, True)]:
+        h = hap_gpu.Hap(S, 2, 0.9, pref=-10.0)
+        if shape is None:
+            assert h.get_launch() == (512, 32, 512, True)
+        else:
+            h.set_launch(*shape[:3], streaming=shape[3])
+        h.iterate(3)
+        got.append([h.labels()] + [_vectors(hap_gpu, h, l) for l in range(2)])
+        h.close()
+        torch.cuda.empty_cache()
+    assert torch.equal(got[0][0], got[1][0])
+    for l in range(2):
+        for a, b_ in zip(got[0][1 + l], got[1][1 + l]):
+            assert torch.equal(a, b_), l
+
+
 def test_streaming_row_pass_f64(hap_gpu):
     b = synth.small_blobs(77, 700, k=5)
     S = oracle_S(b.X, np.float64, 1e-12, 77)
@@ -406,6 +469,16 @@ def test_default_launch_for_long_rows_streams(hap_gpu):
     threads, chunks, rb, streaming = h.get_launch()
     assert streaming and threads == 1024 and chunks == 3
     h.close()
+    # FP32 rows of 32768 < n <= 65536 columns take the paired pass (128 pairs)
+    n = 40000
+    S = torch.zeros((n, n), dtype=torch.float32, device=DEV)
+    h = hap_gpu.Hap(S, 1, 0.5, pref=-1.0)
+    assert h.get_launch() == (512, 32, (n + 127) // 128, True)
+    # a grid larger than the device holds at once is refused
+    with pytest.raises(hap_gpu.HapError):
+        h.set_launch(512, 32, 16, streaming=True)
+    h.close()
+    del S
     # FP32 rows of 16384 < n <= 32768 columns take the held-row pass, FP64 rows stream
     n = 20000
     S = torch.zeros((n, n), dtype=torch.float32, device=DEV)
