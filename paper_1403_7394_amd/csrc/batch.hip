@@ -215,12 +215,17 @@ __device__ __forceinline__ void sweep_rows_grouped(const SweepArgs<float> &a, co
         float m1 = ninf, m2 = ninf, cv = ninf;
         int k1 = INT_MAX, ck = INT_MAX;
         int dcol = i - base;
-        float p_i = 0.f;
+        float p_i = 0.f, tau_i = 0.f;
+        int e_old = 0;
         if (active) {
             const float *Srow = a.S + (int64_t)i * a.lds;
             const float *Rrow = a.R + (int64_t)i * ldw;
             float *Arow = a.A + (int64_t)i * ldw;
+            // the row's scalars are loaded before its rows, so that waiting for them (memory
+            // operations complete in issue order) never waits for the row loads or for stores
             p_i = a.pref[i];
+            if (has_tau) tau_i = a.tau[i];
+            if (!FIRST && ltid == 0) e_old = a.E[i];
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
                 const int j0 = c * NTG * VW + base;
@@ -279,7 +284,12 @@ __device__ __forceinline__ void sweep_rows_grouped(const SweepArgs<float> &a, co
                 }
             }
         }
-        __syncthreads();
+        // LDS exchange of the wave results and the contributions: wait for LDS traffic only,
+        // so that this step's stores stay in flight across the barrier
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
         // group 0: the previous step's rows of groups 1..G-1, in row order, before its own row
         if (grp == 0 && k > 0) {
             const int pb = buf ^ 1;
@@ -305,15 +315,13 @@ __device__ __forceinline__ void sweep_rows_grouped(const SweepArgs<float> &a, co
                     for (int w = 1; w < NWG; ++w) argmax_merge(cv, ck, sh_cv[buf][grp][w], sh_ck[buf][grp][w]);
                     a.C[i] = cv;
                     if (a.phi_down) a.phi_down[i] = m1;
-                    const int old = a.E[i];
                     a.E[i] = ck;
-                    chg |= (t >= 3 && old != ck) ? 1 : 0;
+                    chg |= (t >= 3 && e_old != ck) ? 1 : 0;
                 }
             }
             // phase 2: rho^t and this row's column-sum contribution
             asm volatile("" : "+v"(dcol));
             const int k1r = k1 - base;
-            const float tau_i = has_tau ? a.tau[i] : zero;
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
                 const int j0 = c * NTG * VW + base;
