@@ -578,7 +578,8 @@ def run_profile_form(args, torch, hap, synth) -> int:
 def run_ceiling_form(args, torch, hap) -> dict:
     """What the row pass's read/write mixes reach on this GPU: the library's bandwidth probe
     (same access pattern as the row pass: 512-thread workgroups over blocks of 32 rows, 16-byte
-    accesses, non-temporal S and stores) over 8192 x 8192 FP32 arrays, for a pure read, a copy,
+    accesses, non-temporal S and stores) over 8192 x 8192 FP32 arrays, for a pure write (what
+    the similarity builds do), a pure read, a copy,
     the points-mode mix (read and write rho and alpha) and the S-reading mix (read S, rho,
     alpha; write rho, alpha).  HIP events on the probe's stream, --steps repetitions each after
     two untimed ones."""
@@ -588,7 +589,8 @@ def run_ceiling_form(args, torch, hap) -> dict:
     sink = torch.zeros(1, dtype=torch.float32, device=dev)
     reps = max(5, args.steps)
     out = {"form": "ceiling", "arrays": f"{n} x {n} FP32", "peak_GBs": HBM_PEAK_GBS, "mixes": {}}
-    for name, r, w in (("read", 1, 0), ("copy", 1, 1), ("points_mix_2r2w", 2, 2), ("s_mix_3r2w", 3, 2)):
+    for name, r, w in (("write", 0, 1), ("read", 1, 0), ("copy", 1, 1), ("points_mix_2r2w", 2, 2),
+                       ("s_mix_3r2w", 3, 2)):
         ins, outs = arrs[:r], arrs[r:r + w]
         for _ in range(2):
             hap.bandwidth_probe(ins, outs, sink=sink)

@@ -168,8 +168,10 @@ HAP_API hap_status hap_median_offdiag_noalloc(const void *S, int64_t n, int64_t 
  * aligned; cols and ld multiples of 4, cols <= 8192), with the access pattern of the sweep's
  * row pass (workgroups of 512 threads own rows_per_block consecutive rows, 16 bytes per thread access,
  * the first input and every output non-temporal); each output element is the sum of the inputs.
- * (reads, writes): (1, 0) pure read (out[0] must still point at one writable element, stored to
- * only if the data hold a marker pair, so the loads cannot be dropped), (1, 1) copy, (2, 2) the
+ * (reads, writes): (0, 1) pure write (in may be NULL; every element of a row gets the row's
+ * index, the pattern of the similarity build's stores of S), (1, 0) pure read (out[0] must
+ * still point at one writable element, stored to only if the data hold a marker pair, so the
+ * loads cannot be dropped), (1, 1) copy, (2, 2) the
  * points-mode row pass's mix (read and write rho and alpha), (3, 2) the row pass reading S.
  * Measures what such a mix reaches on the device; not part of the method.  HAP_E_ARG for other
  * mixes or bad sizes, HAP_E_UNSUPPORTED above 8192 columns.  Stream-ordered, no synchronisation.

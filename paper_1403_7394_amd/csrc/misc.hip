@@ -131,9 +131,13 @@ __global__ __launch_bounds__(512) void probe_kernel(ProbeArgs a) {
             const int64_t j = (int64_t)c * 2048 + threadIdx.x * 4;
             if (j < a.cols) {
                 const int64_t o = i * a.ld + j;
-                acc[c] = __builtin_nontemporal_load((const V *)(a.in[0] + o));
+                if constexpr (R == 0) {
+                    acc[c] = (V)((float)i);   // write only: the row index
+                } else {
+                    acc[c] = __builtin_nontemporal_load((const V *)(a.in[0] + o));
 #pragma unroll
-                for (int r = 1; r < R; ++r) acc[c] += *(const V *)(a.in[r] + o);
+                    for (int r = 1; r < R; ++r) acc[c] += *(const V *)(a.in[r] + o);
+                }
             }
         }
 #pragma unroll
@@ -161,6 +165,7 @@ hipError_t launch_probe(int reads, int writes, const ProbeArgs &a, hipStream_t s
         hipLaunchKernelGGL((probe_kernel<RR, WW>), dim3(grid), dim3(512), 0, st, a);      \
         return hipGetLastError();                                                         \
     }
+    HAP_PROBE(0, 1)
     HAP_PROBE(1, 0)
     HAP_PROBE(1, 1)
     HAP_PROBE(2, 2)

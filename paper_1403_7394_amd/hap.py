@@ -196,18 +196,19 @@ def median_offdiag_noalloc(S, out, stream=None) -> None:
 
 def bandwidth_probe(inputs, outputs, sink=None, rows_per_block: int = 32, stream=None) -> None:
     """hap_bandwidth_probe: reads the 2-D FP32 device tensors `inputs` and writes `outputs`, all
-    of one shape and row stride.  With no outputs (the pure-read mix) `sink` is a one-element
-    FP32 device tensor the kernel may store to."""
+    of one shape and row stride (no inputs: the pure-write mix).  With no outputs (the pure-read
+    mix) `sink` is a one-element FP32 device tensor the kernel may store to."""
     import torch
     lib = load()
-    rows, cols = inputs[0].shape
-    ld = _ld(inputs[0])
+    first = inputs[0] if inputs else outputs[0]
+    rows, cols = first.shape
+    ld = _ld(first)
     for t in list(inputs) + list(outputs):
         if t.dtype != torch.float32 or tuple(t.shape) != (rows, cols) or _ld(t) != ld or not t.is_cuda:
             raise ValueError("bandwidth_probe: every array must be an FP32 device tensor of the same shape and stride")
     if not outputs and (sink is None or sink.dtype != torch.float32 or sink.numel() < 1 or not sink.is_cuda):
         raise ValueError("bandwidth_probe: the pure-read mix needs a one-element FP32 device sink")
-    ins = (ctypes.c_void_p * 3)(*[ctypes.c_void_p(t.data_ptr()) for t in inputs])
+    ins = (ctypes.c_void_p * 3)(*[ctypes.c_void_p(t.data_ptr()) for t in inputs]) if inputs else None
     targets = list(outputs) if outputs else [sink]
     outs = (ctypes.c_void_p * 2)(*[ctypes.c_void_p(t.data_ptr()) for t in targets])
     _check("hap_bandwidth_probe", lib.hap_bandwidth_probe(len(inputs), len(outputs), ins, outs, rows, cols,

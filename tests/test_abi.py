@@ -177,6 +177,8 @@ def test_bandwidth_probe_checks_arguments(lib):
     assert lib.hap_bandwidth_probe(1, 1, fake, outs, 64, 64, 60, 32, None) == hap.HAP_E_ARG     # ld < cols
     assert lib.hap_bandwidth_probe(1, 1, fake, outs, 64, 8196, 8196, 32, None) == hap.HAP_E_UNSUPPORTED
     assert lib.hap_bandwidth_probe(1, 0, fake, None, 64, 64, 64, 32, None) == hap.HAP_E_ARG     # no sink
+    assert lib.hap_bandwidth_probe(0, 1, None, None, 64, 64, 64, 32, None) == hap.HAP_E_ARG     # no output
+    assert lib.hap_bandwidth_probe(0, 2, None, outs, 64, 64, 64, 32, None) == hap.HAP_E_ARG     # mix
     import torch
     a = torch.zeros((8, 8))
     with pytest.raises(ValueError):
