@@ -270,8 +270,9 @@ HAP_API hap_status hap_similarity_offsets(hap_ctx *ctx, int32_t level, void *del
  * every workgroup of the launch (2 per block, rounded up to 16) must be resident on the
  * device at once, so a shape whose grid exceeds the device's capacity returns HAP_E_ARG,
  * and if another kernel holds part of the device so that a partner never arrives, the
- * waits give up after two seconds and hap_iterate returns HAP_E_HIP with the context
- * failed; without the flag the register-resident row pass; HAP_LAUNCH_EAGER issues every
+ * waits give up after two seconds (or HAP_PAIR_WAIT_US microseconds, read from the
+ * environment when the pass is first set up) and hap_iterate returns HAP_E_HIP with the
+ * context failed; without the flag the register-resident row pass; HAP_LAUNCH_EAGER issues every
  * launch from the host instead of replaying captured graphs of sweep chunks (the
  * default captures each chunk of up to 16 sweeps once on a private stream and
  * replays it on the context's stream); HAP_LAUNCH_UNFUSED keeps one row-pass launch per

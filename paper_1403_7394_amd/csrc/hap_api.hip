@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <new>
 #include <algorithm>
 #include <string>
@@ -526,6 +527,12 @@ hap_status ensure_pair_slots(hap_ctx *c, const Launch &lc) {
     int khz = 0;
     HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device), c);
     c->pair_wait = (uint64_t)khz * 2000;   // two seconds
+    // HAP_PAIR_WAIT_US shortens the bound (tests force the give-up path with it)
+    if (const char *env = std::getenv("HAP_PAIR_WAIT_US")) {
+        char *end = nullptr;
+        const unsigned long long us = std::strtoull(env, &end, 10);
+        if (end != env) c->pair_wait = (uint64_t)khz * us / 1000;
+    }
     return HAP_OK;
 }
 

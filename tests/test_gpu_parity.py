@@ -651,3 +651,27 @@ def test_maximum_size_on_sampled_rows(hap_gpu, dtype, n):
     h.close()
     del S
     torch.cuda.empty_cache()
+
+
+def test_paired_pass_gives_up_and_fails_the_run(hap_gpu, monkeypatch):
+    """The paired pass's bounded wait, forced from the host: with a zero wait bound
+    (HAP_PAIR_WAIT_US=0) a workgroup whose partner has not yet published gives up, every
+    other wait ends at once, the launch drains, and hap_iterate reports the failure and fails
+    the context instead of returning results."""
+    monkeypatch.setenv("HAP_PAIR_WAIT_US", "0")
+    n = 5001
+    b, _ = synth.workload_plain_f32(n=n)
+    h = hap_gpu.Hap(to_device(oracle_S(b.X, np.float32)), 3, 0.9)
+    h.set_launch(64, 32, 20, streaming=True)
+    with pytest.raises(hap_gpu.HapError) as err:
+        h.iterate(20)
+    assert "partner" in str(err.value)
+    with pytest.raises(hap_gpu.HapError):
+        h.iterate(1)                      # the context stays failed
+    h.close()
+    # a new context with the normal bound runs
+    monkeypatch.delenv("HAP_PAIR_WAIT_US")
+    h = hap_gpu.Hap(to_device(oracle_S(b.X, np.float32)), 3, 0.9)
+    h.set_launch(64, 32, 20, streaming=True)
+    h.iterate(5)
+    h.close()
