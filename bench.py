@@ -18,6 +18,10 @@ algorithmic traffic (read R, A and write R, A: 4 N^2 words per level per sweep,
 3 N^2 in the first sweep, which has no alpha to finish; 5 N^2 and 4 N^2 when S is
 read) divided by its average launch duration, measured with HIP events recorded
 on its own stream around the launches of every 8th sweep of the timed steps.
+The L = 3 run does not meet the stop rule under the literal Eq. 2.6, so the line
+also times, once each, the same workload at L = 1 and with the optional Eq. 2.7
+update (kappa = 0.5), which do, from the points on the GPU to the labels
+(`converging_variants`).
 """
 from __future__ import annotations
 
@@ -660,6 +664,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--no-converge-variants", action="store_true",
+                    help="skip the L = 1 and kappa = 0.5 runs timed to the stop rule")
     ap.add_argument("--cpu-sweeps", type=int, default=5, help="sweeps of the oracle timed for cpu_baseline (about 13 s)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration under rocprofv3)")
@@ -887,6 +893,28 @@ def main() -> int:
         out["read_s"] = {"steps": args.read_s_steps, "ms_per_step": rs["elapsed"] / args.read_s_steps * 1e3,
                          "value": n * n * L * rs["sweeps"] / rs["elapsed"],
                          "labels_equal_points_mode": bool(torch.equal(rs["last"][4], labels))}
+    if args.schedule == "sequential" and args.kappa == 0.0 and not args.no_converge_variants:
+        # Under the literal Eq. 2.6 the L = 3 run never meets the stop rule, so its time to
+        # converge does not exist; the same workload does converge at L = 1 (plain affinity
+        # propagation) and with the optional Eq. 2.7 update (kappa = 0.5).  Each is timed once
+        # from X on the device to labels (build, median, sweeps to the stop rule, labels).
+        variants = {}
+        for name, lv, kap in (("L1", 1, 0.0), ("kappa0.5", L, 0.5)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hap.build_similarity(X, S)
+            h = hap.Hap(S, lv, rp.damping, workspace=ws, kappa=kap)
+            if kap == 0.0:
+                h.set_points(X)
+            r = h.iterate(rp.max_iters, rp.stable_iters)
+            h.labels()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            variants[name] = {"levels": lv, "kappa": kap, "iters": r.iters, "converged": bool(r.converged),
+                              "time_to_converge_ms": ms if r.converged else None,
+                              "exemplars_per_level": [h.exemplars(l)[1] for l in range(lv)]}
+            h.close()
+        out["converging_variants"] = variants
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(blobs.X, rp, args.cpu_sweeps)
     print(json.dumps(out), flush=True)
