@@ -769,9 +769,10 @@ def main() -> int:
         counts = [h.exemplars(l)[1] for l in range(L)]
         ns = h.net_similarity(-1)
         launch = h.get_launch()
+        fused = bool(h.launch_flags() & hap.LAUNCH_FUSED)
         labels = h.labels()
         h.close()
-        return res, counts, ns, prof, launch, labels
+        return res, counts, ns, prof, launch + (fused,), labels
 
     def timed(steps: int, use_points: bool):
         torch.cuda.synchronize()
@@ -795,16 +796,22 @@ def main() -> int:
         w = 4
         # algorithmic bytes of all row-pass launches: read S, R, A and write R, A = 5 N^2 w, or
         # 4 N^2 w in the first sweep (no alpha to finish); one word less per element in points
-        # mode, where S is not read
-        first_w, steady_w = (3, 4) if use_points else (4, 5)
-        first_launches = acc["first"] * L
+        # mode, where S is not read.  The MapReduce schedule's fused pass runs every level in one
+        # launch and reads S once: 1 + 4L words (1 + 3L in the first sweep) per launch.
+        fused = acc["last"][3][4]
+        lps = 1 if fused else L
+        if fused:
+            first_w, steady_w = 1 + 3 * L, 1 + 4 * L
+        else:
+            first_w, steady_w = (3, 4) if use_points else (4, 5)
+        first_launches = acc["first"] * lps
         alg_total = (first_launches * first_w + (acc["row_n"] - first_launches) * steady_w) * n * n * w
         per_launch = alg_total / max(acc["row_n"], 1)
         avg_s = acc["row_ms"] / max(acc["row_n"], 1) * 1e-3
         achieved = per_launch / avg_s / 1e9
         # the counters were taken on the plain row pass; the Eq. 2.7 instance is another kernel
         traffic = (measured_traffic(use_points, first_launches, acc["row_n"] - first_launches)
-                   if args.kappa == 0.0 else None)
+                   if args.kappa == 0.0 and not fused else None)
         return {
             "bound": "hbm",
             "achieved": achieved,
@@ -814,12 +821,13 @@ def main() -> int:
             "traffic": traffic,
             "kernel": ("row pass (sweep_kernel, points mode)" if use_points else
                        "row pass (sweep_kernel, S read, Eq. 2.7 row offsets)" if args.kappa else
+                       f"fused row pass of all {L} levels (sweep_fused_kernel, S read once)" if fused else
                        "row pass (sweep_kernel, S read)"),
             "words_per_element": {"first_sweep": first_w, "later_sweeps": steady_w},
             "avg_launch_us": avg_s * 1e6,
             "alg_bytes_per_launch": per_launch,
             "launches_timed": acc["row_n"],
-            "launches": int(acc["sweeps"] * L),
+            "launches": int(acc["sweeps"] * lps),
             "timed_every": PROF_EVERY,
         }
 
@@ -869,7 +877,7 @@ def main() -> int:
         "net_similarity": ns,
         "purity_per_level": [metrics.purity(x, blobs.truth) for x in lab],
         "launch": {"threads": launch[0], "chunks": launch[1], "rows_per_block": launch[2],
-                   "streaming": launch[3]},
+                   "streaming": launch[3], "fused_levels": launch[4]},
     }
     # how the step's labels compare with the stored oracle runs of the same workload (written by
     # tests/golden/full_run_plain8192.py from the oracle alone); the row-ordered launch

@@ -284,9 +284,11 @@ HAP_API hap_status hap_similarity_offsets(hap_ctx *ctx, int32_t level, void *del
  * (and changes nothing)
  * for a shape that does not fit.  For the autotuner and for comparisons.
  */
-enum { HAP_LAUNCH_STREAM = 2, HAP_LAUNCH_EAGER = 4, HAP_LAUNCH_UNFUSED = 8 };
+enum { HAP_LAUNCH_STREAM = 2, HAP_LAUNCH_EAGER = 4, HAP_LAUNCH_UNFUSED = 8, HAP_LAUNCH_FUSED = 16 };
 HAP_API hap_status hap_set_launch(hap_ctx *ctx, int32_t threads, int32_t chunks, int32_t rows_per_block,
                                   int32_t flags);
+/* The current shape and flags; flags also carries HAP_LAUNCH_FUSED (reported only, ignored by
+ * hap_set_launch) when the sweeps will run the fused all-level pass. */
 HAP_API hap_status hap_get_launch(hap_ctx *ctx, int32_t *threads, int32_t *chunks, int32_t *rows_per_block,
                                   int32_t *flags);
 

@@ -1143,7 +1143,7 @@ hap_status hap_get_launch(hap_ctx *c, int32_t *threads, int32_t *chunks, int32_t
     if (!c) return fail_arg("hap_get_launch: null context");
     if (flags)
         *flags = (c->lc.streaming ? HAP_LAUNCH_STREAM : 0) | (c->use_graphs ? 0 : HAP_LAUNCH_EAGER) |
-                 (c->no_fuse ? HAP_LAUNCH_UNFUSED : 0);
+                 (c->no_fuse ? HAP_LAUNCH_UNFUSED : 0) | (use_fused(c, c->lc) ? HAP_LAUNCH_FUSED : 0);
     if (threads) *threads = c->lc.threads;
     if (chunks) *chunks = c->lc.chunks;
     if (rows_per_block) *rows_per_block = c->lc.rows_per_block;

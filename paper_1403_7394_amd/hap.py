@@ -21,6 +21,7 @@ PREF_MEDIAN, PREF_SCALAR, PREF_VECTOR = 0, 1, 2
 LAUNCH_STREAM = 2
 LAUNCH_EAGER = 4
 LAUNCH_UNFUSED = 8
+LAUNCH_FUSED = 16   # reported by hap_get_launch: the MapReduce levels run in one fused pass
 SCHEDULE_SEQUENTIAL, SCHEDULE_MRHAP = 0, 1
 
 # every symbol include/hap.h declares

@@ -122,6 +122,7 @@ def test_fused_matches_per_level_launches(hap_gpu, n, L):
         h = hap_gpu.Hap(S, L, 0.9, schedule=hap_gpu.SCHEDULE_MRHAP)
         h.set_launch(unfused=unfused)
         assert bool(h.launch_flags() & hap_gpu.LAUNCH_UNFUSED) == unfused
+        assert bool(h.launch_flags() & hap_gpu.LAUNCH_FUSED) == (not unfused)
         res = h.iterate(40, 5)
         outs.append((res, h.labels(), [h.messages(l) for l in range(L)]))
         h.close()
