@@ -568,6 +568,8 @@ def run_profile_form(args, torch, hap, synth) -> int:
     if args.sweep_launch:
         t_, c_, rb_, st_ = (int(v) for v in args.sweep_launch.split(","))
         h.set_launch(t_, c_, rb_, streaming=bool(st_))
+    if args.blocks:
+        h.set_launch(blocks=True)
     if not args.read_s:
         h.set_points(X)
     torch.cuda.synchronize()
@@ -684,6 +686,8 @@ def main() -> int:
                     help="--form sweeps with --schedule mrhap: one row-pass launch per level")
     ap.add_argument("--sweep-launch", default="",
                     help="--form sweeps: row-pass shape threads,chunks,rows_per_block,streaming (empty: the default)")
+    ap.add_argument("--blocks", action="store_true",
+                    help="--form sweeps: each workgroup takes a contiguous block of rows (default: interleaved)")
     ap.add_argument("--copy-gib", type=float, default=1.0,
                     help="--form sweeps / batch-once: GiB of the calibration copy run first (0: none)")
     ap.add_argument("--batch-launch", default="1024,512,4",

@@ -280,11 +280,17 @@ HAP_API hap_status hap_similarity_offsets(hap_ctx *ctx, int32_t level, void *del
  * register-resident shape of 4 chunks per thread and 2 to 4 levels run every level of a row
  * in one launch, which reads the row of S once per sweep instead of once per level, Section
  * 3; with more workgroups than the workspace's partial rows or more than two levels its
- * column partials are library-owned, allocated on first use as above).  Returns HAP_E_ARG
+ * column partials are library-owned, allocated on first use as above); HAP_LAUNCH_BLOCKS
+ * gives workgroup g the contiguous rows [g r, (g + 1) r) (r = rows_per_block) where by
+ * default, with G = ceil(rows / r) workgroups (pairs, for the paired pass), it takes rows g,
+ * g + G, g + 2G, ..., so that the rows being read at any moment lie next to each other in
+ * memory (the rows feeding each column partial differ; with r = 1 the two are the same).
+ * Returns HAP_E_ARG
  * (and changes nothing)
  * for a shape that does not fit.  For the autotuner and for comparisons.
  */
-enum { HAP_LAUNCH_STREAM = 2, HAP_LAUNCH_EAGER = 4, HAP_LAUNCH_UNFUSED = 8, HAP_LAUNCH_FUSED = 16 };
+enum { HAP_LAUNCH_STREAM = 2, HAP_LAUNCH_EAGER = 4, HAP_LAUNCH_UNFUSED = 8, HAP_LAUNCH_FUSED = 16,
+       HAP_LAUNCH_BLOCKS = 32 };
 HAP_API hap_status hap_set_launch(hap_ctx *ctx, int32_t threads, int32_t chunks, int32_t rows_per_block,
                                   int32_t flags);
 /* The current shape and flags; flags also carries HAP_LAUNCH_FUSED (reported only, ignored by

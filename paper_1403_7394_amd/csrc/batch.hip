@@ -463,6 +463,7 @@ __global__ __launch_bounds__(NT) void batch_kernel(BatchArgs g) {
                     a.tau_store = nullptr;
                     a.mrhap = 0;
                     a.delta = nullptr;
+                    a.row_stride = 0;
                     a.n = n;
                     a.rb = n;
                     a.rows = n;

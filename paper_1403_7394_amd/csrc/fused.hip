@@ -76,16 +76,19 @@ __device__ __forceinline__ void fused_rows(const FusedArgs<float> &a, const int 
         }
     };
     int buf = 0, chg = 0;
+    auto rowof = [&](int k) { return slot_row(k, row0, a.rb, a.row_stride); };
     if (row0 < row1) {
-        load_s(row0, sy);
-        load_ra(row0, 0);
+        load_s(rowof(row0), sy);
+        load_ra(rowof(row0), 0);
     }
-    for (int i = row0; i < row1; ++i) {
-        const int r = (i - row0) % kWin;
+    for (int ii = row0; ii < row1; ++ii) {
+        const int i = rowof(ii);
+        const int r = (ii - row0) % kWin;
         if (r == 0) {
             __syncthreads();
-            const int k = i + tid;
-            if (tid < kWin && k < row1) {
+            const int kk = ii + tid;
+            const int k = rowof(kk);
+            if (tid < kWin && kk < row1) {
                 for (int l = 0; l < L; ++l) {
                     st_p[l][tid] = a.pref[l][k];
                     st_e[l][tid] = a.E[l][k];
@@ -107,9 +110,10 @@ __device__ __forceinline__ void fused_rows(const FusedArgs<float> &a, const int 
             // the next item: the level above on this row, or level 0 of the next row
             if (l + 1 < L) {
                 load_ra(i, l + 1);
-            } else if (i + 1 < row1) {
-                load_s(i + 1, sy);
-                load_ra(i + 1, 0);
+            } else if (ii + 1 < row1) {
+                const int nx = rowof(ii + 1);
+                load_s(nx, sy);
+                load_ra(nx, 0);
             }
             float *Rrow = a.R[l] + (int64_t)i * ldw;
             float *Arow = a.A[l] + (int64_t)i * ldw;
@@ -235,7 +239,7 @@ __global__ __launch_bounds__(NT) void sweep_fused_kernel(FusedArgs<float> a) {
 #pragma unroll
         for (int c = 0; c < NCH; ++c) qs[l][c][threadIdx.x] = (V)(0.f);
     const int row0 = blockIdx.x * a.rb;
-    const int row1 = min(a.rows, row0 + a.rb);
+    const int row1 = slots_end(a.rows, a.rb, row0, a.row_stride);
     if (t == 1)
         fused_rows<NT, NCH, true, TAIL>(a, t, row0, row1, qs);
     else

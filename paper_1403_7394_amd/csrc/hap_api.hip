@@ -383,6 +383,7 @@ hap_status run_sweeps(hap_ctx *c, int count, int K) {
                 fa.n = (int)c->n;
                 fa.rows = (int)c->rows;
                 fa.rb = c->lc.rows_per_block;
+                fa.row_stride = hap::row_stride_of(c->lc, c->rows);
                 fa.L = L;
                 fa.lam = (float)c->lam;
                 fa.oml = (float)(1.0 - c->lam);
@@ -1050,6 +1051,7 @@ hap_status hap_set_launch(hap_ctx *c, int32_t threads, int32_t chunks, int32_t r
     if (chunks) lc.chunks = chunks;
     if (rows_per_block) lc.rows_per_block = rows_per_block;
     if (flags >= 0) lc.streaming = (flags & HAP_LAUNCH_STREAM) != 0;
+    if (flags >= 0) lc.blocks = (flags & HAP_LAUNCH_BLOCKS) != 0;
     lc.ordered = (lc.rows_per_block == 1);
     if (!launch_fits(lc, c->n, c->rows, c->esz))
         return fail_arg("hap_set_launch: shape does not fit this problem");
@@ -1143,7 +1145,8 @@ hap_status hap_get_launch(hap_ctx *c, int32_t *threads, int32_t *chunks, int32_t
     if (!c) return fail_arg("hap_get_launch: null context");
     if (flags)
         *flags = (c->lc.streaming ? HAP_LAUNCH_STREAM : 0) | (c->use_graphs ? 0 : HAP_LAUNCH_EAGER) |
-                 (c->no_fuse ? HAP_LAUNCH_UNFUSED : 0) | (use_fused(c, c->lc) ? HAP_LAUNCH_FUSED : 0);
+                 (c->no_fuse ? HAP_LAUNCH_UNFUSED : 0) | (use_fused(c, c->lc) ? HAP_LAUNCH_FUSED : 0) |
+                 (c->lc.blocks ? HAP_LAUNCH_BLOCKS : 0);
     if (threads) *threads = c->lc.threads;
     if (chunks) *chunks = c->lc.chunks;
     if (rows_per_block) *rows_per_block = c->lc.rows_per_block;

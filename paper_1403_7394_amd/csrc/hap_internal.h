@@ -47,7 +47,15 @@ struct Launch {
     bool ordered;       // column partials summed strictly in workgroup order
     bool streaming;     // large rows: 1024 threads, phase 2 re-reads S and R (chunks 2..16); or, FP32
                         // with 512 threads x 16 chunks, the held-row pass (phase 2 reads nothing)
+    bool blocks = false; // workgroup g takes rows [g rb, (g + 1) rb) instead of g, g + G, g + 2G, ...
+                         // (G workgroups), the default, under which the rows in flight at any
+                         // moment are neighbours in memory
 };
+// Row stride of the row passes for this launch over `rows` rows (0: contiguous blocks).
+inline int row_stride_of(const Launch &lc, int rows) {
+    if (lc.blocks || lc.rows_per_block <= 1) return 0;
+    return (rows + lc.rows_per_block - 1) / lc.rows_per_block;
+}
 
 // Pointers of one level inside the workspace.
 template <typename T>
@@ -135,6 +143,7 @@ struct FusedArgs {
     const T *S;
     int64_t lds, ldw;
     int n, rows, rb, L;
+    int row_stride;   // row order of a workgroup, as in the per-level row passes
     T lam, oml;
     DevState *ds;
     T *R[kMaxFused];

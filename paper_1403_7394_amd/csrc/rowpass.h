@@ -39,7 +39,23 @@ struct SweepArgs {
     // diagonal (read by the D < 0 instances of the register-resident row pass and by the
     // streaming row pass); nullptr when the update is off
     const T *delta;
+    // Row order of a workgroup: 0 = the block of rows [row0, row0 + rb); s > 0 = rows
+    // first, first + s, first + 2s, ... (first = row0 / rb, s = the number of row groups), so
+    // that the rows the workgroups work on at any moment are neighbours in memory
+    int row_stride;
 };
+
+// Row of slot k of the workgroup whose slots are [row0, row1) (see SweepArgs::row_stride).
+__device__ __forceinline__ int slot_row(int k, int row0, int rb, int stride) {
+    return stride ? row0 / rb + (k - row0) * stride : k;
+}
+// End of the workgroup's slots: rb rows from row0, or fewer at the end of the rows.
+__device__ __forceinline__ int slots_end(int rows, int rb, int row0, int stride) {
+    if (stride == 0) return min(rows, row0 + rb);
+    const int first = row0 / rb;
+    if (first >= stride || first >= rows) return row0;
+    return row0 + min(rb, (rows - first + stride - 1) / stride);
+}
 
 // The upward message this row pass clips with (Eq. 2.1 at l > 1), or false for no clip.
 template <typename T>
@@ -209,13 +225,16 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, c
     int chg = 0;   // a label of this workgroup's rows changed (thread 0; one atomic per workgroup)
     __shared__ T st_p[kWin], st_tau[kWin], st_d[kWin];
     __shared__ int st_e[kWin], st_has[kWin];
-    if (row0 < row1) load_row<T, NT, NCH, TAIL, D>(a, row0, y);
-    for (int i = row0; i < row1; ++i, buf ^= 1) {
-        const int r = (i - row0) % kWin;
+    auto rowof = [&](int k) { return slot_row(k, row0, a.rb, a.row_stride); };
+    if (row0 < row1) load_row<T, NT, NCH, TAIL, D>(a, rowof(row0), y);
+    for (int ii = row0; ii < row1; ++ii, buf ^= 1) {
+        const int i = rowof(ii);
+        const int r = (ii - row0) % kWin;
         if (r == 0) {
             __syncthreads();
-            const int k = i + tid;
-            if (tid < kWin && k < row1) {
+            const int kk = ii + tid;
+            const int k = rowof(kk);
+            if (tid < kWin && kk < row1) {
                 st_p[tid] = a.pref[k];
                 T tv = zero;
                 st_has[tid] = row_tau(a, k, t, tv) ? 1 : 0;
@@ -226,7 +245,7 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs<T> &a, const int t, c
             __syncthreads();
         }
         x = y;
-        if (i + 1 < row1) load_row<T, NT, NCH, TAIL, D>(a, i + 1, y);
+        if (ii + 1 < row1) load_row<T, NT, NCH, TAIL, D>(a, rowof(ii + 1), y);
         T *Rrow = a.R + (int64_t)i * ldw;
         T *Arow = a.A + (int64_t)i * ldw;
         const T p_i = st_p[r];
@@ -394,14 +413,17 @@ __device__ __forceinline__ void sweep_rows_points(const SweepArgs<T> &a, const i
             }
         }
     };
-    if (row0 < row1) fetch(row0);
-    for (int i = row0; i < row1; ++i, buf ^= 1) {
-        const int r = (i - row0) % kWin;
+    auto rowof = [&](int k) { return slot_row(k, row0, a.rb, a.row_stride); };
+    if (row0 < row1) fetch(rowof(row0));
+    for (int ii = row0; ii < row1; ++ii, buf ^= 1) {
+        const int i = rowof(ii);
+        const int r = (ii - row0) % kWin;
         if (r == 0) {
             // stage the scalars of rows [i, i + kWin)
             __syncthreads();
-            const int k = i + tid;
-            if (tid < kWin && k < row1) {
+            const int kk = ii + tid;
+            const int k = rowof(kk);
+            if (tid < kWin && kk < row1) {
                 L.p[tid] = a.pref[k];
                 L.tau[tid] = has_tau ? (mr ? a.tau_c[k] + a.tau_q[k] : a.tau[k]) : zero;
 #pragma unroll
@@ -415,7 +437,7 @@ __device__ __forceinline__ void sweep_rows_points(const SweepArgs<T> &a, const i
             x.r[c] = yr[c];
             x.a[c] = ya[c];
         }
-        if (i + 1 < row1) fetch(i + 1);
+        if (ii + 1 < row1) fetch(rowof(ii + 1));
         // s_ij from the coordinates, with the direct build's arithmetic
         double xi[D];
 #pragma unroll

@@ -68,7 +68,7 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs<T> a) {
             }
     }
     const int row0 = blockIdx.x * a.rb;
-    const int row1 = min(a.rows, row0 + a.rb);
+    const int row1 = slots_end(a.rows, a.rb, row0, a.row_stride);
     if constexpr (D > 0) {
         __shared__ __attribute__((aligned(16))) PointsLds<T, NT, NCH, D> lds;
         if (first)
@@ -155,8 +155,10 @@ __device__ __forceinline__ void stream_rows(const SweepArgs<T> &a, const int t, 
         av = buf_load<V, 0>(rA, voff, c * CB);
         if constexpr (!FIRST) bv = buf_load<V, 0>(rB, voff, c * CB);
     };
-    if (row0 < row1) load1(row_s(row0), row_w(a.R, row0), row_w(a.A, row0), 0);
-    for (int i = row0; i < row1; ++i, buf ^= 1) {
+    auto rowof = [&](int k) { return slot_row(k, row0, a.rb, a.row_stride); };
+    if (row0 < row1) load1(row_s(rowof(row0)), row_w(a.R, rowof(row0)), row_w(a.A, rowof(row0)), 0);
+    for (int ii = row0; ii < row1; ++ii, buf ^= 1) {
+        const int i = rowof(ii);
         const __amdgpu_buffer_rsrc_t rS = row_s(i);
         const __amdgpu_buffer_rsrc_t rR = row_w(a.R, i);
         const __amdgpu_buffer_rsrc_t rA = row_w(a.A, i);
@@ -254,8 +256,9 @@ __device__ __forceinline__ void stream_rows(const SweepArgs<T> &a, const int t, 
                 s2 = buf_load<V, 0>(rS, voff, (c + 1) * CB);
                 r2 = buf_load<V, 0>(rR, voff, (c + 1) * CB);
                 if (c + 1 >= kLdsChunks) qn = buf_load<V, 0>(rQ, voff, (c + 1) * CB);
-            } else if (i + 1 < row1) {
-                load1(row_s(i + 1), row_w(a.R, i + 1), row_w(a.A, i + 1), 0);
+            } else if (ii + 1 < row1) {
+                const int nx = rowof(ii + 1);
+                load1(row_s(nx), row_w(a.R, nx), row_w(a.A, nx), 0);
             }
             if (has_d) sc = sc + d_i;
             V out;
@@ -303,7 +306,9 @@ __device__ __forceinline__ void stream_rows_unpipelined(const SweepArgs<T> &a, c
     const __amdgpu_buffer_rsrc_t rB = row_rsrc(a.B, ldw * (int64_t)sizeof(T));
     int buf = 0;
     int chg = 0;   // a label of this workgroup's rows changed (thread 0; one atomic per workgroup)
-    for (int i = row0; i < row1; ++i, buf ^= 1) {
+    auto rowof = [&](int k) { return slot_row(k, row0, a.rb, a.row_stride); };
+    for (int ii = row0; ii < row1; ++ii, buf ^= 1) {
+        const int i = rowof(ii);
         const __amdgpu_buffer_rsrc_t rS = row_rsrc(a.S + (int64_t)i * a.lds, a.lds * (int64_t)sizeof(T));
         const __amdgpu_buffer_rsrc_t rR = row_rsrc(a.R + (int64_t)i * ldw, ldw * (int64_t)sizeof(T));
         const __amdgpu_buffer_rsrc_t rA = row_rsrc(a.A + (int64_t)i * ldw, ldw * (int64_t)sizeof(T));
@@ -538,13 +543,16 @@ __device__ __forceinline__ void held_rows(const SweepArgs<float> &a, const int t
     };
     int buf = 0;
     int chg = 0;
-    if (row0 < row1) load1(row0, 0);
-    for (int i = row0; i < row1; ++i, buf ^= 1) {
-        const int r = (i - row0) % kWin;
+    auto rowof = [&](int k) { return slot_row(k, row0, a.rb, a.row_stride); };
+    if (row0 < row1) load1(rowof(row0), 0);
+    for (int ii = row0; ii < row1; ++ii, buf ^= 1) {
+        const int i = rowof(ii);
+        const int r = (ii - row0) % kWin;
         if (r == 0) {
             __syncthreads();
-            const int k = i + tid;
-            if (tid < kWin && k < row1) {
+            const int kk = ii + tid;
+            const int k = rowof(kk);
+            if (tid < kWin && kk < row1) {
                 st_p[tid] = a.pref[k];
                 T tv = zero;
                 st_has[tid] = row_tau(a, k, t, tv) ? 1 : 0;
@@ -670,7 +678,7 @@ __device__ __forceinline__ void held_rows(const SweepArgs<float> &a, const int t
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             const int j0 = c * NT * VW + base;
-            if (c + 1 == NCH && i + 1 < row1) load1(i + 1, 0);
+            if (c + 1 == NCH && ii + 1 < row1) load1(rowof(ii + 1), 0);
             asm volatile("" : "+v"(dcol));
             V out;
 #pragma unroll
@@ -706,7 +714,7 @@ __global__ __launch_bounds__(NT) void sweep_held_kernel(SweepArgs<float> a) {
 #pragma unroll
     for (int c = 0; c < NCH; ++c) qs[c][threadIdx.x] = (V)(0.f);
     const int row0 = blockIdx.x * a.rb;
-    const int row1 = min(a.rows, row0 + a.rb);
+    const int row1 = slots_end(a.rows, a.rb, row0, a.row_stride);
     const HeldPair none{};
     if (t == 1)
         held_rows<NT, NCH, true, TAIL, false>(a, t, row0, row1, 0, a.n, qs, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck, none);
@@ -744,7 +752,7 @@ __global__ __launch_bounds__(NT) void sweep_pair_kernel(SweepArgs<float> a, Pair
 #pragma unroll
     for (int c = 0; c < NCH; ++c) qs[c][threadIdx.x] = (V)(0.f);
     const int row0 = pair * a.rb;
-    const int row1 = min(a.rows, row0 + a.rb);
+    const int row1 = slots_end(a.rows, a.rb, row0, a.row_stride);
     HeldPair hp;
     hp.mine = p.slots + ((size_t)pair * 2 + side) * 10;
     hp.theirs = p.slots + ((size_t)pair * 2 + (side ^ 1)) * 10;
@@ -786,7 +794,7 @@ __global__ __launch_bounds__(NT) void sweep_stream_kernel(SweepArgs<T> a, int nc
             buf_store<V, 0>((V)(T(0)), rQ, threadIdx.x * 16, c * CB);
     }
     const int row0 = blockIdx.x * a.rb;
-    const int row1 = min(a.rows, row0 + a.rb);
+    const int row1 = slots_end(a.rows, a.rb, row0, a.row_stride);
     if constexpr (sizeof(T) == 4) {
         if (t == 1)
             stream_rows<T, NT, true, TAIL>(a, t, row0, row1, nch, qs, rQ, sh_m1, sh_k1, sh_m2, sh_cv, sh_ck);
@@ -1113,6 +1121,7 @@ hipError_t launch_sweep_level(const T *S, int64_t lds, const LevelPtrs<T> &lv, T
     a.tau_store = ex.tau_store;
     a.mrhap = ex.mrhap;
     a.delta = ex.delta;
+    a.row_stride = row_stride_of(lc, a.rows);
     const int nb = (a.rows + lc.rows_per_block - 1) / lc.rows_per_block;
     const bool tail = (int64_t)lc.threads * lc.chunks * Vec<T>::N != n;
     if (lc.streaming && lc.chunks == 32) {

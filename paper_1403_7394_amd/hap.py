@@ -22,6 +22,7 @@ LAUNCH_STREAM = 2
 LAUNCH_EAGER = 4
 LAUNCH_UNFUSED = 8
 LAUNCH_FUSED = 16   # reported by hap_get_launch: the MapReduce levels run in one fused pass
+LAUNCH_BLOCKS = 32  # each workgroup takes a contiguous block of rows (default: rows interleaved)
 SCHEDULE_SEQUENTIAL, SCHEDULE_MRHAP = 0, 1
 
 # every symbol include/hap.h declares
@@ -346,17 +347,20 @@ class Hap:
         _check("hap_similarity_offsets", self._lib.hap_similarity_offsets(self._ctx, level, ctypes.c_void_p(d.data_ptr())))
         return d
 
-    def set_launch(self, threads=0, chunks=0, rows_per_block=0, streaming=None, eager=None, unfused=None):
-        """Launch shape; streaming / eager / unfused None keep the current choice (the flags are
-        set together)."""
-        if streaming is None and eager is None and unfused is None:
+    def set_launch(self, threads=0, chunks=0, rows_per_block=0, streaming=None, eager=None, unfused=None,
+                   blocks=None):
+        """Launch shape; streaming / eager / unfused / blocks None keep the current choice (the
+        flags are set together)."""
+        if streaming is None and eager is None and unfused is None and blocks is None:
             flags = -1
         else:
             cur = self.launch_flags()
             st = bool(cur & LAUNCH_STREAM) if streaming is None else streaming
             ea = bool(cur & LAUNCH_EAGER) if eager is None else eager
             uf = bool(cur & LAUNCH_UNFUSED) if unfused is None else unfused
-            flags = (LAUNCH_STREAM if st else 0) | (LAUNCH_EAGER if ea else 0) | (LAUNCH_UNFUSED if uf else 0)
+            bl = bool(cur & LAUNCH_BLOCKS) if blocks is None else blocks
+            flags = ((LAUNCH_STREAM if st else 0) | (LAUNCH_EAGER if ea else 0) | (LAUNCH_UNFUSED if uf else 0)
+                     | (LAUNCH_BLOCKS if bl else 0))
         _check("hap_set_launch", self._lib.hap_set_launch(self._ctx, threads, chunks, rows_per_block, flags))
 
     def launch_flags(self) -> int:

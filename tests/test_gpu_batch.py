@@ -192,13 +192,15 @@ def _run_batch_split(hap, Xs, L, lam, T, split_n, max_members, K=0, launch=None,
 
 
 def _plain(hap, X, L, lam, T, rows_per_block, K=0):
-    """The single-problem path on the same points with the given rows per workgroup."""
+    """The single-problem path on the same points with the given rows per workgroup, each
+    workgroup taking a contiguous block of rows as a gang member does."""
     n = X.shape[0]
     Xt = torch.from_numpy(X).to(DEV)
     S = torch.empty((n, n + (-n) % 4), dtype=torch.float32, device=DEV)[:, :n]
     hap.build_similarity(Xt, S)
     h = hap.Hap(S, L, lam)
-    h.set_launch(rows_per_block=rows_per_block)
+    h.set_launch(rows_per_block=rows_per_block, blocks=True)
+    assert h.launch_flags() & hap.LAUNCH_BLOCKS
     res = h.iterate(T, K)
     labels = h.labels().cpu().numpy()
     ns = [h.net_similarity(l) for l in range(L)]

@@ -520,6 +520,56 @@ def test_f32_launch_shapes(hap_gpu):
         check_messages(g, r, 3, 1e-4)
 
 
+@pytest.mark.parametrize("rb,streaming", [(7, False), (3, True), (16, False)])
+def test_interleaved_and_block_row_orders(hap_gpu, rb, streaming):
+    """Workgroups taking rows g, g + G, g + 2G, ... (the default) or contiguous blocks
+    (HAP_LAUNCH_BLOCKS) visit every row once, with a ragged last round of rows (300 rows,
+    G = ceil(300 / rb) workgroups): the labels equal the oracle's and the FP64 messages of
+    both orders stay within 1e-10 of it.  With several rows per workgroup the column sums
+    run in another order than the oracle's, which moves each sweep's sums by about
+    n u = 300 x 1.1e-16 of their scale (3e-12 normwise after 40 sweeps here); a row left
+    out or taken twice would move them by its whole share, orders of magnitude more."""
+    b, rp = synth.workload_small_f64()
+    S = sim.add_noise(sim.similarity(b.X), rp.noise_rel, rp.noise_seed)
+    p = sim.median_offdiag(S)
+    r = hap_ref.hap(S, p, rp.levels, rp.damping, 40)
+    St = to_device(S)
+    for blocks in (False, True):
+        h = hap_gpu.Hap(St, rp.levels, rp.damping)
+        h.set_launch(1024 if streaming else 0, 1 if streaming else 0, rb, streaming=streaming, blocks=blocks)
+        assert bool(h.launch_flags() & hap_gpu.LAUNCH_BLOCKS) == blocks
+        h.iterate(40)
+        g = dict(labels=h.labels().cpu().numpy(),
+                 msgs=[{k: v.cpu().numpy() for k, v in h.messages(l).items()} for l in range(rp.levels)])
+        h.close()
+        check_messages(g, r, rp.levels, 1e-10)
+        assert np.array_equal(g["labels"], r.labels), blocks
+
+
+@pytest.mark.parametrize("n,L,rb", [(2051, 1, 5), (3000, 3, 9)])
+def test_interleaved_rows_fp32_held_and_fused(hap_gpu, n, L, rb):
+    """The same for the FP32 held-row pass (one level) and the fused all-level pass (three
+    levels under the MapReduce schedule): both row orders within 1e-4 of the FP64 oracle."""
+    b, _ = synth.workload_plain_f32(n=n)
+    S32 = oracle_S(b.X, np.float32)
+    schedule = 1 if L > 1 else 0
+    r = hap_ref.hap(S32.astype(np.float64), float(sim.median_offdiag(S32, np.float32)), L, 0.9, 20,
+                    schedule="mrhap" if schedule else "sequential")
+    St = to_device(S32)
+    for blocks in (False, True):
+        h = hap_gpu.Hap(St, L, 0.9, schedule=schedule)
+        if L == 1:
+            h.set_launch(512, 16, rb, streaming=True, blocks=blocks)
+        else:
+            h.set_launch(0, 0, rb, blocks=blocks)
+            assert h.launch_flags() & hap_gpu.LAUNCH_FUSED
+        h.iterate(20)
+        g = dict(labels=h.labels().cpu().numpy(),
+                 msgs=[{k: v.cpu().numpy() for k, v in h.messages(l).items()} for l in range(L)])
+        h.close()
+        check_messages(g, r, L, 1e-4)
+
+
 def test_resume_and_determinism(hap_gpu):
     b, _ = synth.workload_plain_f32(n=1000)
     S = to_device(oracle_S(b.X, np.float32))
