@@ -29,6 +29,29 @@ def test_header_declares_the_binding_exports():
     assert _declared_functions() == sorted(hap.EXPORTS)
 
 
+def _header_enums():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return {k: int(v) for k, v in re.findall(r"\b(HAP_[A-Z0-9_]+)\s*=\s*(\d+)", text)}
+
+
+def test_binding_constants_equal_the_header_enums():
+    """Every constant the binding passes or tests against has the header's value (the
+    binding strips the HAP_ prefix of the launch, build, preference and schedule names)."""
+    enums = _header_enums()
+    checked = 0
+    for name, value in enums.items():
+        for attr in (name, name[len("HAP_"):]):
+            if hasattr(hap, attr):
+                assert getattr(hap, attr) == value, name
+                checked += 1
+                break
+    for name in ("HAP_LAUNCH_STREAM", "HAP_LAUNCH_EAGER", "HAP_LAUNCH_UNFUSED", "HAP_LAUNCH_FUSED",
+                 "HAP_LAUNCH_BLOCKS", "HAP_SCHEDULE_MRHAP", "HAP_BUILD_DIRECT_L2", "HAP_E_UNSUPPORTED"):
+        assert name in enums, name
+    assert checked >= 20, checked
+
+
 def test_every_declared_symbol_is_exported(lib):
     missing = [name for name in _declared_functions() if not hasattr(lib, name)]
     assert not missing
