@@ -166,8 +166,11 @@ HAP_API hap_status hap_median_offdiag_noalloc(const void *S, int64_t n, int64_t 
  * Bandwidth probe for the roofline: one kernel that reads `reads` arrays in[0..reads) and writes
  * `writes` arrays out[0..writes) of rows x cols FP32 elements (device, row stride ld, 16-byte
  * aligned; cols and ld multiples of 4, cols <= 8192), with the access pattern of the sweep's
- * row pass (workgroups of 512 threads own rows_per_block consecutive rows, 16 bytes per thread access,
- * the first input and every output non-temporal); each output element is the sum of the inputs.
+ * row pass (G = ceil(rows / rows_per_block) workgroups of 512 threads, workgroup g taking rows g,
+ * g + G, g + 2G, ..., 16 bytes per thread access, every access non-temporal); each output
+ * element is the sum of the inputs.  An output may be one of the inputs (the same array: each
+ * element is read before it is written, by the same thread), which measures an in-place update
+ * such as the row pass's of rho and alpha.
  * (reads, writes): (0, 1) pure write (in may be NULL; every element of a row gets the row's
  * index, the pattern of the similarity build's stores of S), (1, 0) pure read (out[0] must
  * still point at one writable element, stored to only if the data hold a marker pair, so the

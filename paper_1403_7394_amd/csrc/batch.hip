@@ -231,8 +231,8 @@ __device__ __forceinline__ void sweep_rows_grouped(const SweepArgs<float> &a, co
                 const int j0 = c * NTG * VW + base;
                 if (j0 < n) {
                     xs[c] = __builtin_nontemporal_load((const float4v *)(Srow + j0));
-                    xr[c] = *(const float4v *)(Rrow + j0);
-                    xa[c] = *(const float4v *)(Arow + j0);
+                    xr[c] = __builtin_nontemporal_load((const float4v *)(Rrow + j0));
+                    xa[c] = __builtin_nontemporal_load((const float4v *)(Arow + j0));
                 } else {
                     xs[c] = (float4v)(0.f);
                     xr[c] = (float4v)(0.f);

@@ -67,8 +67,8 @@ __device__ __forceinline__ void fused_rows(const FusedArgs<float> &a, const int 
         for (int c = 0; c < NCH; ++c) {
             const int j0 = c * NT * VW + base;
             if (!TAIL || j0 < n) {
-                ry[c] = *(const V *)(Rrow + j0);
-                ay[c] = *(const V *)(Arow + j0);
+                ry[c] = __builtin_nontemporal_load((const V *)(Rrow + j0));
+                ay[c] = __builtin_nontemporal_load((const V *)(Arow + j0));
             } else {
                 ry[c] = (V)(zero);
                 ay[c] = (V)(ninf);

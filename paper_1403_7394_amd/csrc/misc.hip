@@ -114,17 +114,15 @@ __global__ __launch_bounds__(64) void points_check_kernel(const float *__restric
     if (k == 0) bad[0] = __popcll(m);
 }
 
-// Bandwidth probe with the row pass's access pattern: workgroups of 512 threads own blocks of
-// consecutive rows; a thread owns fixed 16-byte column chunks.  Per element it reads R arrays
-// (the first non-temporally, like S in the row pass) and writes W arrays (non-temporally, like
-// R and A); every output is the sum of the inputs, so no read can be dropped.
+// Bandwidth probe with the row pass's access pattern: of G workgroups of 512 threads,
+// workgroup g takes rows g, g + G, g + 2G, ...; a thread owns fixed 16-byte column chunks.  Per
+// element it reads R arrays and writes W arrays, every access non-temporal as in the row pass;
+// every output is the sum of the inputs, so no read can be dropped.
 template <int R, int W>
 __global__ __launch_bounds__(512) void probe_kernel(ProbeArgs a) {
     typedef float V __attribute__((ext_vector_type(4)));
     constexpr int NCH = 4;   // 16-byte chunks per thread and row: rows of up to 8192 columns
-    const int64_t row0 = (int64_t)blockIdx.x * a.rows_per_block;
-    const int64_t row1 = row0 + a.rows_per_block < a.rows ? row0 + a.rows_per_block : a.rows;
-    for (int64_t i = row0; i < row1; ++i) {
+    for (int64_t i = blockIdx.x; i < a.rows; i += gridDim.x) {
         V acc[NCH];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
@@ -136,7 +134,7 @@ __global__ __launch_bounds__(512) void probe_kernel(ProbeArgs a) {
                 } else {
                     acc[c] = __builtin_nontemporal_load((const V *)(a.in[0] + o));
 #pragma unroll
-                    for (int r = 1; r < R; ++r) acc[c] += *(const V *)(a.in[r] + o);
+                    for (int r = 1; r < R; ++r) acc[c] += __builtin_nontemporal_load((const V *)(a.in[r] + o));
                 }
             }
         }

@@ -152,7 +152,7 @@ __device__ __forceinline__ void stream_rows(const SweepArgs<T> &a, const int t, 
     auto load1 = [&](__amdgpu_buffer_rsrc_t rS, __amdgpu_buffer_rsrc_t rR, __amdgpu_buffer_rsrc_t rA, int c) {
         sv = buf_load<V, 0>(rS, voff, c * CB);
         rv = buf_load<V, 0>(rR, voff, c * CB);
-        av = buf_load<V, 0>(rA, voff, c * CB);
+        av = buf_load<V, kNT>(rA, voff, c * CB);   // alpha is not read again in phase 2
         if constexpr (!FIRST) bv = buf_load<V, 0>(rB, voff, c * CB);
     };
     auto rowof = [&](int k) { return slot_row(k, row0, a.rb, a.row_stride); };
@@ -324,7 +324,7 @@ __device__ __forceinline__ void stream_rows_unpipelined(const SweepArgs<T> &a, c
             V sv = buf_load<V, 0>(rS, voff, c * CB);
             if (has_d) sv = sv + d_i;
             const V rv = buf_load<V, 0>(rR, voff, c * CB);
-            V av = buf_load<V, 0>(rA, voff, c * CB);
+            V av = buf_load<V, kNT>(rA, voff, c * CB);
             V bv = (V)(zero);
             if constexpr (!FIRST) bv = buf_load<V, 0>(rB, voff, c * CB);
             if constexpr (TAIL) {
@@ -534,8 +534,8 @@ __device__ __forceinline__ void held_rows(const SweepArgs<float> &a, const int t
         const __amdgpu_buffer_rsrc_t rR = row_rsrc(a.R + (int64_t)row * ldw + coff, ldw_h * (int64_t)sizeof(T));
         const __amdgpu_buffer_rsrc_t rA = row_rsrc(a.A + (int64_t)row * ldw + coff, ldw_h * (int64_t)sizeof(T));
         sv = buf_load<V, kNT>(rS, voff, c * CB);
-        rv = buf_load<V, 0>(rR, voff, c * CB);
-        av = buf_load<V, 0>(rA, voff, c * CB);
+        rv = buf_load<V, kNT>(rR, voff, c * CB);
+        av = buf_load<V, kNT>(rA, voff, c * CB);
         if constexpr (!FIRST) bv = buf_load<V, 0>(rB, voff, c * CB);
         if constexpr (TAIL) {
             if (c * NT * VW + base >= ncols) av = (V)(ninf);   // columns past n never win a maximum

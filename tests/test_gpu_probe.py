@@ -36,3 +36,22 @@ def test_probe_mixes(hap_gpu, rows, cols, ld, rb):
     hap_gpu.bandwidth_probe(ins[:1], [], sink=sink, rows_per_block=rb)
     torch.cuda.synchronize()
     assert sink.item() == 7.0
+
+
+@pytest.mark.parametrize("rows,cols,ld,rb", [(100, 8192, 8192, 32), (37, 1000, 1004, 5)])
+def test_probe_in_place(hap_gpu, rows, cols, ld, rb):
+    """Outputs that are the last inputs (the row pass's in-place update of rho and alpha):
+    every element is read before it is written, so both outputs hold the sum of the inputs'
+    old values."""
+    g = torch.Generator(device="cpu").manual_seed(3 * rows + cols)
+    base = [torch.randn((rows, ld), generator=g).to(DEV) for _ in range(3)]
+    ins = [t[:, :cols] for t in base]
+    old = [t.clone() for t in ins]
+    hap_gpu.bandwidth_probe(ins, ins[1:], rows_per_block=rb)
+    torch.cuda.synchronize()
+    s3 = (old[0] + old[1]) + old[2]
+    assert torch.equal(ins[0], old[0])
+    assert torch.equal(ins[1], s3) and torch.equal(ins[2], s3)
+    hap_gpu.bandwidth_probe(ins[1:], ins[1:], rows_per_block=rb)
+    torch.cuda.synchronize()
+    assert torch.equal(ins[1], s3 + s3) and torch.equal(ins[2], s3 + s3)
