@@ -170,7 +170,10 @@ HAP_API hap_status hap_median_offdiag_noalloc(const void *S, int64_t n, int64_t 
  * g + G, g + 2G, ..., 16 bytes per thread access, every access non-temporal); each output
  * element is the sum of the inputs.  An output may be one of the inputs (the same array: each
  * element is read before it is written, by the same thread), which measures an in-place update
- * such as the row pass's of rho and alpha.
+ * such as the row pass's of rho and alpha.  flags (a bit set) vary the pattern:
+ * HAP_PROBE_CACHED loads the inputs after the first with cached loads, HAP_PROBE_BLOCKS gives
+ * workgroup g the contiguous rows [g rows_per_block, (g + 1) rows_per_block); other bits are
+ * rejected with HAP_E_ARG.
  * (reads, writes): (0, 1) pure write (in may be NULL; every element of a row gets the row's
  * index, the pattern of the similarity build's stores of S), (1, 0) pure read (out[0] must
  * still point at one writable element, stored to only if the data hold a marker pair, so the
@@ -179,8 +182,10 @@ HAP_API hap_status hap_median_offdiag_noalloc(const void *S, int64_t n, int64_t 
  * Measures what such a mix reaches on the device; not part of the method.  HAP_E_ARG for other
  * mixes or bad sizes, HAP_E_UNSUPPORTED above 8192 columns.  Stream-ordered, no synchronisation.
  */
+enum { HAP_PROBE_CACHED = 1, HAP_PROBE_BLOCKS = 2 };
 HAP_API hap_status hap_bandwidth_probe(int32_t reads, int32_t writes, const float *const *in, float *const *out,
-                                       int64_t rows, int64_t cols, int64_t ld, int64_t rows_per_block, void *stream);
+                                       int64_t rows, int64_t cols, int64_t ld, int64_t rows_per_block, int32_t flags,
+                                       void *stream);
 
 /* Bytes of device workspace hap_init needs for this problem. */
 HAP_API hap_status hap_workspace_size(int64_t n, int32_t levels, int32_t dtype, size_t *bytes);

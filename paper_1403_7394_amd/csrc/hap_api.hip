@@ -647,13 +647,14 @@ hap_status hap_median_offdiag_noalloc(const void *S, int64_t n, int64_t lds, int
 }
 
 hap_status hap_bandwidth_probe(int32_t reads, int32_t writes, const float *const *in, float *const *out, int64_t rows,
-                               int64_t cols, int64_t ld, int64_t rows_per_block, void *stream) {
+                               int64_t cols, int64_t ld, int64_t rows_per_block, int32_t flags, void *stream) {
     const bool mix_ok = (reads == 0 && writes == 1) || (reads == 1 && writes == 0) || (reads == 1 && writes == 1) ||
                         (reads == 2 && writes == 2) || (reads == 3 && writes == 2);
     if (!mix_ok) return fail_arg("hap_bandwidth_probe: (reads, writes) must be (0,1), (1,0), (1,1), (2,2) or (3,2)");
     if ((reads > 0 && !in) || (writes > 0 && !out)) return fail_arg("hap_bandwidth_probe: null pointer");
     if (rows < 1 || cols < 1 || ld < cols || ld % 4 != 0 || cols % 4 != 0 || rows_per_block < 1)
         return fail_arg("hap_bandwidth_probe: bad sizes (cols and ld multiples of 4, ld >= cols)");
+    if (flags & ~(HAP_PROBE_CACHED | HAP_PROBE_BLOCKS)) return fail_arg("hap_bandwidth_probe: unknown flags");
     if (cols > 8192) return fail_arg("hap_bandwidth_probe: at most 8192 columns", HAP_E_UNSUPPORTED);
     if (reads == 1 && writes == 0 && (!out || !out[0]))
         return fail_arg("hap_bandwidth_probe: the pure-read probe needs out[0] (one element, written only if the "
@@ -673,7 +674,8 @@ hap_status hap_bandwidth_probe(int32_t reads, int32_t writes, const float *const
     a.cols = cols;
     a.ld = ld;
     a.rows_per_block = rows_per_block;
-    hipError_t e = hap::launch_probe(reads, writes, a, (hipStream_t)stream);
+    hipError_t e = hap::launch_probe(reads, writes, (flags & HAP_PROBE_CACHED) != 0, (flags & HAP_PROBE_BLOCKS) != 0, a,
+                                     (hipStream_t)stream);
     if (e != hipSuccess) return fail_hip(e, "hap_bandwidth_probe");
     return HAP_OK;
 }

@@ -176,7 +176,7 @@ struct ProbeArgs {
     int64_t rows, cols, ld;
     int64_t rows_per_block;
 };
-hipError_t launch_probe(int reads, int writes, const ProbeArgs &a, hipStream_t st);
+hipError_t launch_probe(int reads, int writes, bool cached, bool blocks, const ProbeArgs &a, hipStream_t st);
 
 // Sampled off-diagonal pairs for the points-mode check (at most 64).
 struct PairSample {

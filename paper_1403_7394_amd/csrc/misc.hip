@@ -115,14 +115,19 @@ __global__ __launch_bounds__(64) void points_check_kernel(const float *__restric
 }
 
 // Bandwidth probe with the row pass's access pattern: of G workgroups of 512 threads,
-// workgroup g takes rows g, g + G, g + 2G, ...; a thread owns fixed 16-byte column chunks.  Per
-// element it reads R arrays and writes W arrays, every access non-temporal as in the row pass;
-// every output is the sum of the inputs, so no read can be dropped.
-template <int R, int W>
+// workgroup g takes rows g, g + G, g + 2G, ... (BLOCKS: the rows_per_block rows from
+// g * rows_per_block); a thread owns fixed 16-byte column chunks.  Per element it reads R arrays
+// and writes W arrays, every access non-temporal as in the row pass (CACHED: the inputs after
+// the first with cached loads); every output is the sum of the inputs, so no read can be
+// dropped.
+template <int R, int W, bool CACHED, bool BLOCKS>
 __global__ __launch_bounds__(512) void probe_kernel(ProbeArgs a) {
     typedef float V __attribute__((ext_vector_type(4)));
     constexpr int NCH = 4;   // 16-byte chunks per thread and row: rows of up to 8192 columns
-    for (int64_t i = blockIdx.x; i < a.rows; i += gridDim.x) {
+    const int64_t first = BLOCKS ? (int64_t)blockIdx.x * a.rows_per_block : blockIdx.x;
+    const int64_t end = BLOCKS ? (first + a.rows_per_block < a.rows ? first + a.rows_per_block : a.rows) : a.rows;
+    const int64_t step = BLOCKS ? 1 : gridDim.x;
+    for (int64_t i = first; i < end; i += step) {
         V acc[NCH];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
@@ -134,7 +139,8 @@ __global__ __launch_bounds__(512) void probe_kernel(ProbeArgs a) {
                 } else {
                     acc[c] = __builtin_nontemporal_load((const V *)(a.in[0] + o));
 #pragma unroll
-                    for (int r = 1; r < R; ++r) acc[c] += __builtin_nontemporal_load((const V *)(a.in[r] + o));
+                    for (int r = 1; r < R; ++r)
+                        acc[c] += CACHED ? *(const V *)(a.in[r] + o) : __builtin_nontemporal_load((const V *)(a.in[r] + o));
                 }
             }
         }
@@ -156,19 +162,25 @@ __global__ __launch_bounds__(512) void probe_kernel(ProbeArgs a) {
 
 }  // namespace
 
-hipError_t launch_probe(int reads, int writes, const ProbeArgs &a, hipStream_t st) {
+hipError_t launch_probe(int reads, int writes, bool cached, bool blocks, const ProbeArgs &a, hipStream_t st) {
     const int grid = (int)((a.rows + a.rows_per_block - 1) / a.rows_per_block);
-#define HAP_PROBE(RR, WW)                                                                 \
-    if (reads == RR && writes == WW) {                                                    \
-        hipLaunchKernelGGL((probe_kernel<RR, WW>), dim3(grid), dim3(512), 0, st, a);      \
-        return hipGetLastError();                                                         \
+#define HAP_PROBE_1(RR, WW, CC, BB)                                                               \
+    if (reads == RR && writes == WW && cached == CC && blocks == BB) {                            \
+        hipLaunchKernelGGL((probe_kernel<RR, WW, CC, BB>), dim3(grid), dim3(512), 0, st, a);      \
+        return hipGetLastError();                                                                 \
     }
+#define HAP_PROBE(RR, WW)             \
+    HAP_PROBE_1(RR, WW, false, false) \
+    HAP_PROBE_1(RR, WW, false, true)  \
+    HAP_PROBE_1(RR, WW, true, false)  \
+    HAP_PROBE_1(RR, WW, true, true)
     HAP_PROBE(0, 1)
     HAP_PROBE(1, 0)
     HAP_PROBE(1, 1)
     HAP_PROBE(2, 2)
     HAP_PROBE(3, 2)
 #undef HAP_PROBE
+#undef HAP_PROBE_1
     return hipErrorInvalidValue;
 }
 

@@ -23,6 +23,7 @@ LAUNCH_EAGER = 4
 LAUNCH_UNFUSED = 8
 LAUNCH_FUSED = 16   # reported by hap_get_launch: the MapReduce levels run in one fused pass
 LAUNCH_BLOCKS = 32  # each workgroup takes a contiguous block of rows (default: rows interleaved)
+PROBE_CACHED, PROBE_BLOCKS = 1, 2
 SCHEDULE_SEQUENTIAL, SCHEDULE_MRHAP = 0, 1
 
 # every symbol include/hap.h declares
@@ -77,7 +78,7 @@ def _declare(lib):
         "hap_build_similarity": (I32, [V, I64, I64, I64, I32, V, I64, I32, I32, D, U64, V]),
         "hap_median_offdiag": (I32, [V, I64, I64, I32, _c_dblp, V]),
         "hap_median_offdiag_noalloc": (I32, [V, I64, I64, I32, V, V]),
-        "hap_bandwidth_probe": (I32, [I32, I32, ctypes.POINTER(V), ctypes.POINTER(V), I64, I64, I64, I64, V]),
+        "hap_bandwidth_probe": (I32, [I32, I32, ctypes.POINTER(V), ctypes.POINTER(V), I64, I64, I64, I64, I32, V]),
         "hap_workspace_size": (I32, [I64, I32, I32, ctypes.POINTER(SZ)]),
         "hap_init": (I32, [ctypes.POINTER(V), V, I64, I64, I32, ctypes.POINTER(hap_params), V, SZ, V]),
         "hap_iterate": (I32, [V, I32, I32, _c_i32p, _c_i32p]),
@@ -196,10 +197,12 @@ def median_offdiag_noalloc(S, out, stream=None) -> None:
         _stream(stream)))
 
 
-def bandwidth_probe(inputs, outputs, sink=None, rows_per_block: int = 32, stream=None) -> None:
+def bandwidth_probe(inputs, outputs, sink=None, rows_per_block: int = 32, stream=None, cached: bool = False,
+                    blocks: bool = False) -> None:
     """hap_bandwidth_probe: reads the 2-D FP32 device tensors `inputs` and writes `outputs`, all
     of one shape and row stride (no inputs: the pure-write mix).  With no outputs (the pure-read
-    mix) `sink` is a one-element FP32 device tensor the kernel may store to."""
+    mix) `sink` is a one-element FP32 device tensor the kernel may store to.  cached / blocks:
+    HAP_PROBE_CACHED / HAP_PROBE_BLOCKS."""
     import torch
     lib = load()
     first = inputs[0] if inputs else outputs[0]
@@ -213,8 +216,9 @@ def bandwidth_probe(inputs, outputs, sink=None, rows_per_block: int = 32, stream
     ins = (ctypes.c_void_p * 3)(*[ctypes.c_void_p(t.data_ptr()) for t in inputs]) if inputs else None
     targets = list(outputs) if outputs else [sink]
     outs = (ctypes.c_void_p * 2)(*[ctypes.c_void_p(t.data_ptr()) for t in targets])
+    flags = (PROBE_CACHED if cached else 0) | (PROBE_BLOCKS if blocks else 0)
     _check("hap_bandwidth_probe", lib.hap_bandwidth_probe(len(inputs), len(outputs), ins, outs, rows, cols,
-                                                          ld, rows_per_block, _stream(stream)))
+                                                          ld, rows_per_block, flags, _stream(stream)))
 
 
 def workspace_size(n: int, levels: int, dtype_code: int) -> int:

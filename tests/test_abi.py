@@ -195,13 +195,14 @@ def test_batch_planning_checks_arguments(lib):
 def test_bandwidth_probe_checks_arguments(lib):
     fake = (ctypes.c_void_p * 3)(4096, 8192, 12288)     # never dereferenced: every call fails its checks
     outs = (ctypes.c_void_p * 2)(16384, 20480)
-    assert lib.hap_bandwidth_probe(2, 1, fake, outs, 64, 64, 64, 32, None) == hap.HAP_E_ARG     # mix
-    assert lib.hap_bandwidth_probe(1, 1, fake, outs, 64, 63, 64, 32, None) == hap.HAP_E_ARG     # cols % 4
-    assert lib.hap_bandwidth_probe(1, 1, fake, outs, 64, 64, 60, 32, None) == hap.HAP_E_ARG     # ld < cols
-    assert lib.hap_bandwidth_probe(1, 1, fake, outs, 64, 8196, 8196, 32, None) == hap.HAP_E_UNSUPPORTED
-    assert lib.hap_bandwidth_probe(1, 0, fake, None, 64, 64, 64, 32, None) == hap.HAP_E_ARG     # no sink
-    assert lib.hap_bandwidth_probe(0, 1, None, None, 64, 64, 64, 32, None) == hap.HAP_E_ARG     # no output
-    assert lib.hap_bandwidth_probe(0, 2, None, outs, 64, 64, 64, 32, None) == hap.HAP_E_ARG     # mix
+    assert lib.hap_bandwidth_probe(2, 1, fake, outs, 64, 64, 64, 32, 0, None) == hap.HAP_E_ARG     # mix
+    assert lib.hap_bandwidth_probe(1, 1, fake, outs, 64, 63, 64, 32, 0, None) == hap.HAP_E_ARG     # cols % 4
+    assert lib.hap_bandwidth_probe(1, 1, fake, outs, 64, 64, 60, 32, 0, None) == hap.HAP_E_ARG     # ld < cols
+    assert lib.hap_bandwidth_probe(1, 1, fake, outs, 64, 8196, 8196, 32, 0, None) == hap.HAP_E_UNSUPPORTED
+    assert lib.hap_bandwidth_probe(1, 0, fake, None, 64, 64, 64, 32, 0, None) == hap.HAP_E_ARG     # no sink
+    assert lib.hap_bandwidth_probe(0, 1, None, None, 64, 64, 64, 32, 0, None) == hap.HAP_E_ARG     # no output
+    assert lib.hap_bandwidth_probe(0, 2, None, outs, 64, 64, 64, 32, 0, None) == hap.HAP_E_ARG     # mix
+    assert lib.hap_bandwidth_probe(1, 1, fake, outs, 64, 64, 64, 32, 4, None) == hap.HAP_E_ARG     # flags
     import torch
     a = torch.zeros((8, 8))
     with pytest.raises(ValueError):
