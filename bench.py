@@ -276,7 +276,8 @@ def run_batched_form(args, torch, hap, synth) -> dict:
         hap.build_similarity(X[o:o + n], Sv)
         h = hap.Hap(Sv, L, rp.damping, workspace=ws)
         if rows_per_block:
-            h.set_launch(rows_per_block=rows_per_block)
+            # a gang member owns a contiguous block of rows: the plain path's HAP_LAUNCH_BLOCKS order
+            h.set_launch(rows_per_block=rows_per_block, blocks=True)
         h.iterate(iters, 0)
         lab = h.labels()
         ns = h.net_similarity(-1)

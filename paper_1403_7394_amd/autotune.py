@@ -139,14 +139,16 @@ def split_candidates():
     return [(0, 1), (1448, 2), (1024, 2), (1024, 4), (724, 4), (724, 8)]
 
 
-def tune_batch(bt: "hap.HapBatch", X, damping: float, iters: int = 10, use_cache: bool = True):
+def tune_batch(bt: "hap.HapBatch", X, damping: float, iters: int = 50, use_cache: bool = True):
     """Pick threads, workgroup count and row groups of the persistent batched kernel for this
     batch (every shape computes the same bits, so only time decides), then the split of its
     large problems over gangs of workgroups (a split changes the order of the column sums of the
-    split problems, so it is chosen with the shape fixed).  Returns (threads, workgroups,
-    row_groups, split_n, max_members)."""
+    split problems, so it is chosen with the shape fixed).  Each candidate runs `iters`
+    iterations: enough that the sweeps decide, as in a run of a few hundred iterations, rather
+    than the build and median of the largest problems, which a split shortens.  Returns
+    (threads, workgroups, row_groups, split_n, max_members)."""
     import torch
-    key = f"batch2:{_arch()}:d{bt.d}:L{bt.levels}:{batch_signature(bt.sizes)}"
+    key = f"batch3:{_arch()}:d{bt.d}:L{bt.levels}:i{iters}:{batch_signature(bt.sizes)}"
     if use_cache:
         hit = _load_cache().get(key)
         if hit and len(hit) == 6:

@@ -267,9 +267,9 @@ def test_split_plan_and_arguments(hap_gpu):
 
 def test_split_full_batched_workload_sampled_problems(hap_gpu):
     """The full batched workload (512 problems, N ~ U{64..2048}, d = 16, L = 3, damping 0.8) in
-    the launch the autotuner picks, with the benchmark's split: the smallest, a middle and the
-    largest problem (split) equal the single-problem path with the same row blocks over 8
-    iterations."""
+    the launch and split the autotuner picks, as the benchmark does: the smallest, a middle and
+    the largest problem (split, if the tuner splits it) equal the single-problem path with the
+    same row blocks over 8 iterations."""
     from paper_1403_7394_amd import autotune
     problems, rp = synth.workload_batched()
     sizes = [b.X.shape[0] for b in problems]
