@@ -861,6 +861,14 @@ __global__ __launch_bounds__(16 * NG) void colsum_kernel(ColArgs<T> a) {
     const int col = threadIdx.x & 15, g = threadIdx.x >> 4;
     const int j0 = (blockIdx.x * 16 + col) * VW;
     const int n = a.n, nb = a.nb;
+    // the vectors the sums are combined with were written before this launch: load them first,
+    // so that their latency overlaps that of the partials
+    V cv = (V)(T(0)), bd = (V)(T(0));
+    if (g == 0 && j0 < n) {
+        if (a.tau_next != nullptr) cv = *(const V *)(a.C + j0);
+        if (a.B_down != nullptr)
+            bd = (*(const V *)(a.C_down + j0) + *(const V *)(a.phi_down + j0)) + *(const V *)(a.Q_down + j0);
+    }
     V acc = (V)(T(0));
     if (j0 < n) {
         if (NG == 1) {
@@ -881,11 +889,9 @@ __global__ __launch_bounds__(16 * NG) void colsum_kernel(ColArgs<T> a) {
 #pragma unroll
         for (int k = 1; k < NG; ++k) tot += sh[k][col];
         *(V *)(a.Q + j0) = tot;
-        if (a.tau_next != nullptr) *(V *)(a.tau_next + j0) = *(const V *)(a.C + j0) + tot;
+        if (a.tau_next != nullptr) *(V *)(a.tau_next + j0) = cv + tot;
         if (a.B_top != nullptr) *(V *)(a.B_top + j0) = tot;
-        if (a.B_down != nullptr)
-            *(V *)(a.B_down + j0) =
-                (*(const V *)(a.C_down + j0) + *(const V *)(a.phi_down + j0)) + *(const V *)(a.Q_down + j0);
+        if (a.B_down != nullptr) *(V *)(a.B_down + j0) = bd;
     }
     if (a.last && blockIdx.x == 0 && threadIdx.x == 0) {
         DevState *ds = a.ds;
