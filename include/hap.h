@@ -477,8 +477,9 @@ HAP_API hap_status hap_iterate_warm(hap_ctx *ctx, const float *Y, int64_t ldy, i
  * cold run (Algorithm 1's alpha = 0) on the same context; each is scored by its net
  * similarity summed over the levels (hap_net_similarity(level -1) with the X, d, ldx, x_dtype
  * given here: recomputed from X in FP64 when X is not NULL, else read from S).  The run kept
- * is the converged one if only one converged, else the one with the larger score (the warm
- * run on a tie).  When the warm run is kept it is run again, so that the context's state and
+ * is the one with the larger score (the warm run on a tie), whether or not it converged: a
+ * converged run can score far worse (a start from which every point stays its own exemplar
+ * converges at once).  When the warm run is kept it is run again, so that the context's state and
  * labels are the kept run's (every pass is deterministic, so the rerun repeats it bit for
  * bit; HAP_E_STATE if the rerun's stop iteration differs).  Outputs (host, each may be
  * NULL): iters_done and converged of the kept run,

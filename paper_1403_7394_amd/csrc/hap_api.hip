@@ -1583,7 +1583,9 @@ hap_status hap_iterate_warm_judged(hap_ctx *c, const float *Y, int64_t ldy, int3
     if (s == HAP_OK) s = hap_iterate(c, max_iters, stable_iters, &it_c, &cv_c);
     if (s == HAP_OK) s = hap_net_similarity(c, -1, X, d, ldx, x_dtype, &sc);
     if (s != HAP_OK) return s;
-    const bool keep_warm = (cv_w != cv_c) ? (cv_w != 0) : !(sc > sw);
+    // net similarity decides: a converged run whose clustering scores worse (such as one
+    // where every point stays its own exemplar) loses against an unconverged better one
+    const bool keep_warm = !(sc > sw);
     if (keep_warm) {
         int32_t it = 0, cv = 0;
         s = hap_set_warm_start(c, Y, ldy);

@@ -439,8 +439,8 @@ class Hap:
 
     def iterate_warm_judged(self, Y, max_iters: int, stable_iters: int, X=None):
         """Warm run judged by the cold start: both run, the one with the larger net similarity
-        summed over levels (from X in FP64 when given, else from S; a converged run beats one
-        that did not converge) is kept.  Returns (IterResult, fell_back, ns_warm, ns_cold)."""
+        summed over levels (from X in FP64 when given, else from S; the warm run on a tie) is
+        kept, converged or not.  Returns (IterResult, fell_back, ns_warm, ns_cold)."""
         if Y is None:
             raise ValueError("iterate_warm_judged needs a warm start Y")
         it, cv, fb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

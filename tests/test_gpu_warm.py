@@ -296,11 +296,9 @@ def test_end_to_end_warm_start_runs(hap_gpu):
     jns = j.net_similarity(-1)
     j.close()
     assert ns_c == cns
-    if cres.converged:
-        assert jres.converged
     assert jns == (ns_c if jfell else ns_w)
-    if jres.converged == cres.converged:
-        assert jns >= cns
+    assert jns >= cns
+    assert jfell == (ns_c > ns_w)
     if jfell:
         assert np.array_equal(jlab, clab) and jres.iters == cres.iters
     else:
