@@ -23,9 +23,10 @@
 // reads at that point, so the trajectory is the level-sequential one, while
 // each level moves 5 N^2 words per sweep (read S, R, A; write R, A).
 //
-// Each workgroup owns a block of consecutive rows and keeps its column partials
-// in registers (every thread owns the same columns for every row); the partials
-// are summed in a fixed order by the epilogue, so results are deterministic.
+// Each workgroup owns a set of rows (by default, of G workgroups, workgroup g takes rows g,
+// g + G, g + 2G, ...; a contiguous block on request) and keeps its column partials in
+// registers (every thread owns the same columns for every row); the partials are summed in a
+// fixed order by the epilogue, so results are deterministic.
 #include "rowpass.h"
 
 namespace hap {
