@@ -420,7 +420,7 @@ __device__ __forceinline__ void sweep_rows_points(const SweepArgs<T> &a, const i
         const int i = rowof(ii);
         const int r = (ii - row0) % kWin;
         if (r == 0) {
-            // stage the scalars of rows [i, i + kWin)
+            // stage the scalars of this workgroup's next kWin rows
             __syncthreads();
             const int kk = ii + tid;
             const int k = rowof(kk);

@@ -429,7 +429,7 @@ __device__ __forceinline__ void stream_rows_unpipelined(const SweepArgs<T> &a, c
 // window of kWin rows, so that no global load issued after those loads is waited for in a row.
 //
 // PAIR: the paired pass for rows twice as long (32768 < n <= 65536 at 512 threads): two
-// workgroups share a block of rows, one holding columns [0, H) and the other [H, n) of every
+// workgroups share a set of rows, one holding columns [0, H) and the other [H, n) of every
 // row (H = NT*NCH*4), each exactly as above on its half.  Between the phases of a row each
 // workgroup publishes its half's (M1, k1, M2) and (c, e) and merges the partner's: thread 0
 // writes five 64-bit words, each a value with a tag naming the sweep and the row in its upper
