@@ -393,23 +393,25 @@ def _vectors(hap_gpu, h, l):
     return c, phi, tau
 
 
-@pytest.mark.parametrize("n,rb,schedule,kappa", [(5001, 20, 0, 0.0), (8192, 32, 0, 0.0), (6001, 24, 1, 0.0),
-                                                 (7000, 28, 0, 0.5)])
-def test_paired_pass_matches_streaming(hap_gpu, n, rb, schedule, kappa):
+@pytest.mark.parametrize("n,rb,schedule,kappa,blocks", [(5001, 20, 0, 0.0, False), (8192, 32, 0, 0.0, False),
+                                                        (6001, 24, 1, 0.0, False), (7000, 28, 0, 0.5, False),
+                                                        (5001, 20, 0, 0.0, True), (6001, 24, 1, 0.0, True)])
+def test_paired_pass_matches_streaming(hap_gpu, n, rb, schedule, kappa, blocks):
     """The paired pass (two workgroups per block of rows, each holding half of every row, the
     row maxima exchanged once per row), here with 64-thread workgroups so that a row of a few
     thousand points already spans two of them, against the streaming pass with the same rows
     per block (the same column-sum order): bit-identical messages, labels and vectors over 20
-    sweeps, for the plain and the MapReduce schedule and with the Eq. 2.7 offsets; the last
-    block of 5001 and 6001 rows holds a single row, so its exchange slots carry the previous
-    level's values with the same sweep and row when the next level starts."""
+    sweeps, for the plain and the MapReduce schedule, with the Eq. 2.7 offsets, and with
+    contiguous row blocks (HAP_LAUNCH_BLOCKS) as well as the default interleaved rows; with
+    blocks the last block of 5001 and 6001 rows holds a single row, so its exchange slots carry
+    the previous level's values with the same sweep and row when the next level starts."""
     b, _ = synth.workload_plain_f32(n=n)
     S32 = oracle_S(b.X, np.float32)
     St = to_device(S32)
     out = []
     for shape in [(64, 32, rb, True), (1024, -(-n // 4096), rb, True)]:
         h = hap_gpu.Hap(St, 3, 0.9, schedule=schedule, kappa=kappa)
-        h.set_launch(*shape[:3], streaming=shape[3])
+        h.set_launch(*shape[:3], streaming=shape[3], blocks=blocks)
         assert h.get_launch() == shape
         h.iterate(20)
         out.append([h.messages(l) for l in range(3)] + [h.labels()])
