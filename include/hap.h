@@ -463,6 +463,16 @@ HAP_API hap_status hap_warm_targets(hap_ctx *ctx, float *T, int64_t ldt);
  */
 HAP_API hap_status hap_set_warm_start(hap_ctx *ctx, const float *Y, int64_t ldy);
 /*
+ * Restart the context from the Algorithm 1 initial state (the preferences stay) with given
+ * initial availabilities instead of alpha = 0: alpha^l_jj = alpha_diag0[j*ld + l] (device, the
+ * working type, n rows, ld >= levels) and alpha^l_ij = min(0, alpha_diag0[j*ld + l]) for
+ * i != j, the values Eq. 2.2-2.3 give at rho = 0 from an availability base per column (what
+ * hap_set_warm_start forms from the network outputs; this call takes the values themselves,
+ * for a start computed elsewhere).  HAP_E_ARG for a null pointer or ld < levels.
+ * Synchronises the stream.
+ */
+HAP_API hap_status hap_set_warm_alpha(hap_ctx *ctx, const void *alpha_diag0, int64_t ld);
+/*
  * Warm run with the cold start as fallback: hap_set_warm_start(Y), hap_iterate(max_iters,
  * stable_iters); if that run does not converge (and Y is not NULL), restart cold and iterate
  * again.  *fell_back (host, may be NULL) is 1 when the cold run's result is the one

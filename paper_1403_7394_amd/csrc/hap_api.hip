@@ -1473,7 +1473,7 @@ namespace {
 // Back to the Algorithm 1 initial state (the preferences stay), then, when Y is given, the
 // warm initial availabilities of every level from the network outputs Y (n x L, row stride ldy).
 template <typename T>
-hap_status restart_state(hap_ctx *c, const float *Y, int64_t ldy) {
+hap_status restart_state(hap_ctx *c, const float *Y, int64_t ldy, const T *diag = nullptr, int64_t ldd = 0) {
     const Layout lo = make_layout(c->n, c->L, c->esz);
     char *base = (char *)c->ws;
     hipStream_t st = c->stream;
@@ -1488,6 +1488,11 @@ hap_status restart_state(hap_ctx *c, const float *Y, int64_t ldy) {
         for (int l = 0; l < c->L; ++l) {
             LevelPtrs<T> lv = level_ptrs<T>(c, l);
             HIP_TRY(hap::launch_warm_alpha<T>(lv, (int)c->n, c->ldw, Y, ldy, l, (T *)c->Qpart, st), c);
+        }
+    } else if (diag) {
+        for (int l = 0; l < c->L; ++l) {
+            LevelPtrs<T> lv = level_ptrs<T>(c, l);
+            HIP_TRY(hap::launch_warm_fill<T>(lv, (int)c->n, c->ldw, diag + l, ldd, st), c);
         }
     }
     HIP_TRY(hipStreamSynchronize(st), c);
@@ -1544,6 +1549,15 @@ hap_status hap_set_warm_start(hap_ctx *c, const float *Y, int64_t ldy) {
     if (c->failed) return fail_arg("hap_set_warm_start: context failed earlier", HAP_E_STATE);
     if (Y && ldy < c->L) return fail_arg("hap_set_warm_start: ldy < levels");
     return c->dtype == HAP_F32 ? restart_state<float>(c, Y, ldy) : restart_state<double>(c, Y, ldy);
+}
+
+hap_status hap_set_warm_alpha(hap_ctx *c, const void *alpha_diag0, int64_t ld) {
+    if (!c) return fail_arg("hap_set_warm_alpha: null context");
+    if (c->failed) return fail_arg("hap_set_warm_alpha: context failed earlier", HAP_E_STATE);
+    if (!alpha_diag0) return fail_arg("hap_set_warm_alpha: null alpha_diag0 (hap_set_warm_start(ctx, NULL, 0) restarts cold)");
+    if (ld < c->L) return fail_arg("hap_set_warm_alpha: ld < levels");
+    if (c->dtype == HAP_F32) return restart_state<float>(c, nullptr, 0, (const float *)alpha_diag0, ld);
+    return restart_state<double>(c, nullptr, 0, (const double *)alpha_diag0, ld);
 }
 
 hap_status hap_iterate_warm(hap_ctx *c, const float *Y, int64_t ldy, int32_t max_iters, int32_t stable_iters,

@@ -275,6 +275,10 @@ hipError_t launch_warm_targets(const LevelPtrs<T> &lv, int n, int64_t ldw, doubl
 template <typename T>
 hipError_t launch_warm_alpha(const LevelPtrs<T> &lv, int n, int64_t ldw, const float *Y, int64_t ldy, int col,
                              T *bases_scratch, hipStream_t st);
+// alpha^l from given diagonal values bases[j * stride] (alpha_ij = min(0, bases_j) off it).
+template <typename T>
+hipError_t launch_warm_fill(const LevelPtrs<T> &lv, int n, int64_t ldw, const T *bases, int64_t stride,
+                            hipStream_t st);
 
 void set_error(const std::string &msg);
 

@@ -194,10 +194,11 @@ __global__ __launch_bounds__(256) void warm_bases_kernel(const float *__restrict
     bases[j] = (T)b;
 }
 
-// alpha_ij = min(0, B_j) (i != j), alpha_jj = B_j; padding columns -inf.
+// alpha_ij = min(0, B_j) (i != j), alpha_jj = B_j with B_j = bases[j * stride]; padding
+// columns -inf.
 template <typename T>
 __global__ __launch_bounds__(256) void warm_fill_kernel(T *__restrict__ A, int n, int64_t ldw,
-                                                        const T *__restrict__ bases) {
+                                                        const T *__restrict__ bases, int64_t stride) {
     using V = typename Vec<T>::type;
     constexpr int VW = Vec<T>::N;
     const int64_t per_row = ldw / VW;
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(256) void warm_fill_kernel(T *__restrict__ A, int n
             const int j = j0 + v;
             T x = ninf;
             if (j < n) {
-                const T b = bases[j];
+                const T b = bases[(int64_t)j * stride];
                 x = (j == i) ? b : fmin(zero, b);
             }
             out[v] = x;
@@ -253,10 +254,16 @@ hipError_t launch_warm_alpha(const LevelPtrs<T> &lv, int n, int64_t ldw, const f
                        bases_scratch);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    return launch_warm_fill<T>(lv, n, ldw, bases_scratch, 1, st);
+}
+
+template <typename T>
+hipError_t launch_warm_fill(const LevelPtrs<T> &lv, int n, int64_t ldw, const T *bases, int64_t stride,
+                            hipStream_t st) {
     const int64_t total = (int64_t)n * (ldw / Vec<T>::N);
     const int64_t blocks = (total + 255) / 256;
     hipLaunchKernelGGL((warm_fill_kernel<T>), dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256), 0, st, lv.A,
-                       n, ldw, (const T *)bases_scratch);
+                       n, ldw, bases, stride);
     return hipGetLastError();
 }
 
@@ -266,7 +273,8 @@ hipError_t launch_warm_alpha(const LevelPtrs<T> &lv, int n, int64_t ldw, const f
     template hipError_t launch_warm_targets<T>(const LevelPtrs<T> &, int, int64_t, double, int, float *, int64_t,  \
                                                hipStream_t);                                                       \
     template hipError_t launch_warm_alpha<T>(const LevelPtrs<T> &, int, int64_t, const float *, int64_t, int, T *, \
-                                             hipStream_t);
+                                             hipStream_t);                                                         \
+    template hipError_t launch_warm_fill<T>(const LevelPtrs<T> &, int, int64_t, const T *, int64_t, hipStream_t);
 HAP_WARM_INSTANTIATE(float)
 HAP_WARM_INSTANTIATE(double)
 

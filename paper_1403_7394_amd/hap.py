@@ -36,7 +36,8 @@ EXPORTS = (
     "hap_get_launch", "hap_profile", "hap_profile_read", "hap_destroy",
     "hap_batch_workspace_size", "hap_batch_create", "hap_batch_run", "hap_batch_set_launch",
     "hap_batch_get_launch", "hap_batch_set_split", "hap_batch_get_split", "hap_batch_get_members", "hap_batch_destroy",
-    "hap_warm_features", "hap_warm_targets", "hap_set_warm_start", "hap_iterate_warm", "hap_iterate_warm_judged",
+    "hap_warm_features", "hap_warm_targets", "hap_set_warm_start", "hap_set_warm_alpha", "hap_iterate_warm",
+    "hap_iterate_warm_judged",
     "hap_mlp_param_count", "hap_mlp_workspace_size", "hap_mlp_forward", "hap_mlp_loss_grad", "hap_mlp_adam",
     "hap_mlp_train",
 )
@@ -107,6 +108,7 @@ def _declare(lib):
         "hap_warm_features": (I32, [V, V, I64]),
         "hap_warm_targets": (I32, [V, V, I64]),
         "hap_set_warm_start": (I32, [V, V, I64]),
+        "hap_set_warm_alpha": (I32, [V, V, I64]),
         "hap_iterate_warm": (I32, [V, V, I64, I32, I32, _c_i32p, _c_i32p, _c_i32p]),
         "hap_iterate_warm_judged": (I32, [V, V, I64, I32, I32, V, I64, I64, I32, _c_i32p, _c_i32p, _c_i32p,
                                           _c_dblp, _c_dblp]),
@@ -428,6 +430,17 @@ class Hap:
         ptr, ld = (None, 0) if Y is None else (ctypes.c_void_p(Y.data_ptr()), _ld(Y))
         self._warm_keep = Y
         _check("hap_set_warm_start", self._lib.hap_set_warm_start(self._ctx, ptr, ld))
+
+    def set_warm_alpha(self, alpha_diag0):
+        """Restart from given initial availabilities: alpha_diag0 (n, levels), device, the
+        working type; alpha^l_jj = alpha_diag0[j, l], alpha^l_ij = min(0, alpha_diag0[j, l])."""
+        import torch
+        if alpha_diag0 is None or not alpha_diag0.is_cuda or alpha_diag0.dtype != self.dtype or \
+                alpha_diag0.dim() != 2 or alpha_diag0.shape[0] != self.n or alpha_diag0.stride(1) != 1:
+            raise ValueError("set_warm_alpha: a device (n, levels) tensor of the working type, unit column stride")
+        self._warm_keep = alpha_diag0
+        _check("hap_set_warm_alpha", self._lib.hap_set_warm_alpha(self._ctx, ctypes.c_void_p(alpha_diag0.data_ptr()),
+                                                                  alpha_diag0.stride(0)))
 
     def iterate_warm(self, Y, max_iters: int, stable_iters: int):
         """Warm run with the cold start as fallback: (IterResult, fell_back)."""

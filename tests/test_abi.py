@@ -162,6 +162,7 @@ def test_warm_calls_reject_a_null_context(lib):
     assert lib.hap_warm_features(None, fake, 32) == hap.HAP_E_ARG
     assert lib.hap_warm_targets(None, fake, 3) == hap.HAP_E_ARG
     assert lib.hap_set_warm_start(None, None, 0) == hap.HAP_E_ARG
+    assert lib.hap_set_warm_alpha(None, fake, 3) == hap.HAP_E_ARG
     assert lib.hap_iterate_warm(None, None, 0, 10, 5, None, None, None) == hap.HAP_E_ARG
     assert lib.hap_iterate_warm_judged(None, fake, 1, 10, 5, None, 0, 0, 0, None, None, None, None,
                                        None) == hap.HAP_E_ARG

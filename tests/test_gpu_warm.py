@@ -115,6 +115,43 @@ def test_warm_availabilities_and_run_match_fp32_oracle(hap_gpu):
     assert np.array_equal(labels, r.labels)
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_given_initial_availabilities_match_the_oracle(hap_gpu, dtype):
+    """hap_set_warm_alpha: initial availabilities from given diagonal values (alpha_jj = b_j,
+    alpha_ij = min(0, b_j)), negative and positive, set exactly and run bit-identically to the
+    oracle started from the same alpha^0 (one row per workgroup, so the column sums run in row
+    order); a cold restart afterwards equals a fresh cold run."""
+    S, p = problem(913, 260, k=4, dtype=dtype)
+    n, L, lam, T = 260, 3, 0.8, 20
+    rng = np.random.default_rng(7)
+    B0 = (rng.standard_normal((L, n)) * abs(float(p))).astype(dtype)
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    h = hap_gpu.Hap(to_device(S), L, lam)
+    h.set_launch(rows_per_block=1)
+    h.set_warm_alpha(torch.from_numpy(np.ascontiguousarray(B0.T)).to(DEV))
+    a0 = warm.warm_alpha0(B0.astype(np.float64), n, dtype)
+    for l in range(L):
+        assert np.array_equal(h.messages(l)["alpha"].cpu().numpy(), a0[l]), l
+    h.iterate(T)
+    msgs = [{k: v.cpu().numpy() for k, v in h.messages(l).items()} for l in range(L)]
+    labels = h.labels().cpu().numpy()
+    r = hap_ref.hap(S, p, L, lam, T, alpha0=a0, dtype=dtype)
+    for l in range(L):
+        assert np.array_equal(msgs[l]["rho"], r.state.rho[l]), l
+        assert np.array_equal(msgs[l]["alpha"], r.state.alpha[l]), l
+    assert np.array_equal(labels, r.labels)
+    h.set_warm_start(None)
+    h.iterate(T)
+    cold_labels = h.labels().cpu().numpy()
+    h.close()
+    assert np.array_equal(cold_labels, hap_ref.hap(S, p, L, lam, T, dtype=dtype).labels)
+    # fewer columns than levels: refused by the library (HAP_E_ARG), nothing read
+    h2 = hap_gpu.Hap(to_device(S), L, lam)
+    with pytest.raises(hap_gpu.HapError):
+        h2.set_warm_alpha(torch.zeros((n, L - 1), dtype=tdt, device=DEV))
+    h2.close()
+
+
 def test_zero_outputs_equal_the_cold_start(hap_gpu):
     S, p = problem(912, 200, k=3)
     St = to_device(S)
