@@ -93,6 +93,31 @@ def test_fp32_streaming_bit_identical(hap_gpu, launch):
     same_as_oracle(g, hap_ref.hap(S32, p, 3, 0.7, 30, dtype=np.float32, kappa=0.5), 3)
 
 
+@pytest.mark.parametrize("launch,streaming", [((0, 0, 7), None), ((1024, 1, 3), True)])
+def test_several_rows_per_workgroup_both_orders(hap_gpu, launch, streaming):
+    """With several rows per workgroup the column sums run in another order than the oracle's
+    (interleaved rows, the default, or contiguous blocks): FP64 messages and offsets within
+    1e-10 of the oracle (rounding of reordered sums over 40 sweeps, as in the plain parity
+    tests) and the labels equal, for the register-resident and the streaming pass."""
+    b, rp = synth.workload_small_f64()
+    S = sim.add_noise(sim.similarity(b.X), rp.noise_rel, rp.noise_seed)
+    p = sim.median_offdiag(S)
+    r = hap_ref.hap(S, p, 3, 0.5, 40, kappa=0.5)
+    for blocks in (False, True):
+        h = hap_gpu.Hap(to_device(S), 3, 0.5, kappa=0.5)
+        h.set_launch(*launch, streaming=streaming, blocks=blocks)
+        h.iterate(40)
+        labels = h.labels().cpu().numpy()
+        for l in range(3):
+            m = h.messages(l)
+            assert normwise(m["rho"].cpu().numpy(), r.state.rho[l]) <= 1e-10, (blocks, l)
+            assert normwise(m["alpha"].cpu().numpy(), r.state.alpha[l]) <= 1e-10, (blocks, l)
+            if l > 0:
+                assert normwise(h.offsets(l).cpu().numpy(), r.state.delta[l]) <= 1e-10, (blocks, l)
+        h.close()
+        assert np.array_equal(labels, r.labels), blocks
+
+
 def test_fp32_points_mode_bit_identical(hap_gpu):
     b, _ = synth.workload_plain_f32(n=700)
     X = b.X.astype(np.float32)
